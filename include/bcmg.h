@@ -1,0 +1,260 @@
+/*
+ * bcmg.h -- C ABI of a ghost-point geometric multigrid for the Poisson
+ * equation on level-set domains embedded in a uniform Cartesian grid
+ * (Coco, Mazza & Semplice, "A ghost-point smoothing strategy for geometric
+ * multigrid on curved boundaries", arXiv 2207.14208), built for AMD Instinct
+ * MI355X (gfx950).  Every step of the cycle runs as a HIP kernel on the
+ * device; the host only validates arguments, sizes buffers and launches.
+ *
+ * Problem (Sec. 2, eq. mainProblem2D; Sec. 2.3; Sec. 3):
+ *   box D = [-1,1]^d, d in {1,2,3}, nodes x_i = -1 + i h, h = 2/N, i = 0..N;
+ *   Omega = {phi < 0};  -Laplace(u) = f in Omega;  u = g on the curved
+ *   boundary (ghost-point Dirichlet rows, eq. BCh);  u = g_B on nodes of the
+ *   box faces inside Omega (eliminated Dirichlet nodes).
+ *
+ * Node arrays are dense, (N+1)^d entries, x fastest (index i + n j + n^2 k,
+ * n = N+1).  Node classes (Sec. 2.3 partition of D_h):
+ *   BCMG_OUTSIDE 0  inactive node
+ *   BCMG_INSIDE  1  phi < 0, not on a box face: interior unknown
+ *   BCMG_GHOST   2  phi >= 0 with an INSIDE axis neighbour: ghost unknown
+ *   BCMG_BOXDIR  3  phi < 0 on a box face: fixed value g_B
+ *
+ * Conventions for every call:
+ *   - pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors); *_host are host pointers.  The library never frees caller
+ *     memory and never keeps a caller pointer beyond the call, except u_dev
+ *     in a batch slot (kept until bcmg_batch_remove).
+ *   - calls are ordered on the problem's stream (given at setup).  Calls that
+ *     return host values synchronise that stream.
+ *   - every call returns a bcmg_status; on failure bcmg_last_error() holds a
+ *     thread-local message.  Arguments are validated on the host before any
+ *     launch; a failed setup leaves no handle.
+ *   - the library is not thread-safe per handle: calls on one problem or
+ *     batch must not overlap.
+ */
+#ifndef BCMG_H
+#define BCMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bcmg_status;
+#define BCMG_OK 0
+#define BCMG_ERR_INVALID 1       /* bad argument (size, pointer, option, NaN in phi) */
+#define BCMG_ERR_OOM 2           /* device allocation failed */
+#define BCMG_ERR_DEVICE 3        /* HIP runtime error */
+#define BCMG_ERR_NOT_CONVERGED 4 /* max_cycles reached before rel_tol */
+#define BCMG_ERR_DIVERGED 5      /* residual non-finite or grew 1e3-fold */
+#define BCMG_ERR_STATE 6         /* call not valid in the handle's state */
+
+#define BCMG_OUTSIDE 0
+#define BCMG_INSIDE 1
+#define BCMG_GHOST 2
+#define BCMG_BOXDIR 3
+
+#define BCMG_FP64 0   /* every step in FP64 */
+#define BCMG_MIXED 1  /* FP32 cycle on the correction, FP64 residual, update and coarse solve */
+
+#define BCMG_DTAU_OPT_EXP 0  /* dtau = 2/(e^{-p1 t} + e^{-pd t}), Remark exptheta2D */
+#define BCMG_DTAU_OPT_POLY 1 /* dtau = 2/(min|G0| + max|G0|), Prop. opt / opt3D, eq. coeff */
+#define BCMG_DTAU_CONST 2    /* dtau = dtau_const on every ghost (the constant strategy) */
+
+#define BCMG_RESTRICT_RENORM_FW 0 /* FW weights renormalised over the admissible nodes */
+#define BCMG_RESTRICT_PLAIN_MEAN 1 /* unweighted mean over the admissible nodes */
+
+typedef struct bcmg_problem bcmg_problem;
+typedef struct bcmg_batch bcmg_batch;
+
+typedef struct {
+    int32_t nu1;           /* pre-smoothing steps (default 2) */
+    int32_t nu2;           /* post-smoothing steps (default 1) */
+    int32_t coarsest_N;    /* intervals per axis on the coarsest grid (must be 4: 5^d nodes) */
+    int32_t max_cycles;    /* cycle limit of a solve (default 100, at most 1000) */
+    int32_t precision;     /* BCMG_FP64 or BCMG_MIXED */
+    int32_t dtau_mode;     /* BCMG_DTAU_* */
+    double dtau_const;     /* used by BCMG_DTAU_CONST */
+    int32_t ext_iters;     /* K: Jacobi sweeps of the normal extension (default 4, 1..8) */
+    int32_t restrict_mode; /* BCMG_RESTRICT_* */
+} bcmg_options;
+
+typedef struct {
+    int32_t cycles;        /* V-cycles performed */
+    bcmg_status status;    /* BCMG_OK, _NOT_CONVERGED or _DIVERGED */
+    double r0;             /* ||r^0||_2 over INSIDE and GHOST rows */
+    double r_final;        /* ||r^m||_2 at exit */
+    double rho_mean;       /* mean of ||r^(m+1)||/||r^(m)|| over m = 11..15 (0 if fewer cycles) */
+    double solve_ms;       /* device time of the solve (HIP events on the stream) */
+} bcmg_solve_stats;
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *bcmg_last_error(void);
+
+/* Library version (major*100 + minor). */
+int32_t bcmg_version(void);
+
+/* Fill *opt with the defaults: V(2,1), coarsest N = 4, 100 cycles, FP64,
+ * exponential-form dtau (Remark exptheta2D), K = 4, renormalised FW. */
+bcmg_status bcmg_default_options(bcmg_options *opt);
+
+/*
+ * Build the grid hierarchy for the level set phi sampled at the finest nodes.
+ *   dim: 1, 2 or 3.  N: intervals per axis, a power of two with N >= 8
+ *   and N <= 4096 (1D/2D) or 1024 (3D).
+ *   phi_dev: (N+1)^dim FP64 node values, x fastest; read during the call only.
+ *     Coarse levels take phi by injection (every coarse node is a fine node) and
+ *     are classified on their own (Sec. 2.3: a node may be inactive on one
+ *     level and a ghost on the next).
+ *   stream: hipStream_t for every later call on this problem (NULL = default).
+ * Per level the setup classifies nodes, compacts the ghost list in ascending
+ * node order, computes each ghost's upwind stencil, projection Q = G - eta h n,
+ * theta~ = eta and dtau (eqs. BCh, rel, DtauOptTheta), the extension band and
+ * the coarsest-level inverse.  Returns BCMG_ERR_INVALID for bad sizes/options
+ * or non-finite phi.
+ */
+bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg_options *opt, void *stream,
+                       bcmg_problem **out);
+
+/* Release every device buffer of the problem (stream-ordered). */
+bcmg_status bcmg_destroy(bcmg_problem *prob);
+
+/* Number of grid levels (finest = 0). */
+bcmg_status bcmg_num_levels(const bcmg_problem *prob, int32_t *levels);
+
+/* Sizes of a level: intervals N, INSIDE and GHOST counts, extension band and
+ * row-segment counts.  Any output pointer may be NULL. */
+bcmg_status bcmg_level_info(const bcmg_problem *prob, int32_t level, int32_t *N, int64_t *n_inside,
+                            int64_t *n_ghost, int64_t *n_band, int64_t *n_segments);
+
+/* Copy the class array of a level ((N_l+1)^dim uint8, BCMG_* codes) to cls_dev. */
+bcmg_status bcmg_classes(const bcmg_problem *prob, int32_t level, uint8_t *cls_dev);
+
+/*
+ * Ghost data of a level in ghost-list order (ascending node index); any
+ * pointer may be NULL.
+ *   idx_dev   int32[n_ghost]     node index
+ *   code_dev  int32[n_ghost]     stencil code: bits 0-1,2-3,4-5 widths w_x,w_y,w_z
+ *                                (1..3); bits 6,7,8 set when s_x,s_y,s_z = -1
+ *                                (the stencil extends towards -s_k, upwind)
+ *   eta_dev   double[n_ghost]    theta~ = |G-Q|/h (eq. DtauOptTheta)
+ *   normal_dev double[3*n_ghost] unit normal n (from central differences of phi)
+ *   q_dev     double[3*n_ghost]  projection Q = G - eta h n
+ *   tau_dev   double[3*n_ghost]  local coordinates of Q along each stencil axis
+ *   dtau_dev  double[n_ghost]    fictitious time step of the ghost row
+ *   fallback_dev int32[n_ghost]  1 if the root search fell back to the first-order distance
+ */
+bcmg_status bcmg_ghost_info(const bcmg_problem *prob, int32_t level, int32_t *idx_dev, int32_t *code_dev,
+                            double *eta_dev, double *normal_dev, double *q_dev, double *tau_dev, double *dtau_dev,
+                            int32_t *fallback_dev);
+
+/*
+ * Right-hand side of the finest level: f_dev (nodes; used on INSIDE nodes) and
+ * gq_dev (n_ghost values g(Q) in ghost-list order, the boundary data at the
+ * projections returned by bcmg_ghost_info).  Both copied; NULL f means 0.
+ */
+bcmg_status bcmg_set_data(bcmg_problem *prob, const double *f_dev, const double *gq_dev);
+
+/* u_dev[BOXDIR nodes] = gbox_dev (nodes; NULL means 0).  Other entries untouched. */
+bcmg_status bcmg_fill_boundary(bcmg_problem *prob, const double *gbox_dev, double *u_dev);
+
+/* One V(nu1,nu2) cycle on u_dev (finest level, FP64, in place).  INSIDE and
+ * GHOST entries are the unknowns, BOXDIR entries must hold g_B, other entries
+ * are never read or written.  Sec. 1.1 (TGCS and its gamma = 1 recursion). */
+bcmg_status bcmg_vcycle(bcmg_problem *prob, double *u_dev);
+
+/* ||f - A u||_2 over INSIDE and GHOST rows of the finest level (host result). */
+bcmg_status bcmg_residual_norm(bcmg_problem *prob, const double *u_dev, double *norm_host);
+
+/*
+ * Solve in place from the given u_dev until ||r^m|| <= rel_tol ||r^0||
+ * (residual normalised by the first iteration, Sec. 2.3 comparison with AGMG).
+ * In BCMG_MIXED mode each cycle is an FP64 residual, an FP32 V-cycle on the
+ * correction with an FP64 coarse solve, and an FP64 update (iterative
+ * refinement).  hist_host (max_cycles+1 doubles, may be NULL) receives
+ * ||r^m|| for m = 0..cycles.  Returns the solve status.
+ */
+bcmg_status bcmg_solve(bcmg_problem *prob, double *u_dev, double rel_tol, bcmg_solve_stats *stats_host,
+                       double *hist_host);
+
+/* ---- single steps of the cycle on caller buffers (FP64), level l ---------- */
+
+/* steps x (red-black Gauss-Seidel on INSIDE nodes, then one Jacobi ghost
+ * relaxation u_G += dtau_G (rhs_G - sum w u), eqs. GSLEX_2D in red-black
+ * order, rel, 2Ddiri:P); rhs holds f on INSIDE and the ghost-row data on GHOST. */
+bcmg_status bcmg_level_smooth(bcmg_problem *prob, int32_t level, double *u_dev, const double *rhs_dev,
+                              int32_t steps);
+
+/* r = rhs - A u on INSIDE and GHOST rows (r elsewhere untouched); optional norm. */
+bcmg_status bcmg_level_residual(bcmg_problem *prob, int32_t level, const double *u_dev, const double *rhs_dev,
+                                double *r_dev, double *norm_host);
+
+/* Normal extension of the GHOST values of v into the OUTSIDE nodes within
+ * Chebyshev distance K of a ghost (K upwind Jacobi sweeps from 0, Sec. 2.3
+ * transfer operators); other OUTSIDE entries of v must already be 0. */
+bcmg_status bcmg_level_extend(bcmg_problem *prob, int32_t level, double *v_dev);
+
+/* rhs_coarse (level+1) from the extended residual r_fine (level), eq.
+ * coarseFW and Sec. 2.3: renormalised FW kept separate for interior and ghost
+ * rows.  Written on coarse INSIDE and GHOST nodes only. */
+bcmg_status bcmg_level_restrict(bcmg_problem *prob, int32_t level, const double *rfine_dev, double *rhs_coarse_dev);
+
+/* u_fine += P e_coarse on fine INSIDE and GHOST nodes (multilinear); e_coarse
+ * (level+1) must hold 0 on BOXDIR and OUTSIDE nodes; its OUTSIDE band entries
+ * are overwritten by the extension first (Sec. 2.3). */
+bcmg_status bcmg_level_prolong(bcmg_problem *prob, int32_t level, double *ecoarse_dev, double *ufine_dev);
+
+/* Exact solve on the coarsest level (dense inverse built at setup; BOXDIR
+ * values of the coarsest level are 0). */
+bcmg_status bcmg_coarse_solve(bcmg_problem *prob, double *u_dev, const double *rhs_dev);
+
+/* ---- batches: many independent problems advanced together ---------------- */
+
+/*
+ * A batch advances every active slot by whole V-cycles with one set of
+ * launches per cycle (levels aligned at the coarsest grid), captured once in a
+ * hipGraph and replayed.  All problems of a batch share dim and precision.
+ * Problems stay owned by the caller; u_dev of each slot is kept until removal.
+ */
+bcmg_status bcmg_batch_create(int32_t capacity, void *stream, bcmg_batch **out);
+bcmg_status bcmg_batch_destroy(bcmg_batch *b);
+
+/* Add a problem (after bcmg_set_data) with its solution buffer and tolerance;
+ * computes ||r^0|| and returns the slot. */
+bcmg_status bcmg_batch_add(bcmg_batch *b, bcmg_problem *prob, double *u_dev, double rel_tol, int32_t *slot);
+
+/* Drop a slot (its problem and u_dev are released to the caller). */
+bcmg_status bcmg_batch_remove(bcmg_batch *b, int32_t slot);
+
+/* Advance every active slot by `cycles` V-cycles (converged slots are left
+ * untouched), then copy each slot's state to the host: active_host[capacity]
+ * = 1 while a slot still iterates, 0 when done or free.  Synchronises. */
+bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host);
+
+/* Step until no slot is active or max_steps steps were taken. */
+bcmg_status bcmg_batch_run(bcmg_batch *b, int32_t cycles_per_step, int32_t max_steps);
+
+/* Final state of a slot (valid once inactive). hist_host may be NULL. */
+bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stats_host, double *hist_host);
+
+/* Device bytes a problem of this size would need (for admission control). */
+bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64_t *bytes);
+
+/* Bytes of device memory held by a problem. */
+bcmg_status bcmg_problem_bytes(const bcmg_problem *prob, int64_t *bytes);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+/* When enabled, every launch of the finest-level red-black sweep kernel is
+ * bracketed by HIP events on the problem's stream; bcmg_timing_read returns
+ * the number of such launches and their summed duration in ms. */
+bcmg_status bcmg_timing_enable(int32_t on);
+bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *inside_nodes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCMG_H */

@@ -944,7 +944,7 @@ static void or_level_geometry(or_level *L, const or_options *o) {
  * two levels down to opt->coarsest_N.  Returns NULL on bad arguments.
  */
 or_problem *or_setup(int d, int N, const double *phi, const or_options *opt) {
-    if (d < 1 || d > 3 || N < 4) return NULL;
+    if (d < 1 || d > 3 || N < 4 || opt->coarsest_N < 4) return NULL; /* 3-node interpolants need N >= 4 */
     if (N & (N - 1)) return NULL;
     or_problem *P = (or_problem *)calloc(1, sizeof(or_problem));
     P->d = d;

@@ -1,0 +1,1290 @@
+// Host side of the C ABI: argument checks, allocation of the level
+// hierarchy, work lists, the cycle launch sequence, hipGraph capture and
+// replay, batches and the single-step entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bcmg_internal.h"
+#include "launch.h"
+
+using namespace bcmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+bcmg_status fail(bcmg_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(BCMG_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// finest-level red-black sweep timing (bcmg_timing_*)
+struct Timing {
+    bool on = false;
+    long long launches = 0;
+    double ms = 0.0;
+    long long nodes = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+} g_timing;
+
+}  // namespace
+
+struct LevelH {
+    int N = 0, n = 0;
+    long long nn = 0;
+    double h = 0.0;
+    long long ni = 0, ng = 0, nb = 0;
+    uint8_t *cls = nullptr;
+    double *phi = nullptr;
+    int *gidx = nullptr, *gcode = nullptr, *gfb = nullptr;
+    double *gtau = nullptr, *gdtau = nullptr, *geta = nullptr, *gn = nullptr, *gq = nullptr;
+    int *bidx = nullptr, *bref = nullptr;
+    double *bw = nullptr;
+    void *u = nullptr, *rhs = nullptr, *r = nullptr, *bufA = nullptr, *bufB = nullptr;
+    double *gdelta = nullptr;
+    std::vector<Item> segs;  // desc field 0; patched when copied into a table
+    // coarsest level
+    int nc = 0, singular = 0;
+    double *ainv = nullptr;
+    int *cmap = nullptr;
+};
+
+struct bcmg_problem {
+    int d = 0, N = 0, L = 0;
+    bcmg_options opt{};
+    hipStream_t stream = nullptr;
+    int fp32 = 0;
+    LevelH lev[kMaxLevels];
+    double *rhs64 = nullptr;  // finest FP64 right-hand side (f on INSIDE, g(Q) on GHOST)
+    double *r64 = nullptr;    // finest FP64 residual scratch
+    std::vector<void *> allocs;
+    long long bytes = 0;
+    // single-step entry points
+    Desc *d_step = nullptr;   // [L]
+    SlotState *d_stepst = nullptr;
+    Item *d_stepitems = nullptr;  // per level: segs, gch, bch
+    std::vector<int> off_seg, off_gch, off_bch, n_seg, n_gch, n_bch;
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
+    NormRange *d_range = nullptr;
+    double *d_out = nullptr;
+    Desc *h_stage = nullptr;  // pinned staging for descriptor uploads
+    bcmg_batch *solo = nullptr;
+};
+
+struct Lists {
+    Item *segs = nullptr;
+    int nseg = 0;
+    Item *gch = nullptr;
+    int ngch = 0;
+    Item *bch = nullptr;
+    int nbch = 0;
+    Item *csegs = nullptr;
+    int ncseg = 0;
+    Item *cbch = nullptr;
+    int ncbch = 0;
+};
+
+struct bcmg_batch {
+    int cap = 0;
+    hipStream_t stream = nullptr;       // private non-blocking stream (graph capture needs one)
+    hipStream_t user_stream = nullptr;  // caller's stream, joined at every entry
+    hipEvent_t join = nullptr;
+    long long fine_inside = 0;          // INSIDE nodes on the finest aligned level
+    int d = 0, fp32 = 0, nu1 = 2, nu2 = 1, K = 4, max_hist = 0;
+    std::vector<bcmg_problem *> prob;
+    std::vector<double *> u;
+    std::vector<double> rtol;
+    // device state
+    SlotState *d_state = nullptr;
+    SlotState *h_state = nullptr;  // pinned mirror
+    double *d_rtol2 = nullptr;
+    double *d_hist = nullptr;
+    int hist_stride = 0;
+    NormRange *d_ranges = nullptr;
+    // rebuilt on membership change
+    Desc *d_desc = nullptr;
+    size_t desc_cap = 0;
+    Desc *d_outer = nullptr;
+    float **d_eptr = nullptr;
+    Item *d_items = nullptr;
+    size_t items_cap = 0;
+    int *d_coarse = nullptr;
+    int ncoarse = 0;
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
+    int A = 0;
+    std::vector<Lists> lv;
+    Item *fsegs = nullptr, *fgch = nullptr;
+    int nfseg = 0, nfgch = 0;
+    std::vector<int> sing_slots;  // slots whose coarsest level is singular
+    Item *ssegs = nullptr, *sgch = nullptr;
+    int nsseg = 0, nsgch = 0;
+    bool dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_cycles = 0;
+};
+
+namespace {
+
+bcmg_status dalloc(bcmg_problem *P, void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(BCMG_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    e = hipMemsetAsync(*out, 0, bytes, P->stream);
+    if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+    P->allocs.push_back(*out);
+    P->bytes += (long long)bytes;
+    return BCMG_OK;
+}
+
+template <typename T>
+bcmg_status dalloc_t(bcmg_problem *P, T **out, size_t count) {
+    void *p = nullptr;
+    bcmg_status s = dalloc(P, &p, count * sizeof(T));
+    *out = (T *)p;
+    return s;
+}
+
+void free_problem_memory(bcmg_problem *P) {
+    for (void *p : P->allocs) hipFree(p);
+    P->allocs.clear();
+    if (P->h_stage) hipHostFree(P->h_stage);
+    P->h_stage = nullptr;
+}
+
+Item seg_item(int desc, long long start, int x0, int len, int j, int k) {
+    Item it;
+    it.x = desc;
+    it.y = (int)start;
+    it.z = x0 | (len << 16);
+    it.w = j | (k << 16);
+    return it;
+}
+
+void append_chunks(std::vector<Item> &out, int desc, long long count) {
+    for (long long b = 0; b < count; b += kChunk) {
+        Item it;
+        it.x = desc;
+        it.y = (int)b;
+        it.z = (int)std::min<long long>(kChunk, count - b);
+        it.w = 0;
+        out.push_back(it);
+    }
+}
+
+Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int slot) {
+    const LevelH &V = P->lev[l];
+    Desc D;
+    memset(&D, 0, sizeof D);
+    D.d = P->d;
+    D.n = V.n;
+    D.N = V.N;
+    D.level = l;
+    D.nn = V.nn;
+    D.sy = P->d >= 2 ? V.n : 0;
+    D.sz = P->d >= 3 ? (long long)V.n * V.n : 0;
+    D.h = V.h;
+    D.h2 = V.h * V.h;
+    D.cls = V.cls;
+    D.ng = (int)V.ng;
+    D.nb = (int)V.nb;
+    D.gidx = V.gidx;
+    D.gcode = V.gcode;
+    D.gtau = V.gtau;
+    D.gdtau = V.gdtau;
+    D.bidx = V.bidx;
+    D.bref = V.bref;
+    D.bw = V.bw;
+    D.u = u;
+    D.rhs = rhs;
+    D.r = r;
+    D.gdelta = V.gdelta;
+    D.bufA = V.bufA;
+    D.bufB = V.bufB;
+    D.nc = V.nc;
+    D.singular = V.singular;
+    D.ainv = V.ainv;
+    D.cmap = V.cmap;
+    D.slot = slot;
+    D.restrict_mode = P->opt.restrict_mode;
+    return D;
+}
+
+// ------------------------------------------------------------------ setup
+bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratch_offsets, int *total_dev,
+                        int *h_total) {
+    LevelH &V = P->lev[l];
+    const int d = P->d;
+    hipStream_t s = P->stream;
+    bcmg_status st;
+    launch_classify(d, V.n, V.phi, V.cls, s);
+    // counts of INSIDE and GHOST nodes, ghost list
+    launch_compact(V.cls, V.nn, C_INSIDE, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+    HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    V.ni = *h_total;
+    launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+    HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    V.ng = *h_total;
+    const size_t ng = (size_t)std::max<long long>(V.ng, 1);
+    if ((st = dalloc_t(P, &V.gidx, ng)) || (st = dalloc_t(P, &V.gcode, ng)) || (st = dalloc_t(P, &V.gfb, ng)) ||
+        (st = dalloc_t(P, &V.gtau, 3 * ng)) || (st = dalloc_t(P, &V.gdtau, ng)) || (st = dalloc_t(P, &V.geta, ng)) ||
+        (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gdelta, ng)))
+        return st;
+    launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
+    launch_ghost_geometry(d, V.N, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
+                          V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, s);
+    // extension band (only levels that restrict or receive a prolongation need it)
+    {
+        uint8_t *mark = nullptr;
+        void *tmp = nullptr;
+        HIPCHK(hipMallocAsync(&tmp, (size_t)V.nn, s));
+        mark = (uint8_t *)tmp;
+        HIPCHK(hipMemsetAsync(mark, 0, (size_t)V.nn, s));
+        launch_band_mark(d, V.N, V.cls, V.gidx, (int)V.ng, P->opt.ext_iters, mark, s);
+        launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+        HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        V.nb = *h_total;
+        const size_t nb = (size_t)std::max<long long>(V.nb, 1);
+        const size_t esz = P->fp32 ? 4 : 8;
+        if ((st = dalloc_t(P, &V.bidx, nb)) || (st = dalloc_t(P, &V.bref, 3 * nb)) ||
+            (st = dalloc_t(P, &V.bw, 3 * nb)) || (st = dalloc(P, &V.bufA, nb * esz)) ||
+            (st = dalloc(P, &V.bufB, nb * esz))) {
+            hipFreeAsync(tmp, s);
+            return st;
+        }
+        launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, V.bidx, total_dev, s);
+        launch_band_records(d, V.N, V.h, V.phi, V.cls, V.bidx, (int)V.nb, V.bref, V.bw, s);
+        HIPCHK(hipFreeAsync(tmp, s));
+    }
+    // row segments of INSIDE/GHOST nodes
+    {
+        long long rows = 1;
+        for (int k = 1; k < d; k++) rows *= V.n;
+        int *ext = nullptr;
+        HIPCHK(hipMallocAsync((void **)&ext, sizeof(int) * 2 * rows, s));
+        launch_row_extent(d, V.n, V.cls, ext, ext + rows, s);
+        std::vector<int> h(2 * rows);
+        HIPCHK(hipMemcpyAsync(h.data(), ext, sizeof(int) * 2 * rows, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipFreeAsync(ext, s));
+        V.segs.clear();
+        for (long long r = 0; r < rows; r++) {
+            const int lo = h[r], hi = h[rows + r];
+            if (lo < 0) continue;
+            const int j = d >= 2 ? (int)(r % V.n) : 0;
+            const int k = d >= 3 ? (int)(r / V.n) : 0;
+            for (int x = lo; x <= hi; x += kSegLen) {
+                const int len = std::min(kSegLen, hi - x + 1);
+                V.segs.push_back(seg_item(0, r * V.n + x, x, len, j, k));
+            }
+        }
+    }
+    // level arrays (cycle precision); the finest FP64 level uses caller memory for u
+    const size_t esz = P->fp32 ? 4 : 8;
+    if (l > 0 || P->fp32) {
+        if ((st = dalloc(P, &V.u, V.nn * esz))) return st;
+    }
+    if (l > 0 || P->fp32) {
+        if ((st = dalloc(P, &V.rhs, V.nn * esz))) return st;
+    }
+    if ((st = dalloc(P, &V.r, V.nn * esz))) return st;
+    return BCMG_OK;
+}
+
+bcmg_status setup_coarse(bcmg_problem *P) {
+    LevelH &V = P->lev[P->L - 1];
+    bcmg_status st;
+    const int ncmax = (int)(V.ni + V.ng);
+    if (ncmax > kCoarseMax) return fail(BCMG_ERR_INVALID, "coarsest level has %d unknowns (> %d)", ncmax, kCoarseMax);
+    double *work = nullptr;
+    int *info = nullptr;
+    if ((st = dalloc_t(P, &V.ainv, (size_t)std::max(1, ncmax * ncmax))) ||
+        (st = dalloc_t(P, &V.cmap, (size_t)std::max(1, ncmax))) ||
+        (st = dalloc_t(P, &work, (size_t)std::max(1, 2 * ncmax * ncmax))) || (st = dalloc_t(P, &info, 2)))
+        return st;
+    launch_coarse_setup(P->d, V.N, V.h, V.cls, V.gidx, (int)V.ng, V.gcode, V.gtau, work, V.ainv, V.cmap, info,
+                        P->stream);
+    int h[2];
+    HIPCHK(hipMemcpyAsync(h, info, sizeof h, hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    V.nc = h[0];
+    V.singular = h[1];
+    return BCMG_OK;
+}
+
+bcmg_status setup_step_tables(bcmg_problem *P) {
+    bcmg_status st;
+    std::vector<Item> all;
+    P->off_seg.assign(P->L, 0);
+    P->off_gch.assign(P->L, 0);
+    P->off_bch.assign(P->L, 0);
+    P->n_seg.assign(P->L, 0);
+    P->n_gch.assign(P->L, 0);
+    P->n_bch.assign(P->L, 0);
+    for (int l = 0; l < P->L; l++) {
+        const LevelH &V = P->lev[l];
+        P->off_seg[l] = (int)all.size();
+        for (Item it : V.segs) {
+            it.x = l;
+            all.push_back(it);
+        }
+        P->n_seg[l] = (int)V.segs.size();
+        P->off_gch[l] = (int)all.size();
+        append_chunks(all, l, V.ng);
+        P->n_gch[l] = (int)all.size() - P->off_gch[l];
+        P->off_bch[l] = (int)all.size();
+        append_chunks(all, l, V.nb);
+        P->n_bch[l] = (int)all.size() - P->off_bch[l];
+    }
+    if ((st = dalloc_t(P, &P->d_stepitems, all.size() + 1))) return st;
+    HIPCHK(hipMemcpyAsync(P->d_stepitems, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice, P->stream));
+    if ((st = dalloc_t(P, &P->d_step, P->L)) || (st = dalloc_t(P, &P->d_stepst, 1)) ||
+        (st = dalloc_t(P, &P->d_range, 1)) || (st = dalloc_t(P, &P->d_out, 1)))
+        return st;
+    SlotState one;
+    memset(&one, 0, sizeof one);
+    one.active = 1;
+    one.max_cycles = 1 << 30;
+    HIPCHK(hipMemcpyAsync(P->d_stepst, &one, sizeof one, hipMemcpyHostToDevice, P->stream));
+    const size_t np = (size_t)P->n_seg[0] + (size_t)P->n_gch[0] + 1;
+    if ((st = dalloc_t(P, &P->d_partials, np))) return st;
+    P->partials_cap = np;
+    NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};
+    HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
+    HIPCHK(hipHostMalloc((void **)&P->h_stage, sizeof(Desc) * kMaxLevels));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bool valid_level(const bcmg_problem *P, int l) { return P && l >= 0 && l < P->L; }
+
+// upload step descriptors for levels [l0, l0+cnt) with the given pointers
+bcmg_status upload_step_descs(bcmg_problem *P, int l0, int cnt, void *const *u, void *const *rhs, void *const *r) {
+    for (int i = 0; i < cnt; i++) P->h_stage[i] = make_desc(P, l0 + i, u[i], rhs[i], r[i], 0);
+    HIPCHK(hipMemcpyAsync(P->d_step + l0, P->h_stage, sizeof(Desc) * cnt, hipMemcpyHostToDevice, P->stream));
+    return BCMG_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *bcmg_last_error(void) { return g_err.c_str(); }
+
+int32_t bcmg_version(void) { return 100; }
+
+bcmg_status bcmg_default_options(bcmg_options *o) {
+    if (!o) return fail(BCMG_ERR_INVALID, "null options");
+    o->nu1 = 2;
+    o->nu2 = 1;
+    o->coarsest_N = 4;
+    o->max_cycles = 100;
+    o->precision = BCMG_FP64;
+    o->dtau_mode = BCMG_DTAU_OPT_EXP;
+    o->dtau_const = 1.0;
+    o->ext_iters = 4;
+    o->restrict_mode = BCMG_RESTRICT_RENORM_FW;
+    return BCMG_OK;
+}
+
+static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
+    if (dim < 1 || dim > 3) return fail(BCMG_ERR_INVALID, "dim must be 1, 2 or 3 (got %d)", dim);
+    // the quadratic root interpolant needs 3 nodes per axis on both sides of any node: N >= 4
+    if (o->coarsest_N != 4) return fail(BCMG_ERR_INVALID, "coarsest_N must be 4");
+    if (N < 2 * o->coarsest_N || (N & (N - 1))) return fail(BCMG_ERR_INVALID, "N must be a power of two >= 2*coarsest_N (got %d)", N);
+    const int nmax = dim == 3 ? 1024 : 4096;
+    if (N > nmax) return fail(BCMG_ERR_INVALID, "N=%d exceeds the limit %d for dim %d", N, nmax, dim);
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 16 || o->nu2 > 16)
+        return fail(BCMG_ERR_INVALID, "nu1, nu2 must be in 0..16 with nu1+nu2 >= 1");
+    if (o->max_cycles < 1 || o->max_cycles > 1000) return fail(BCMG_ERR_INVALID, "max_cycles must be in 1..1000");
+    if (o->precision != BCMG_FP64 && o->precision != BCMG_MIXED) return fail(BCMG_ERR_INVALID, "bad precision");
+    if (o->dtau_mode < 0 || o->dtau_mode > 2) return fail(BCMG_ERR_INVALID, "bad dtau_mode");
+    if (o->dtau_mode == BCMG_DTAU_CONST && !(o->dtau_const > 0.0 && std::isfinite(o->dtau_const)))
+        return fail(BCMG_ERR_INVALID, "dtau_const must be positive");
+    if (o->ext_iters < 1 || o->ext_iters > 8) return fail(BCMG_ERR_INVALID, "ext_iters must be in 1..8");
+    if (o->restrict_mode != 0 && o->restrict_mode != 1) return fail(BCMG_ERR_INVALID, "bad restrict_mode");
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64_t *bytes) {
+    if (!bytes || dim < 1 || dim > 3 || N < 4) return fail(BCMG_ERR_INVALID, "bad arguments");
+    double tot = 0.0;
+    const double esz = precision == BCMG_MIXED ? 4.0 : 8.0;
+    for (int NN = N; NN >= 2; NN /= 2) {
+        double nn = std::pow(NN + 1.0, dim);
+        // phi, class, u, rhs, r, band mark scratch; ghosts/band ~ surface terms
+        tot += nn * (8.0 + 1.0 + 3.0 * esz) + 64.0 * std::pow(NN + 1.0, dim - 1) * 8.0;
+        if (NN == N) tot += nn * 16.0;  // FP64 rhs + residual on the finest level
+    }
+    *bytes = (int64_t)(tot * 1.1) + (1 << 20);
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg_options *opt, void *stream,
+                       bcmg_problem **out) {
+    if (!out) return fail(BCMG_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    if (!phi_dev) return fail(BCMG_ERR_INVALID, "null phi");
+    bcmg_options o;
+    if (opt)
+        o = *opt;
+    else
+        bcmg_default_options(&o);
+    bcmg_status st = check_options(dim, N, &o);
+    if (st) return st;
+    bcmg_problem *P = new bcmg_problem();
+    P->d = dim;
+    P->N = N;
+    P->opt = o;
+    P->stream = (hipStream_t)stream;
+    P->fp32 = o.precision == BCMG_MIXED;
+    int L = 0;
+    for (int NN = N; NN >= o.coarsest_N; NN /= 2) L++;
+    if (L > kMaxLevels) {
+        delete P;
+        return fail(BCMG_ERR_INVALID, "too many levels");
+    }
+    P->L = L;
+    auto bail = [&](bcmg_status s) {
+        hipStreamSynchronize(P->stream);
+        free_problem_memory(P);
+        delete P;
+        return s;
+    };
+    for (int l = 0; l < L; l++) {
+        LevelH &V = P->lev[l];
+        V.N = N >> l;
+        V.n = V.N + 1;
+        V.nn = 1;
+        for (int k = 0; k < dim; k++) V.nn *= V.n;
+        V.h = 2.0 / V.N;
+        if ((st = dalloc_t(P, &V.phi, V.nn)) || (st = dalloc_t(P, &V.cls, V.nn))) return bail(st);
+    }
+    int *flag = nullptr;
+    if ((st = dalloc_t(P, &flag, 4))) return bail(st);
+    launch_check_finite(phi_dev, P->lev[0].nn, flag, P->stream);
+    int hflag = 0;
+    if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess)
+        return bail(fail(BCMG_ERR_DEVICE, "phi check failed: %s", hipGetErrorString(hipGetLastError())));
+    if (hflag) return bail(fail(BCMG_ERR_INVALID, "phi has non-finite values"));
+    if (hipMemcpyAsync(P->lev[0].phi, phi_dev, sizeof(double) * P->lev[0].nn, hipMemcpyDeviceToDevice, P->stream) !=
+        hipSuccess)
+        return bail(fail(BCMG_ERR_DEVICE, "copy of phi failed"));
+    for (int l = 1; l < L; l++) launch_inject(dim, P->lev[l - 1].phi, P->lev[l - 1].n, P->lev[l].phi, P->lev[l].n, P->stream);
+    const int nblk = compact_blocks(P->lev[0].nn);
+    int *counts = nullptr, *offsets = nullptr;
+    if ((st = dalloc_t(P, &counts, nblk)) || (st = dalloc_t(P, &offsets, nblk))) return bail(st);
+    int *h_total = nullptr;
+    if (hipHostMalloc((void **)&h_total, sizeof(int)) != hipSuccess) return bail(fail(BCMG_ERR_OOM, "pinned alloc"));
+    for (int l = 0; l < L; l++) {
+        if ((st = setup_level(P, l, counts, offsets, flag, h_total))) {
+            hipHostFree(h_total);
+            return bail(st);
+        }
+    }
+    hipHostFree(h_total);
+    if ((st = setup_coarse(P))) return bail(st);
+    if ((st = dalloc_t(P, &P->rhs64, P->lev[0].nn))) return bail(st);
+    if (P->fp32) {
+        if ((st = dalloc_t(P, &P->r64, P->lev[0].nn))) return bail(st);
+    } else {
+        P->r64 = (double *)P->lev[0].r;
+        P->lev[0].rhs = P->rhs64;  // the FP64 cycle reads the finest rhs directly
+    }
+    if ((st = setup_step_tables(P))) return bail(st);
+    hipError_t e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return bail(fail(BCMG_ERR_DEVICE, "setup: %s", hipGetErrorString(e)));
+    *out = P;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_destroy(bcmg_batch *b);
+
+bcmg_status bcmg_destroy(bcmg_problem *P) {
+    if (!P) return BCMG_OK;
+    if (P->solo) bcmg_batch_destroy(P->solo);
+    hipStreamSynchronize(P->stream);
+    free_problem_memory(P);
+    delete P;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_num_levels(const bcmg_problem *P, int32_t *levels) {
+    if (!P || !levels) return fail(BCMG_ERR_INVALID, "null argument");
+    *levels = P->L;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_info(const bcmg_problem *P, int32_t l, int32_t *N, int64_t *ni, int64_t *ng, int64_t *nb,
+                            int64_t *nseg) {
+    if (!valid_level(P, l)) return fail(BCMG_ERR_INVALID, "bad problem or level");
+    const LevelH &V = P->lev[l];
+    if (N) *N = V.N;
+    if (ni) *ni = V.ni;
+    if (ng) *ng = V.ng;
+    if (nb) *nb = V.nb;
+    if (nseg) *nseg = (int64_t)V.segs.size();
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_problem_bytes(const bcmg_problem *P, int64_t *bytes) {
+    if (!P || !bytes) return fail(BCMG_ERR_INVALID, "null argument");
+    *bytes = P->bytes;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_classes(const bcmg_problem *P, int32_t l, uint8_t *cls_dev) {
+    if (!valid_level(P, l) || !cls_dev) return fail(BCMG_ERR_INVALID, "bad argument");
+    HIPCHK(hipMemcpyAsync(cls_dev, P->lev[l].cls, (size_t)P->lev[l].nn, hipMemcpyDeviceToDevice, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_ghost_info(const bcmg_problem *P, int32_t l, int32_t *idx, int32_t *code, double *eta, double *nrm,
+                            double *q, double *tau, double *dtau, int32_t *fb) {
+    if (!valid_level(P, l)) return fail(BCMG_ERR_INVALID, "bad problem or level");
+    const LevelH &V = P->lev[l];
+    const size_t ng = (size_t)V.ng;
+    if (ng == 0) return BCMG_OK;
+    hipStream_t s = P->stream;
+    if (idx) HIPCHK(hipMemcpyAsync(idx, V.gidx, ng * 4, hipMemcpyDeviceToDevice, s));
+    if (code) HIPCHK(hipMemcpyAsync(code, V.gcode, ng * 4, hipMemcpyDeviceToDevice, s));
+    if (eta) HIPCHK(hipMemcpyAsync(eta, V.geta, ng * 8, hipMemcpyDeviceToDevice, s));
+    if (nrm) HIPCHK(hipMemcpyAsync(nrm, V.gn, ng * 24, hipMemcpyDeviceToDevice, s));
+    if (q) HIPCHK(hipMemcpyAsync(q, V.gq, ng * 24, hipMemcpyDeviceToDevice, s));
+    if (tau) HIPCHK(hipMemcpyAsync(tau, V.gtau, ng * 24, hipMemcpyDeviceToDevice, s));
+    if (dtau) HIPCHK(hipMemcpyAsync(dtau, V.gdtau, ng * 8, hipMemcpyDeviceToDevice, s));
+    if (fb) HIPCHK(hipMemcpyAsync(fb, V.gfb, ng * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_set_data(bcmg_problem *P, const double *f, const double *gq) {
+    if (!P) return fail(BCMG_ERR_INVALID, "null problem");
+    if (!gq && P->lev[0].ng > 0) return fail(BCMG_ERR_INVALID, "null ghost data");
+    launch_set_rhs(P->lev[0].nn, P->lev[0].cls, f, P->rhs64, P->stream);
+    launch_scatter_ghosts(P->lev[0].gidx, (int)P->lev[0].ng, gq, P->rhs64, P->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_fill_boundary(bcmg_problem *P, const double *gbox, double *u) {
+    if (!P || !u) return fail(BCMG_ERR_INVALID, "null argument");
+    launch_fill_boundary(P->lev[0].nn, P->lev[0].cls, gbox, u, P->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+// ---------------------------------------------------------------- steps
+static bcmg_status check_fp64_step(const bcmg_problem *P, int l) {
+    if (!valid_level(P, l)) return fail(BCMG_ERR_INVALID, "bad problem or level");
+    if (P->fp32) return fail(BCMG_ERR_STATE, "single-step calls need an FP64 problem");
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_smooth(bcmg_problem *P, int32_t l, double *u, const double *rhs, int32_t steps) {
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (!u || !rhs || steps < 0) return fail(BCMG_ERR_INVALID, "bad argument");
+    void *pu[1] = {u}, *pr[1] = {(void *)rhs}, *px[1] = {P->lev[l].r};
+    if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
+    const Item *segs = P->d_stepitems + P->off_seg[l], *gch = P->d_stepitems + P->off_gch[l];
+    for (int i = 0; i < steps; i++) {
+        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 0, P->d_stepst, P->stream);
+        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 1, P->d_stepst, P->stream);
+        launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_residual(bcmg_problem *P, int32_t l, const double *u, const double *rhs, double *r,
+                                double *norm_host) {
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (!u || !rhs || !r) return fail(BCMG_ERR_INVALID, "null argument");
+    void *pu[1] = {(void *)u}, *pr[1] = {(void *)rhs}, *px[1] = {r};
+    if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
+    const Item *segs = P->d_stepitems + P->off_seg[l], *gch = P->d_stepitems + P->off_gch[l];
+    const size_t need = (size_t)P->n_seg[l] + P->n_gch[l] + 1;
+    if (need > P->partials_cap) {
+        if ((st = dalloc_t(P, &P->d_partials, need))) return st;
+        P->partials_cap = need;
+    }
+    launch_residual(P->d, 0, 0, norm_host ? 1 : 0, P->d_step, segs, P->n_seg[l], gch, P->n_gch[l], P->d_stepst,
+                    P->d_partials, P->stream);
+    if (norm_host) {
+        NormRange R{0, P->n_seg[l], 0, P->n_gch[l]};
+        HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
+        launch_norm_finish(P->d_range, 1, P->d_partials, P->n_seg[l], P->d_stepst, nullptr, nullptr, 0, 2, P->d_out,
+                           P->stream);
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, P->d_out, sizeof v, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        *norm_host = std::sqrt(v);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_extend(bcmg_problem *P, int32_t l, double *v) {
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (!v) return fail(BCMG_ERR_INVALID, "null argument");
+    void *pu[1] = {v}, *pr[1] = {P->lev[l].rhs}, *px[1] = {P->lev[l].r};
+    if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
+    launch_extend(P->d, 0, P->d_step, P->d_stepitems + P->off_bch[l], P->n_bch[l], 0, P->opt.ext_iters, P->d_stepst,
+                  P->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_restrict(bcmg_problem *P, int32_t l, const double *rf, double *rc) {
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (l + 1 >= P->L || !rf || !rc) return fail(BCMG_ERR_INVALID, "bad argument");
+    void *pu[2] = {P->lev[l].u ? P->lev[l].u : (void *)rf, P->lev[l + 1].u}, *pr[2] = {P->lev[l].rhs, rc},
+         *px[2] = {(void *)rf, P->lev[l + 1].r};
+    if ((st = upload_step_descs(P, l, 2, pu, pr, px))) return st;
+    launch_restrict(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l + 1], P->n_seg[l + 1], P->d_stepst, P->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_level_prolong(bcmg_problem *P, int32_t l, double *ec, double *uf) {
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (l + 1 >= P->L || !ec || !uf) return fail(BCMG_ERR_INVALID, "bad argument");
+    void *pu[2] = {uf, ec}, *pr[2] = {P->lev[l].rhs, P->lev[l + 1].rhs}, *px[2] = {P->lev[l].r, P->lev[l + 1].r};
+    if ((st = upload_step_descs(P, l, 2, pu, pr, px))) return st;
+    launch_extend(P->d, 0, P->d_step, P->d_stepitems + P->off_bch[l + 1], P->n_bch[l + 1], 0, P->opt.ext_iters,
+                  P->d_stepst, P->stream);
+    launch_prolong(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l], P->n_seg[l], P->d_stepst, P->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_coarse_solve(bcmg_problem *P, double *u, const double *rhs) {
+    const int l = P ? P->L - 1 : 0;
+    bcmg_status st = check_fp64_step(P, l);
+    if (st) return st;
+    if (!u || !rhs) return fail(BCMG_ERR_INVALID, "null argument");
+    void *pu[1] = {u}, *pr[1] = {(void *)rhs}, *px[1] = {P->lev[l].r};
+    if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
+    if (P->lev[l].singular) {
+        const Item *segs = P->d_stepitems + P->off_seg[l], *gch = P->d_stepitems + P->off_gch[l];
+        for (int i = 0; i < 50; i++) {
+            launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 0, P->d_stepst, P->stream);
+            launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 1, P->d_stepst, P->stream);
+            launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream);
+        }
+    } else {
+        int lvl = l;
+        int *dl = nullptr;
+        HIPCHK(hipMallocAsync((void **)&dl, sizeof(int), P->stream));
+        HIPCHK(hipMemcpyAsync(dl, &lvl, sizeof(int), hipMemcpyHostToDevice, P->stream));
+        launch_coarse(0, P->d_step, dl, 1, P->d_stepst, P->stream);
+        HIPCHK(hipFreeAsync(dl, P->stream));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(P->stream));
+    return BCMG_OK;
+}
+
+// ---------------------------------------------------------------- batches
+bcmg_status bcmg_batch_create(int32_t capacity, void *stream, bcmg_batch **out) {
+    if (!out || capacity < 1 || capacity > 65536) return fail(BCMG_ERR_INVALID, "bad capacity");
+    *out = nullptr;
+    bcmg_batch *b = new bcmg_batch();
+    b->cap = capacity;
+    b->user_stream = (hipStream_t)stream;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(BCMG_ERR_DEVICE, "stream creation failed");
+    }
+    b->prob.assign(capacity, nullptr);
+    b->u.assign(capacity, nullptr);
+    b->rtol.assign(capacity, 0.0);
+    b->hist_stride = 1001;
+    hipError_t e = hipMalloc((void **)&b->d_state, sizeof(SlotState) * capacity);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_state, 0, sizeof(SlotState) * capacity, b->stream);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_state, sizeof(SlotState) * capacity);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_rtol2, sizeof(double) * capacity);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_hist, sizeof(double) * capacity * b->hist_stride);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_ranges, sizeof(NormRange) * capacity);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_outer, sizeof(Desc) * capacity);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_eptr, sizeof(float *) * capacity);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        bcmg_batch_destroy(b);
+        return fail(BCMG_ERR_OOM, "batch allocation: %s", hipGetErrorString(e));
+    }
+    memset(b->h_state, 0, sizeof(SlotState) * capacity);
+    *out = b;
+    return BCMG_OK;
+}
+
+static void drop_graph(bcmg_batch *b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_cycles = 0;
+}
+
+bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
+    if (!b) return BCMG_OK;
+    hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    hipFree(b->d_state);
+    if (b->h_state) hipHostFree(b->h_state);
+    hipFree(b->d_rtol2);
+    hipFree(b->d_hist);
+    hipFree(b->d_ranges);
+    hipFree(b->d_desc);
+    hipFree(b->d_outer);
+    hipFree(b->d_eptr);
+    hipFree(b->d_items);
+    hipFree(b->d_coarse);
+    hipFree(b->d_partials);
+    if (b->join) hipEventDestroy(b->join);
+    if (b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return BCMG_OK;
+}
+
+// order the batch stream after the caller's stream
+static bcmg_status batch_join(bcmg_batch *b) {
+    HIPCHK(hipEventRecord(b->join, b->user_stream));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->join, 0));
+    return BCMG_OK;
+}
+
+// Rebuild descriptor tables and work lists for the current slots.
+static bcmg_status batch_rebuild(bcmg_batch *b) {
+    HIPCHK(hipStreamSynchronize(b->stream));  // tables may be in use by queued work
+    drop_graph(b);
+    std::vector<Desc> descs;
+    std::vector<Desc> outer(b->cap);
+    std::vector<float *> eptr(b->cap, nullptr);
+    std::vector<int> base(b->cap, -1);
+    int A = 0;
+    for (int s = 0; s < b->cap; s++) {
+        bcmg_problem *P = b->prob[s];
+        if (!P) continue;
+        base[s] = (int)descs.size();
+        for (int l = 0; l < P->L; l++) {
+            void *u = l == 0 ? (P->fp32 ? P->lev[0].u : (void *)b->u[s]) : P->lev[l].u;
+            descs.push_back(make_desc(P, l, u, P->lev[l].rhs, P->lev[l].r, s));
+        }
+        // outer (finest, FP64) descriptor: residual of u64 into rhs32 (mixed) or r64
+        outer[s] = make_desc(P, 0, b->u[s], P->rhs64, P->fp32 ? P->lev[0].rhs : (void *)P->r64, s);
+        eptr[s] = P->fp32 ? (float *)P->lev[0].u : nullptr;
+        A = std::max(A, P->L);
+    }
+    b->A = A;
+    // work lists
+    std::vector<Item> items;
+    struct Off {
+        size_t seg, gch, bch, cseg, cbch;
+        int nseg, ngch, nbch, ncseg, ncbch;
+    };
+    std::vector<Off> off(A);
+    auto add_segs = [&](int desc, const LevelH &V) {
+        for (Item it : V.segs) {
+            it.x = desc;
+            items.push_back(it);
+        }
+    };
+    for (int a = 0; a < A; a++) {
+        Off &o = off[a];
+        o.seg = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a) add_segs(base[s] + b->prob[s]->L - 1 - a, b->prob[s]->lev[b->prob[s]->L - 1 - a]);
+        o.nseg = (int)(items.size() - o.seg);
+        o.gch = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a) {
+                const int l = b->prob[s]->L - 1 - a;
+                append_chunks(items, base[s] + l, b->prob[s]->lev[l].ng);
+            }
+        o.ngch = (int)(items.size() - o.gch);
+        o.bch = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a && a >= 1) {
+                const int l = b->prob[s]->L - 1 - a;
+                append_chunks(items, base[s] + l, b->prob[s]->lev[l].nb);
+            }
+        o.nbch = (int)(items.size() - o.bch);
+        o.cseg = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a && a >= 1) {
+                const int l = b->prob[s]->L - 1 - a;
+                add_segs(base[s] + l + 1, b->prob[s]->lev[l + 1]);
+            }
+        o.ncseg = (int)(items.size() - o.cseg);
+        o.cbch = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a && a >= 1) {
+                const int l = b->prob[s]->L - 1 - a;
+                append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].nb);
+            }
+        o.ncbch = (int)(items.size() - o.cbch);
+    }
+    // finest lists over the outer descriptors, with per-slot norm ranges
+    std::vector<NormRange> ranges(b->cap, NormRange{0, 0, 0, 0});
+    const size_t fseg0 = items.size();
+    for (int s = 0; s < b->cap; s++) {
+        if (!b->prob[s]) continue;
+        ranges[s].seg_beg = (int)(items.size() - fseg0);
+        add_segs(s, b->prob[s]->lev[0]);
+        ranges[s].seg_end = (int)(items.size() - fseg0);
+    }
+    const int nfseg = (int)(items.size() - fseg0);
+    const size_t fgch0 = items.size();
+    for (int s = 0; s < b->cap; s++) {
+        if (!b->prob[s]) continue;
+        ranges[s].gch_beg = (int)(items.size() - fgch0);
+        append_chunks(items, s, b->prob[s]->lev[0].ng);
+        ranges[s].gch_end = (int)(items.size() - fgch0);
+    }
+    const int nfgch = (int)(items.size() - fgch0);
+    std::vector<int> coarse;
+    b->sing_slots.clear();
+    b->fine_inside = 0;
+    for (int s = 0; s < b->cap; s++)
+        if (b->prob[s]) {
+            coarse.push_back(base[s] + b->prob[s]->L - 1);
+            if (b->prob[s]->lev[b->prob[s]->L - 1].singular) b->sing_slots.push_back(s);
+            if (b->prob[s]->L == A) b->fine_inside += b->prob[s]->lev[0].ni;
+        }
+    // coarsest levels of slots whose coarse matrix is singular: smoothed instead
+    const size_t sseg0 = items.size();
+    for (int s : b->sing_slots) add_segs(base[s] + b->prob[s]->L - 1, b->prob[s]->lev[b->prob[s]->L - 1]);
+    const int nsseg = (int)(items.size() - sseg0);
+    const size_t sgch0 = items.size();
+    for (int s : b->sing_slots) {
+        const int l = b->prob[s]->L - 1;
+        append_chunks(items, base[s] + l, b->prob[s]->lev[l].ng);
+    }
+    const int nsgch = (int)(items.size() - sgch0);
+    // upload
+    hipStream_t st = b->stream;
+    if (descs.size() > b->desc_cap) {
+        hipFree(b->d_desc);
+        b->desc_cap = std::max<size_t>(descs.size(), 2 * b->desc_cap);
+        HIPCHK(hipMalloc((void **)&b->d_desc, sizeof(Desc) * b->desc_cap));
+    }
+    if (items.size() + 1 > b->items_cap) {
+        hipFree(b->d_items);
+        b->items_cap = std::max<size_t>(items.size() + 1, 2 * b->items_cap);
+        HIPCHK(hipMalloc((void **)&b->d_items, sizeof(Item) * b->items_cap));
+    }
+    hipFree(b->d_coarse);
+    HIPCHK(hipMalloc((void **)&b->d_coarse, sizeof(int) * (coarse.size() + 1)));
+    const size_t np = (size_t)nfseg + nfgch + 1;
+    if (np > b->partials_cap) {
+        hipFree(b->d_partials);
+        b->partials_cap = std::max(np, 2 * b->partials_cap);
+        HIPCHK(hipMalloc((void **)&b->d_partials, sizeof(double) * b->partials_cap));
+    }
+    hipStream_t cs = b->stream;
+    if (!descs.empty())
+        HIPCHK(hipMemcpyAsync(b->d_desc, descs.data(), sizeof(Desc) * descs.size(), hipMemcpyHostToDevice, cs));
+    if (!items.empty())
+        HIPCHK(hipMemcpyAsync(b->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, cs));
+    if (!coarse.empty())
+        HIPCHK(hipMemcpyAsync(b->d_coarse, coarse.data(), sizeof(int) * coarse.size(), hipMemcpyHostToDevice, cs));
+    HIPCHK(hipMemcpyAsync(b->d_outer, outer.data(), sizeof(Desc) * b->cap, hipMemcpyHostToDevice, cs));
+    HIPCHK(hipMemcpyAsync(b->d_eptr, eptr.data(), sizeof(float *) * b->cap, hipMemcpyHostToDevice, cs));
+    HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), sizeof(NormRange) * b->cap, hipMemcpyHostToDevice, cs));
+    HIPCHK(hipStreamSynchronize(cs));
+    b->lv.assign(A, Lists());
+    for (int a = 0; a < A; a++) {
+        const Off &o = off[a];
+        Lists &L = b->lv[a];
+        L.segs = b->d_items + o.seg;
+        L.nseg = o.nseg;
+        L.gch = b->d_items + o.gch;
+        L.ngch = o.ngch;
+        L.bch = b->d_items + o.bch;
+        L.nbch = o.nbch;
+        L.csegs = b->d_items + o.cseg;
+        L.ncseg = o.ncseg;
+        L.cbch = b->d_items + o.cbch;
+        L.ncbch = o.ncbch;
+    }
+    b->fsegs = b->d_items + fseg0;
+    b->nfseg = nfseg;
+    b->fgch = b->d_items + fgch0;
+    b->nfgch = nfgch;
+    b->ncoarse = (int)coarse.size();
+    b->ssegs = b->d_items + sseg0;
+    b->nsseg = nsseg;
+    b->sgch = b->d_items + sgch0;
+    b->nsgch = nsgch;
+    b->dirty = false;
+    return BCMG_OK;
+}
+
+static void timed_sweep(bcmg_batch *b, int a, int colour) {
+    const Lists &L = b->lv[a];
+    const bool fine = g_timing.on && a == b->A - 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (fine) {
+        g_timing.nodes = b->fine_inside;
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        hipEventRecord(e0, b->stream);
+    }
+    launch_rb_sweep(b->d, b->fp32, b->d_desc, L.segs, L.nseg, colour, b->d_state, b->stream);
+    if (fine) {
+        hipEventRecord(e1, b->stream);
+        g_timing.pending.push_back({e0, e1});
+    }
+}
+
+static void smooth(bcmg_batch *b, int a) {
+    timed_sweep(b, a, 0);
+    timed_sweep(b, a, 1);
+    const Lists &L = b->lv[a];
+    launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream);
+}
+
+// one V(nu1, nu2) cycle over every slot, levels aligned at the coarsest grid
+static void launch_vcycle(bcmg_batch *b) {
+    const int d = b->d, f = b->fp32;
+    hipStream_t s = b->stream;
+    for (int a = b->A - 1; a >= 1; a--) {
+        const Lists &L = b->lv[a];
+        if (L.nseg == 0 && L.ngch == 0) continue;
+        for (int i = 0; i < b->nu1; i++) smooth(b, a);
+        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s);
+        launch_extend(d, f, b->d_desc, L.bch, L.nbch, 1, b->K, b->d_state, s);
+        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, b->d_state, s);
+    }
+    launch_coarse(f, b->d_desc, b->d_coarse, b->ncoarse, b->d_state, s);
+    for (int i = 0; i < 50 && !b->sing_slots.empty(); i++) {
+        // singular coarsest matrices: 50 smoothing steps instead of the exact solve
+        launch_rb_sweep(d, f, b->d_desc, b->ssegs, b->nsseg, 0, b->d_state, s);
+        launch_rb_sweep(d, f, b->d_desc, b->ssegs, b->nsseg, 1, b->d_state, s);
+        launch_ghost_relax(d, f, b->d_desc, b->sgch, b->nsgch, b->d_state, s);
+    }
+    for (int a = 1; a < b->A; a++) {
+        const Lists &L = b->lv[a];
+        if (L.nseg == 0 && L.ngch == 0) continue;
+        launch_extend(d, f, b->d_desc, L.cbch, L.ncbch, 0, b->K, b->d_state, s);
+        launch_prolong(d, f, b->d_desc, L.segs, L.nseg, b->d_state, s);
+        for (int i = 0; i < b->nu2; i++) smooth(b, a);
+    }
+}
+
+// finest FP64 residual (into r64, or into the FP32 right-hand side of the
+// correction cycle) plus per-slot norm and convergence bookkeeping
+static void launch_outer_residual(bcmg_batch *b, int mode) {
+    launch_residual(b->d, 0, b->fp32, 1, b->d_outer, b->fsegs, b->nfseg, b->fgch, b->nfgch, b->d_state, b->d_partials,
+                    b->stream);
+    launch_norm_finish(b->d_ranges, b->cap, b->d_partials, b->nfseg, b->d_state, b->d_rtol2, b->d_hist,
+                       b->hist_stride, mode, nullptr, b->stream);
+}
+
+static void launch_cycle(bcmg_batch *b) {
+    launch_vcycle(b);
+    if (b->fp32) launch_ir_update(b->d_outer, b->fsegs, b->nfseg, b->d_state, b->d_eptr, b->stream);
+    launch_outer_residual(b, 1);
+}
+
+static bcmg_status batch_init_slot(bcmg_batch *b, int slot, double rtol) {
+    bcmg_problem *P = b->prob[slot];
+    SlotState s0;
+    memset(&s0, 0, sizeof s0);
+    s0.active = 2;  // pending: norm_finish mode 0 initialises it
+    s0.max_cycles = P->opt.max_cycles;
+    double r2 = rtol * rtol;
+    HIPCHK(hipMemcpyAsync(b->d_state + slot, &s0, sizeof s0, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_rtol2 + slot, &r2, sizeof r2, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    launch_outer_residual(b, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_add(bcmg_batch *b, bcmg_problem *P, double *u, double rtol, int32_t *slot) {
+    if (!b || !P || !u) return fail(BCMG_ERR_INVALID, "null argument");
+    if (!(rtol >= 0.0)) return fail(BCMG_ERR_INVALID, "bad tolerance");
+    int n_used = 0;
+    for (int s = 0; s < b->cap; s++) n_used += b->prob[s] != nullptr;
+    if (n_used > 0) {
+        if (P->d != b->d || P->fp32 != b->fp32 || P->opt.nu1 != b->nu1 || P->opt.nu2 != b->nu2 ||
+            P->opt.ext_iters != b->K)
+            return fail(BCMG_ERR_INVALID, "problem does not match the batch (dim, precision, nu1, nu2, ext_iters)");
+    } else {
+        b->d = P->d;
+        b->fp32 = P->fp32;
+        b->nu1 = P->opt.nu1;
+        b->nu2 = P->opt.nu2;
+        b->K = P->opt.ext_iters;
+    }
+    int s = -1;
+    for (int i = 0; i < b->cap; i++)
+        if (!b->prob[i]) {
+            s = i;
+            break;
+        }
+    if (s < 0) return fail(BCMG_ERR_STATE, "batch full");
+    if (bcmg_status jst = batch_join(b)) return jst;
+    // FP32 correction must start at 0
+    if (P->fp32) HIPCHK(hipMemsetAsync(P->lev[0].u, 0, P->lev[0].nn * 4, b->stream));
+    b->prob[s] = P;
+    b->u[s] = u;
+    b->rtol[s] = rtol;
+    b->dirty = true;
+    bcmg_status st = batch_rebuild(b);
+    if (st) {
+        b->prob[s] = nullptr;
+        b->u[s] = nullptr;
+        return st;
+    }
+    if ((st = batch_init_slot(b, s, rtol))) return st;
+    if (slot) *slot = s;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_remove(bcmg_batch *b, int32_t slot) {
+    if (!b || slot < 0 || slot >= b->cap || !b->prob[slot]) return fail(BCMG_ERR_INVALID, "bad slot");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->prob[slot] = nullptr;
+    b->u[slot] = nullptr;
+    SlotState z;
+    memset(&z, 0, sizeof z);
+    HIPCHK(hipMemcpyAsync(b->d_state + slot, &z, sizeof z, hipMemcpyHostToDevice, b->stream));
+    b->dirty = true;
+    return BCMG_OK;
+}
+
+static bcmg_status batch_launch_cycles(bcmg_batch *b, int cycles) {
+    if (b->dirty) {
+        bcmg_status st = batch_rebuild(b);
+        if (st) return st;
+    }
+    if (g_timing.on) {
+        for (int c = 0; c < cycles; c++) launch_cycle(b);
+        HIPCHK(hipGetLastError());
+        return BCMG_OK;
+    }
+    if (!b->exec || b->graph_cycles != cycles) {
+        drop_graph(b);
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < cycles; c++) launch_cycle(b);
+        hipError_t e = hipStreamEndCapture(b->stream, &b->graph);
+        if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_cycles = cycles;
+    }
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host) {
+    if (!b || cycles < 1) return fail(BCMG_ERR_INVALID, "bad argument");
+    bcmg_status st = batch_join(b);
+    if (st) return st;
+    st = batch_launch_cycles(b, cycles);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState) * b->cap, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (active_host)
+        for (int s = 0; s < b->cap; s++) active_host[s] = b->prob[s] && b->h_state[s].active ? 1 : 0;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_run(bcmg_batch *b, int32_t cycles_per_step, int32_t max_steps) {
+    if (!b || cycles_per_step < 1) return fail(BCMG_ERR_INVALID, "bad argument");
+    for (int i = 0; i < max_steps; i++) {
+        bcmg_status st = bcmg_batch_step(b, cycles_per_step, nullptr);
+        if (st) return st;
+        bool any = false;
+        for (int s = 0; s < b->cap; s++) any |= b->prob[s] && b->h_state[s].active;
+        if (!any) return BCMG_OK;
+    }
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stats, double *hist) {
+    if (!b || slot < 0 || slot >= b->cap) return fail(BCMG_ERR_INVALID, "bad slot");
+    HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState) * b->cap, hipMemcpyDeviceToHost, b->stream));
+    std::vector<double> h(b->hist_stride);
+    HIPCHK(hipMemcpyAsync(h.data(), b->d_hist + (size_t)slot * b->hist_stride, sizeof(double) * b->hist_stride,
+                          hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const SlotState &S = b->h_state[slot];
+    const int c = std::min(S.cycles, b->hist_stride - 1);
+    if (hist) std::copy(h.begin(), h.begin() + c + 1, hist);
+    if (stats) {
+        stats->cycles = S.cycles;
+        stats->status = S.active ? BCMG_ERR_STATE : S.status;
+        stats->r0 = std::sqrt(S.r0sq);
+        stats->r_final = std::sqrt(S.lastsq);
+        double rho = 0.0;
+        if (c >= 16) {
+            for (int m = 11; m <= 15; m++) rho += h[m + 1] / h[m];
+            rho /= 5.0;
+        }
+        stats->rho_mean = rho;
+        stats->solve_ms = 0.0;
+    }
+    return BCMG_OK;
+}
+
+// ------------------------------------------------------------ single solve
+static bcmg_status solo_attach(bcmg_problem *P, double *u, double rtol) {
+    bcmg_status st;
+    if (!P->solo) {
+        if ((st = bcmg_batch_create(1, P->stream, &P->solo))) return st;
+    }
+    bcmg_batch *b = P->solo;
+    if ((st = batch_join(b))) return st;
+    if (b->prob[0] == P && b->u[0] == u) {
+        b->rtol[0] = rtol;
+        if (P->fp32) HIPCHK(hipMemsetAsync(P->lev[0].u, 0, P->lev[0].nn * 4, b->stream));
+        return batch_init_slot(b, 0, rtol);
+    }
+    if (b->prob[0]) bcmg_batch_remove(b, 0);
+    int32_t slot = 0;
+    return bcmg_batch_add(b, P, u, rtol, &slot);
+}
+
+bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats *stats, double *hist) {
+    if (!P || !u) return fail(BCMG_ERR_INVALID, "null argument");
+    if (!(rtol >= 0.0)) return fail(BCMG_ERR_INVALID, "bad tolerance");
+    bcmg_status st = solo_attach(P, u, rtol);
+    if (st) return st;
+    bcmg_batch *b = P->solo;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, b->stream));
+    b->h_state[0].active = 1;
+    HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    while (b->h_state[0].active) {
+        if ((st = bcmg_batch_step(b, 1, nullptr))) return st;
+    }
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    bcmg_solve_stats s;
+    if ((st = bcmg_batch_stats(b, 0, &s, hist))) return st;
+    s.solve_ms = ms;
+    if (stats) *stats = s;
+    return s.status;
+}
+
+bcmg_status bcmg_vcycle(bcmg_problem *P, double *u) {
+    if (!P || !u) return fail(BCMG_ERR_INVALID, "null argument");
+    bcmg_status st = solo_attach(P, u, 0.0);
+    if (st) return st;
+    bcmg_batch *b = P->solo;
+    SlotState s1;
+    memset(&s1, 0, sizeof s1);
+    s1.active = 1;
+    s1.max_cycles = 1 << 30;
+    HIPCHK(hipMemcpyAsync(b->d_state, &s1, sizeof s1, hipMemcpyHostToDevice, b->stream));
+    launch_vcycle(b);
+    if (b->fp32) launch_ir_update(b->d_outer, b->fsegs, b->nfseg, b->d_state, b->d_eptr, b->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_residual_norm(bcmg_problem *P, const double *u, double *norm_host) {
+    if (!P || !u || !norm_host) return fail(BCMG_ERR_INVALID, "null argument");
+    void *pu[1] = {(void *)u}, *pr[1] = {P->rhs64}, *px[1] = {P->r64};
+    bcmg_status st;
+    for (int i = 0; i < 1; i++) P->h_stage[i] = make_desc(P, 0, pu[i], pr[i], px[i], 0);
+    HIPCHK(hipMemcpyAsync(P->d_step, P->h_stage, sizeof(Desc), hipMemcpyHostToDevice, P->stream));
+    launch_residual(P->d, 0, 0, 1, P->d_step, P->d_stepitems + P->off_seg[0], P->n_seg[0],
+                    P->d_stepitems + P->off_gch[0], P->n_gch[0], P->d_stepst, P->d_partials, P->stream);
+    NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};
+    HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
+    launch_norm_finish(P->d_range, 1, P->d_partials, P->n_seg[0], P->d_stepst, nullptr, nullptr, 0, 2, P->d_out,
+                       P->stream);
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, P->d_out, sizeof v, hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    (void)st;
+    *norm_host = std::sqrt(v);
+    return BCMG_OK;
+}
+
+// ------------------------------------------------------------ timing
+bcmg_status bcmg_timing_enable(int32_t on) {
+    for (auto &pr : g_timing.pending) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    g_timing.pending.clear();
+    g_timing.on = on != 0;
+    g_timing.launches = 0;
+    g_timing.ms = 0.0;
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *nodes) {
+    for (auto &pr : g_timing.pending) {
+        HIPCHK(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        g_timing.ms += ms;
+        g_timing.launches++;
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    g_timing.pending.clear();
+    if (launches) *launches = g_timing.launches;
+    if (total_ms) *total_ms = g_timing.ms;
+    if (nodes) *nodes = g_timing.nodes;
+    return BCMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libbcmg.
+// Device data layout:
+//   * every level keeps dense node arrays (x fastest): class (uint8), u, rhs, r;
+//   * the work of a launch is a list of items: row segments of <= 64 nodes
+//     (one wavefront each) or chunks of <= 256 ghost / band entries (one
+//     workgroup each); each item names a level descriptor, so one launch can
+//     serve many problems and levels at once (batches);
+//   * descriptors of one problem are contiguous, finest first, so the coarse
+//     level of descriptor i is i+1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bcmg.h"
+
+namespace bcmg {
+
+enum : uint8_t { C_OUTSIDE = 0, C_INSIDE = 1, C_GHOST = 2, C_BOXDIR = 3 };
+
+constexpr int kMaxLevels = 16;
+constexpr int kSegLen = 64;     // nodes per row segment = one wavefront
+constexpr int kChunk = 256;     // ghost / band entries per chunk = one workgroup
+constexpr int kBlock = 256;     // threads per workgroup
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRefZero = INT32_MIN;       // band reference to a node whose value is 0
+constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
+constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
+
+// Work item over a row segment: desc, first node, x0 | len << 16, j | k << 16.
+// Ghost / band chunk: desc, first entry, count, unused.
+using Item = int4;
+
+struct alignas(16) Desc {
+    int d, n, N, level;
+    long long nn;
+    long long sy, sz;         // strides of y and z (0 beyond d)
+    double h, h2;
+    const uint8_t *cls;
+    int ng, nb;
+    const int *gidx;          // ghost node indices, ascending
+    const int *gcode;         // widths / signs (see bcmg_ghost_info)
+    const double *gtau;       // [3*ng]
+    const double *gdtau;      // [ng]
+    const int *bidx;          // band node indices, ascending
+    const int *bref;          // [3*nb] upwind references
+    const double *bw;         // [3*nb] normalised weights
+    void *u, *rhs, *r;        // level arrays, element type = cycle precision
+    double *gdelta;           // [ng] ghost increments
+    void *bufA, *bufB;        // [nb] extension ping-pong
+    // coarsest level: dense inverse over INSIDE then GHOST unknowns
+    int nc, singular;
+    const double *ainv;       // [nc*nc]
+    const int *cmap;          // [nc] node index of each unknown
+    int slot;                 // problem slot (state / flags index)
+    int restrict_mode;
+};
+
+// Per-slot solve state kept on the device.
+struct alignas(16) SlotState {
+    int active;     // 1 while the slot iterates
+    int cycles;     // cycles done
+    int status;     // bcmg_status of the solve
+    int max_cycles;
+    double r0sq;    // ||r^0||^2
+    double tolsq;   // (rel_tol * ||r^0||)^2
+    double refsq;   // max(||r^0||^2, ||r^1||^2): divergence reference
+    double lastsq;  // latest ||r||^2
+};
+
+// Per-slot ranges of the partial sums written by a finest-level residual.
+struct alignas(16) NormRange {
+    int seg_beg, seg_end;     // wavefront partials
+    int gch_beg, gch_end;     // ghost-chunk partials (offset by the segment count)
+};
+
+inline __host__ __device__ int code_w(int code, int k) { return (code >> (2 * k)) & 3; }
+inline __host__ __device__ int code_s(int code, int k) { return ((code >> (6 + k)) & 1) ? -1 : 1; }
+
+}  // namespace bcmg

@@ -1,0 +1,53 @@
+// Host-side launchers of the device kernels (defined in cycle.hip / setup.hip).
+#pragma once
+
+#include "bcmg_internal.h"
+
+namespace bcmg {
+
+// ---- cycle kernels (cycle.hip); fp32 selects the element type of u/rhs/r ----
+void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
+                     const SlotState *st, hipStream_t s);
+void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
+                        hipStream_t s);
+// tu32/tr32: element types of (u, rhs) and r; norm: write partial sums of r^2
+void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
+                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s);
+void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
+                        const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s);
+// which: 0 extends u, 1 extends r
+void launch_extend(int d, int fp32, const Desc *descs, const Item *bch, int nbch, int which, int K,
+                   const SlotState *st, hipStream_t s);
+void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const SlotState *st,
+                     hipStream_t s);
+void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
+                    hipStream_t s);
+void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s);
+void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
+                      hipStream_t s);
+
+// ---- setup kernels (setup.hip) ----
+void launch_check_finite(const double *a, long long n, int *flag, hipStream_t s);
+void launch_inject(int d, const double *phi_f, int nf, double *phi_c, int nc, hipStream_t s);
+void launch_classify(int d, int n, const double *phi, uint8_t *cls, hipStream_t s);
+// ordered compaction of the node indices p < nn with pred(p):
+//   kind 0: cls[p] == value;  kind 1: mark[p] != 0 (mark passed as cls)
+// counts/offsets: scratch of compact_blocks(nn) ints each; total written to *total_dev
+int compact_blocks(long long nn);
+void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
+                    int *total_dev, hipStream_t s);
+void launch_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx, int ng,
+                           int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau, double *geta,
+                           double *gn, double *gq, int *gfb, hipStream_t s);
+void launch_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng, int K, uint8_t *mark,
+                      hipStream_t s);
+void launch_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,
+                         int *bref, double *bw, hipStream_t s);
+void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s);
+void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
+                         const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s);
+void launch_set_rhs(long long nn, const uint8_t *cls, const double *f, double *rhs, hipStream_t s);
+void launch_scatter_ghosts(const int *gidx, int ng, const double *gq, double *rhs, hipStream_t s);
+void launch_fill_boundary(long long nn, const uint8_t *cls, const double *gbox, double *u, hipStream_t s);
+
+}  // namespace bcmg

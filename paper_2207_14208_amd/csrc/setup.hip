@@ -1,0 +1,647 @@
+// Setup kernels: level-set injection, node classification, ordered
+// compaction (ghost list, extension band), ghost geometry (normal, upwind
+// stencil widths, projection Q, theta~, dtau), band references, row extents
+// and the coarsest-level inverse.
+//
+// This file is compiled with -ffp-contract=off: the geometry is evaluated
+// with exactly the rounded operations written here (no fused multiply-add),
+// so classes, ghost lists and stencil codes depend only on exact comparisons
+// of the given FP64 node values of phi.
+#include <math.h>
+
+#include "bcmg_internal.h"
+#include "launch.h"
+
+namespace bcmg {
+
+__device__ __forceinline__ void coords(long long p, int n, int d, int I[3]) {
+    I[0] = I[1] = I[2] = 0;
+    for (int k = 0; k < d; k++) {
+        I[k] = (int)(p % n);
+        p /= n;
+    }
+}
+
+__device__ __forceinline__ long long index_of(const int I[3], int n, int d) {
+    long long p = 0;
+    for (int k = d - 1; k >= 0; k--) p = p * n + I[k];
+    return p;
+}
+
+__device__ __forceinline__ bool in_box(const int I[3], int N, int d) {
+    for (int k = 0; k < d; k++)
+        if (I[k] < 0 || I[k] > N) return false;
+    return true;
+}
+
+__global__ void k_check_finite(const double *a, long long n, int *flag) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(a[i])) *flag = 1;
+}
+
+void launch_check_finite(const double *a, long long n, int *flag, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a, n, flag);
+}
+
+// phi on a coarse level is the fine value at the same point (every coarse
+// node is the fine node 2J).
+__global__ void k_inject(int d, const double *phi_f, int nf, double *phi_c, int nc, long long nnc) {
+    long long pc = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pc >= nnc) return;
+    int J[3];
+    coords(pc, nc, d, J);
+    int X[3] = {2 * J[0], 2 * J[1], 2 * J[2]};
+    phi_c[pc] = phi_f[index_of(X, nf, d)];
+}
+
+void launch_inject(int d, const double *phi_f, int nf, double *phi_c, int nc, hipStream_t s) {
+    long long nnc = 1;
+    for (int k = 0; k < d; k++) nnc *= nc;
+    hipLaunchKernelGGL(k_inject, dim3((unsigned)((nnc + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, phi_f, nf, phi_c,
+                       nc, nnc);
+}
+
+// Partition of the nodes (Sec. 2.3): INSIDE / BOXDIR by the sign of phi and
+// the box faces, then GHOST = not inside with an INSIDE axis neighbour.
+__global__ void k_classify_a(int d, int n, const double *phi, uint8_t *cls, long long nn) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nn) return;
+    int I[3];
+    coords(p, n, d, I);
+    bool face = false;
+    for (int k = 0; k < d; k++) face |= (I[k] == 0 || I[k] == n - 1);
+    cls[p] = phi[p] < 0.0 ? (face ? C_BOXDIR : C_INSIDE) : C_OUTSIDE;
+}
+
+__global__ void k_classify_b(int d, int n, uint8_t *cls, long long nn) {
+    long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nn) return;
+    if (cls[p] != C_OUTSIDE) return;  // only OUTSIDE nodes change, to GHOST; INSIDE never changes
+    int I[3];
+    coords(p, n, d, I);
+    long long str = 1;
+    bool ghost = false;
+    for (int k = 0; k < d; k++) {
+        if (I[k] > 0 && cls[p - str] == C_INSIDE) ghost = true;
+        if (I[k] < n - 1 && cls[p + str] == C_INSIDE) ghost = true;
+        str *= n;
+    }
+    if (ghost) cls[p] = C_GHOST;
+}
+
+void launch_classify(int d, int n, const double *phi, uint8_t *cls, hipStream_t s) {
+    long long nn = 1;
+    for (int k = 0; k < d; k++) nn *= n;
+    dim3 g((unsigned)((nn + kBlock - 1) / kBlock)), b(kBlock);
+    hipLaunchKernelGGL(k_classify_a, g, b, 0, s, d, n, phi, cls, nn);
+    hipLaunchKernelGGL(k_classify_b, g, b, 0, s, d, n, cls, nn);
+}
+
+// ---------------------------------------------------------------- compaction
+constexpr int kPer = 16;
+constexpr int kTile = kBlock * kPer;
+
+int compact_blocks(long long nn) { return (int)((nn + kTile - 1) / kTile); }
+
+__device__ int block_exclusive_scan(int v, int *total) {
+    __shared__ int buf[kBlock];
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        int add = t >= o ? buf[t - o] : 0;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    const int incl = buf[t];
+    if (total) *total = buf[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_compact_count(const uint8_t *cls, long long nn, uint8_t value, int *counts) {
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kPer;
+    int c = 0;
+    for (int i = 0; i < kPer; i++) {
+        const long long p = base + i;
+        if (p < nn && cls[p] == value) c++;
+    }
+    int tot;
+    block_exclusive_scan(c, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_counts(const int *counts, int n, int *offsets, int *total_dev) {
+    const int per = (n + kBlock - 1) / kBlock;
+    const int beg = threadIdx.x * per;
+    int s = 0;
+    for (int i = beg; i < beg + per && i < n; i++) s += counts[i];
+    int tot;
+    int off = block_exclusive_scan(s, &tot);
+    for (int i = beg; i < beg + per && i < n; i++) {
+        offsets[i] = off;
+        off += counts[i];
+    }
+    if (threadIdx.x == 0) *total_dev = tot;
+}
+
+__global__ void k_compact_scatter(const uint8_t *cls, long long nn, uint8_t value, const int *offsets, int *out) {
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kPer;
+    int c = 0;
+    for (int i = 0; i < kPer; i++) {
+        const long long p = base + i;
+        if (p < nn && cls[p] == value) c++;
+    }
+    int off = offsets[blockIdx.x] + block_exclusive_scan(c, nullptr);
+    for (int i = 0; i < kPer; i++) {
+        const long long p = base + i;
+        if (p < nn && cls[p] == value) out[off++] = (int)p;
+    }
+}
+
+void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
+                    int *total_dev, hipStream_t s) {
+    const int nb = compact_blocks(nn);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, counts);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, counts, nb, offsets, total_dev);
+    if (out) hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, offsets, out);
+}
+
+// ---------------------------------------------------------- ghost geometry
+__device__ void grad_at(const double *phi, int n, int d, double h, const int I[3], long long p, double g[3]) {
+    g[0] = g[1] = g[2] = 0.0;
+    long long str = 1;
+    for (int k = 0; k < d; k++) {
+        if (I[k] > 0 && I[k] < n - 1)
+            g[k] = (phi[p + str] - phi[p - str]) / (2.0 * h);
+        else if (I[k] == 0)
+            g[k] = (phi[p + str] - phi[p]) / h;
+        else
+            g[k] = (phi[p] - phi[p - str]) / h;
+        str *= n;
+    }
+}
+
+__device__ __forceinline__ double lag(int w, int m, double t) {
+    if (w == 1) return 1.0;
+    if (w == 2) return m == 0 ? 1.0 - t : t;
+    if (m == 0) return (1.0 - t) * (2.0 - t) / 2.0;
+    if (m == 1) return t * (2.0 - t);
+    return t * (t - 1.0) / 2.0;
+}
+
+// tensor-product quadratic interpolant of phi on {I - m o s : m_k < 3}
+__device__ double phi_tilde(const double *phi, int n, int d, const int I[3], const int s[3], const double t[3]) {
+    double val = 0.0;
+    const int mmax0 = 3, mmax1 = d >= 2 ? 3 : 1, mmax2 = d >= 3 ? 3 : 1;
+    for (int m2 = 0; m2 < mmax2; m2++)
+        for (int m1 = 0; m1 < mmax1; m1++)
+            for (int m0 = 0; m0 < mmax0; m0++) {
+                const int m[3] = {m0, m1, m2};
+                int J[3];
+                double wgt = 1.0;
+                for (int k = 0; k < 3; k++) {
+                    J[k] = I[k] - m[k] * s[k];
+                    if (k < d) wgt *= lag(3, m[k], t[k]);
+                }
+                val += wgt * phi[index_of(J, n, d)];
+            }
+    return val;
+}
+
+__device__ bool block_valid(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3]) {
+    for (int m2 = 0; m2 < w[2]; m2++)
+        for (int m1 = 0; m1 < w[1]; m1++)
+            for (int m0 = 0; m0 < w[0]; m0++) {
+                const int J[3] = {I[0] - m0 * s[0], I[1] - m1 * s[1], I[2] - m2 * s[2]};
+                if (!in_box(J, n - 1, d)) return false;
+                const uint8_t c = cls[index_of(J, n, d)];
+                if (c != C_INSIDE && c != C_GHOST) return false;
+            }
+    return true;
+}
+
+__device__ double dtau_of(int d, double theta, int mode, double cnst) {
+    if (mode == BCMG_DTAU_CONST) return cnst;
+    double t = theta < 1.0 ? theta : 1.0;
+    if (t < 0.0) t = 0.0;
+    if (d == 1) return 1.0;
+    double gmin = INFINITY, gmax = -INFINITY;
+    for (int v = 0; v < d; v++) {
+        const double p = v < d - 1 ? acosh(2.0 + v) : acosh(2.0 * d - 1.0);
+        double g;
+        if (mode == BCMG_DTAU_OPT_EXP) {
+            g = exp(-p * t);
+        } else {
+            const double c0 = (1.0 - t) * (2.0 - t) / 2.0, c1 = t * (2.0 - t), c2 = t * (t - 1.0) / 2.0;
+            g = fabs(c2 * exp(-2.0 * p) + c1 * exp(-p) + c0);
+        }
+        gmin = fmin(gmin, g);
+        gmax = fmax(gmax, g);
+    }
+    return 2.0 / (gmin + gmax);
+}
+
+// One ghost G: discrete normal, upwind signs, axis dominance, first valid
+// stencil widths, root eta of phi~(G - eta h n) = 0 by bracketing and 60
+// bisections, Q, tau and dtau(theta~ = eta).  Sec. 2.3 eqs. BCh, rel,
+// DtauOptTheta, Remark exptheta2D.
+__global__ void k_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx,
+                                 int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
+                                 double *geta, double *gn, double *gq, int *gfb) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= ng) return;
+    const int n = N + 1;
+    const long long p = gidx[gi];
+    int I[3];
+    coords(p, n, d, I);
+    double g[3];
+    grad_at(phi, n, d, h, I, p, g);
+    double gnorm = 0.0;
+    for (int k = 0; k < d; k++) gnorm += g[k] * g[k];
+    gnorm = sqrt(gnorm);
+    double nv[3] = {0.0, 0.0, 0.0}, key[3] = {0.0, 0.0, 0.0};
+    if (gnorm > 0.0) {
+        for (int k = 0; k < d; k++) {
+            nv[k] = g[k] / gnorm;
+            key[k] = fabs(g[k]);
+        }
+    } else {
+        bool found = false;
+        long long str = 1;
+        for (int k = 0; k < d && !found; k++) {
+            if (I[k] > 0 && cls[p - str] == C_INSIDE) {
+                nv[k] = 1.0;
+                found = true;
+            } else if (I[k] < N && cls[p + str] == C_INSIDE) {
+                nv[k] = -1.0;
+                found = true;
+            }
+            str *= n;
+        }
+        for (int k = 0; k < d; k++) key[k] = fabs(nv[k]);
+    }
+    int s[3] = {1, 1, 1};
+    for (int k = 0; k < d; k++) s[k] = (gnorm > 0.0 ? g[k] : nv[k]) >= 0.0 ? 1 : -1;
+    int ord[3] = {0, 1, 2};
+    for (int a = 1; a < d; a++)
+        for (int b = a; b > 0 && key[ord[b - 1]] < key[ord[b]]; b--) {
+            const int tmp = ord[b - 1];
+            ord[b - 1] = ord[b];
+            ord[b] = tmp;
+        }
+    const int cand3[7][3] = {{3, 3, 3}, {2, 2, 2}, {3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
+    int w[3] = {1, 1, 1};
+    for (int c = 0; c < ncand; c++) {
+        const int *cd = d == 3 ? cand3[c] : (d == 2 ? cand2[c] : cand1[c]);
+        int wt[3] = {1, 1, 1};
+        for (int r = 0; r < d; r++) wt[ord[r]] = cd[r];
+        if (block_valid(cls, n, d, I, s, wt)) {
+            w[0] = wt[0];
+            w[1] = wt[1];
+            w[2] = wt[2];
+            break;
+        }
+    }
+    int sp[3] = {s[0], s[1], s[2]};
+    for (int k = 0; k < d; k++) {
+        const int far = I[k] - 2 * s[k];
+        if (far < 0 || far > N) sp[k] = -s[k];
+    }
+    const double phiG = phi[p];
+    double eta;
+    int fb = 0;
+    if (phiG == 0.0) {
+        eta = 0.0;
+    } else {
+        const double his[3] = {1.0, 1.5, 2.0};
+        double hi = -1.0;
+        for (int c = 0; c < 3; c++) {
+            double t[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < d; k++) t[k] = his[c] * nv[k] * sp[k];
+            if (phi_tilde(phi, n, d, I, sp, t) < 0.0) {
+                hi = his[c];
+                break;
+            }
+        }
+        if (hi > 0.0) {
+            double lo = 0.0;
+            for (int it = 0; it < 60; it++) {
+                const double mid = 0.5 * (lo + hi);
+                double t[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < d; k++) t[k] = mid * nv[k] * sp[k];
+                if (phi_tilde(phi, n, d, I, sp, t) < 0.0)
+                    hi = mid;
+                else
+                    lo = mid;
+            }
+            eta = 0.5 * (lo + hi);
+        } else {
+            eta = phiG / (h * gnorm);
+            if (!(eta < 1.0)) eta = 1.0;
+            fb = 1;
+        }
+    }
+    int code = 0;
+    for (int k = 0; k < 3; k++) {
+        code |= (w[k] & 3) << (2 * k);
+        if (s[k] < 0) code |= 1 << (6 + k);
+        gn[3 * gi + k] = nv[k];
+        const double xk = k < d ? -1.0 + I[k] * h : 0.0;
+        gq[3 * gi + k] = k < d ? xk - eta * h * nv[k] : 0.0;
+        gtau[3 * gi + k] = (k < d && w[k] >= 2) ? eta * fabs(nv[k]) : 0.0;
+    }
+    gcode[gi] = code;
+    geta[gi] = eta;
+    gfb[gi] = fb;
+    gdtau[gi] = dtau_of(d, eta, dtau_mode, dtau_const);
+}
+
+void launch_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx, int ng,
+                           int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau, double *geta,
+                           double *gn, double *gq, int *gfb, hipStream_t s) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(k_ghost_geometry, dim3((ng + 127) / 128), dim3(128), 0, s, d, N, h, phi, cls, gidx, ng,
+                       dtau_mode, dtau_const, gcode, gtau, gdtau, geta, gn, gq, gfb);
+}
+
+// ----------------------------------------------------------- extension band
+// OUTSIDE nodes within Chebyshev distance K of a ghost: the only nodes the
+// K extension sweeps can make non-zero.
+__global__ void k_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng, int K, uint8_t *mark) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= ng) return;
+    const int n = N + 1;
+    int I[3];
+    coords(gidx[gi], n, d, I);
+    const int r2 = d >= 3 ? K : 0, r1 = d >= 2 ? K : 0;
+    for (int m2 = -r2; m2 <= r2; m2++)
+        for (int m1 = -r1; m1 <= r1; m1++)
+            for (int m0 = -K; m0 <= K; m0++) {
+                const int J[3] = {I[0] + m0, I[1] + m1, I[2] + m2};
+                if (!in_box(J, N, d)) continue;
+                const long long q = index_of(J, n, d);
+                if (cls[q] == C_OUTSIDE) mark[q] = 1;
+            }
+}
+
+void launch_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng, int K, uint8_t *mark,
+                      hipStream_t s) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(k_band_mark, dim3((ng + 127) / 128), dim3(128), 0, s, d, N, cls, gidx, ng, K, mark);
+}
+
+__device__ int band_find(const int *bidx, int nb, int q) {
+    int lo = 0, hi = nb - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = bidx[mid];
+        if (v == q) return mid;
+        if (v < q)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+// Per band node X: its upwind neighbours X - s_k e_k with weights |n_k|:
+// reference >= 0: band entry; -1 - q: a GHOST node q (read from the field);
+// kRefZero: value 0 (BOXDIR, or OUTSIDE beyond the band), weight kept;
+// out-of-box terms get weight 0.  kRefFallback when the weights sum to 0.
+__global__ void k_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,
+                               int *bref, double *bw) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int n = N + 1;
+    const long long p = bidx[b];
+    int I[3];
+    coords(p, n, d, I);
+    double g[3];
+    grad_at(phi, n, d, h, I, p, g);
+    double gnorm = 0.0;
+    for (int k = 0; k < d; k++) gnorm += g[k] * g[k];
+    gnorm = sqrt(gnorm);
+    double den = 0.0;
+    for (int k = 0; k < 3; k++) {
+        bref[3 * b + k] = kRefZero;
+        bw[3 * b + k] = 0.0;
+    }
+    if (gnorm > 0.0) {
+        for (int k = 0; k < d; k++) {
+            const double nk = g[k] / gnorm;
+            const int sk = g[k] >= 0.0 ? 1 : -1;
+            int J[3] = {I[0], I[1], I[2]};
+            J[k] -= sk;
+            if (!in_box(J, N, d)) continue;
+            const long long q = index_of(J, n, d);
+            const uint8_t c = cls[q];
+            int ref = kRefZero;
+            if (c == C_GHOST) {
+                ref = -1 - (int)q;
+            } else if (c == C_OUTSIDE) {
+                const int bi = band_find(bidx, nb, (int)q);
+                ref = bi >= 0 ? bi : kRefZero;
+            }
+            bref[3 * b + k] = ref;
+            bw[3 * b + k] = fabs(nk);
+            den += fabs(nk);
+        }
+    }
+    if (!(den > 0.0)) bref[3 * b] = kRefFallback;
+}
+
+void launch_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,
+                         int *bref, double *bw, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_band_records, dim3((nb + 127) / 128), dim3(128), 0, s, d, N, h, phi, cls, bidx, nb, bref, bw);
+}
+
+// x-extent of the INSIDE/GHOST nodes of each grid row (-1 if none).
+__global__ void k_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, long long rows) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const uint8_t *row = cls + r * n;
+    int lo = -1, hi = -1;
+    for (int x = 0; x < n; x++) {
+        const uint8_t c = row[x];
+        if (c == C_INSIDE || c == C_GHOST) {
+            if (lo < 0) lo = x;
+            hi = x;
+        }
+    }
+    xmin[r] = lo;
+    xmax[r] = hi;
+}
+
+void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s) {
+    long long rows = 1;
+    for (int k = 1; k < d; k++) rows *= n;
+    hipLaunchKernelGGL(k_row_extent, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, s, d, n, cls, xmin, xmax,
+                       rows);
+}
+
+// ----------------------------------------------------- coarsest-level inverse
+// One workgroup: unknowns INSIDE (ascending) then GHOST (ascending), dense
+// matrix of the interior and ghost rows, Gauss-Jordan with partial pivoting
+// on [A | I].  info[0] = unknowns, info[1] = 1 if a pivot falls below
+// 1e-14 max|A| (singular: the cycle then smooths instead).
+__global__ void k_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
+                               const double *gtau, double *work, double *ainv, int *cmap, int *info) {
+    const int n = N + 1;
+    int nn = 1;
+    for (int k = 0; k < d; k++) nn *= n;
+    __shared__ int pos[kCoarseMax];
+    __shared__ int s_nc, s_piv, s_sing;
+    __shared__ double s_amax;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int c = 0;
+        for (int p = 0; p < nn; p++) {
+            pos[p] = -1;
+            if (cls[p] == C_INSIDE) {
+                pos[p] = c;
+                cmap[c++] = p;
+            }
+        }
+        for (int g = 0; g < ng; g++) {
+            pos[gidx[g]] = c;
+            cmap[c++] = gidx[g];
+        }
+        s_nc = c;
+        s_sing = 0;
+    }
+    __syncthreads();
+    const int nc = s_nc;
+    const int W = 2 * nc;
+    for (int i = t; i < nc * W; i += blockDim.x) {
+        const int r = i / W, c = i % W;
+        work[i] = (c >= nc && c - nc == r) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double ih2 = 1.0 / (h * h);
+    if (t == 0) {
+        for (int row = 0; row < nc; row++) {
+            const int p = cmap[row];
+            if (cls[p] == C_INSIDE) {
+                work[row * W + row] += 2.0 * d * ih2;
+                int str = 1;
+                for (int k = 0; k < d; k++) {
+                    if (pos[p - str] >= 0) work[row * W + pos[p - str]] -= ih2;
+                    if (pos[p + str] >= 0) work[row * W + pos[p + str]] -= ih2;
+                    str *= n;
+                }
+            }
+        }
+        for (int g = 0; g < ng; g++) {
+            const int row = pos[gidx[g]];
+            int I[3];
+            coords(gidx[g], n, d, I);
+            const int code = gcode[g];
+            int w[3], s[3];
+            for (int k = 0; k < 3; k++) {
+                w[k] = k < d ? code_w(code, k) : 1;
+                s[k] = code_s(code, k);
+            }
+            for (int m2 = 0; m2 < w[2]; m2++)
+                for (int m1 = 0; m1 < w[1]; m1++)
+                    for (int m0 = 0; m0 < w[0]; m0++) {
+                        const int m[3] = {m0, m1, m2};
+                        int J[3];
+                        double wgt = 1.0;
+                        for (int k = 0; k < 3; k++) {
+                            J[k] = I[k] - m[k] * s[k];
+                            wgt *= lag(w[k], m[k], k < d ? gtau[3 * g + k] : 0.0);
+                        }
+                        work[row * W + pos[index_of(J, n, d)]] += wgt;
+                    }
+        }
+        double amax = 0.0;
+        for (int r = 0; r < nc; r++)
+            for (int c = 0; c < nc; c++) amax = fmax(amax, fabs(work[r * W + c]));
+        s_amax = amax;
+    }
+    __syncthreads();
+    for (int k = 0; k < nc; k++) {
+        if (t == 0) {
+            int pr = k;
+            for (int i = k + 1; i < nc; i++)
+                if (fabs(work[i * W + k]) > fabs(work[pr * W + k])) pr = i;
+            s_piv = pr;
+            if (fabs(work[pr * W + k]) < 1e-14 * s_amax) s_sing = 1;
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const int pr = s_piv;
+        if (pr != k)
+            for (int c = t; c < W; c += blockDim.x) {
+                const double tmp = work[k * W + c];
+                work[k * W + c] = work[pr * W + c];
+                work[pr * W + c] = tmp;
+            }
+        __syncthreads();
+        const double piv = work[k * W + k];
+        __syncthreads();
+        for (int c = t; c < W; c += blockDim.x) work[k * W + c] /= piv;
+        __syncthreads();
+        for (int i = t; i < nc * W; i += blockDim.x) {
+            const int r = i / W, c = i % W;
+            if (r == k || c == k) continue;
+            work[i] -= work[r * W + k] * work[k * W + c];
+        }
+        __syncthreads();
+        for (int r = t; r < nc; r += blockDim.x)
+            if (r != k) work[r * W + k] = 0.0;
+        __syncthreads();
+    }
+    for (int i = t; i < nc * nc; i += blockDim.x) ainv[i] = work[(i / nc) * W + nc + (i % nc)];
+    if (t == 0) {
+        info[0] = nc;
+        info[1] = s_sing;
+    }
+}
+
+void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
+                         const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_setup, dim3(1), dim3(kBlock), 0, s, d, N, h, cls, gidx, ng, gcode, gtau, work, ainv,
+                       cmap, info);
+}
+
+// ------------------------------------------------------------- data movement
+__global__ void k_set_rhs(long long nn, const uint8_t *cls, const double *f, double *rhs) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nn) return;
+    rhs[p] = (f && cls[p] == C_INSIDE) ? f[p] : 0.0;
+}
+
+void launch_set_rhs(long long nn, const uint8_t *cls, const double *f, double *rhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_rhs, dim3((unsigned)((nn + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nn, cls, f, rhs);
+}
+
+__global__ void k_scatter_ghosts(const int *gidx, int ng, const double *gq, double *rhs) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ng) rhs[gidx[g]] = gq[g];
+}
+
+void launch_scatter_ghosts(const int *gidx, int ng, const double *gq, double *rhs, hipStream_t s) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(k_scatter_ghosts, dim3((ng + kBlock - 1) / kBlock), dim3(kBlock), 0, s, gidx, ng, gq, rhs);
+}
+
+__global__ void k_fill_boundary(long long nn, const uint8_t *cls, const double *gbox, double *u) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nn) return;
+    if (cls[p] == C_BOXDIR) u[p] = gbox ? gbox[p] : 0.0;
+}
+
+void launch_fill_boundary(long long nn, const uint8_t *cls, const double *gbox, double *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_boundary, dim3((unsigned)((nn + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nn, cls,
+                       gbox, u);
+}
+
+}  // namespace bcmg

@@ -1,0 +1,196 @@
+"""GPU parity against the oracle, through the C ABI (needs an MI355X).
+
+ * setup: class arrays, ghost lists and stencil codes bit-exact on every
+   level; eta, normal, Q, tau and dtau within 1e-13 (relative to 1);
+ * single steps on identical inputs: smoothing, residual, extension,
+   restriction, prolongation, coarse solve within 1e-12 (relative);
+ * whole FP64 solves: same cycle count, per-cycle residual norms within 1e-8
+   relative while above 1e-13 of r0, final u within 1e-12 relative.
+Sizes span several row segments and ghost chunks with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_14208_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_14208_amd.solver import Problem
+    return Problem
+
+
+def spheres_case(N=64, seed=7, m=30):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cen = rng.uniform(-0.7, 0.7, size=(m, 3))
+    rad = rng.uniform(0.05, 0.2, size=m)
+    f_fn = W.smooth_random_f(rng, 3)
+    return W.make_case(f"spheres{N}", 3, N, W.phi_spheres(cen, rad), None, f_fn=f_fn)
+
+
+CASES = {
+    "circle65": lambda: W.circle_65(),
+    "flower2d_129": lambda: W.make_case("flower2d", 2, 128, W.phi_flower2d(), W.sincos_xy()),
+    "star_257": lambda: W.star_case(0, 257, 0.45, 0.08, 5),
+    "fullbox2d_33": lambda: W.make_case("box", 2, 32, W.phi_full_box, W.sincos_xy()),
+    "ellipsoid_33": lambda: W.ellipsoid(32),
+    "flower3d_65": lambda: W.flower3d(64),
+    "spheres_65": lambda: spheres_case(64),
+    "line1d_129": lambda: W.make_case("line1d", 1, 128, W.phi_halfspace(0.3137), W.Manufactured(
+        u=lambda x: np.exp(x), f=lambda x: -np.exp(x))),
+}
+
+
+def build_pair(name, **opt):
+    Problem = _gpu()
+    c = CASES[name]()
+    o_opts = oracle.Options(**{k: v for k, v in opt.items() if k in ("dtau_mode", "dtau_const", "ext_iters", "restrict_mode")})
+    O = oracle.Problem(c.d, c.N, c.phi, o_opts)
+    G = Problem(c.d, c.N, c.phi, **opt)
+    return c, O, G
+
+
+def unknowns(cls):
+    return (cls == oracle.INSIDE) | (cls == oracle.GHOST)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_setup_parity(name):
+    c, O, G = build_pair(name)
+    assert G.levels == O.L
+    for l in range(O.L):
+        co = O.classes(l)
+        cg = G.classes(l).cpu().numpy()
+        assert np.array_equal(co, cg), f"level {l}: classes differ at {np.nonzero(co != cg)[0][:10]}"
+        ni, ng = O.counts(l)
+        info = G.level_info(l)
+        assert (info["n_inside"], info["n_ghost"]) == (ni, ng)
+        og = O.ghosts(l)
+        gg = {k: v.cpu().numpy() for k, v in G.ghost_info(l).items()}
+        assert np.array_equal(og["idx"], gg["idx"].astype(np.int64))
+        code = gg["code"]
+        w = np.stack([(code >> (2 * k)) & 3 for k in range(3)], axis=1)
+        s = np.stack([np.where((code >> (6 + k)) & 1, -1, 1) for k in range(3)], axis=1)
+        assert np.array_equal(w, og["w"]), f"level {l}: widths differ"
+        assert np.array_equal(s, og["s"]), f"level {l}: signs differ"
+        assert np.array_equal(gg["fb"], og["fb"])
+        for key in ("eta", "n", "q", "tau", "dtau"):
+            a, b = og[key], gg[key]
+            assert np.allclose(a, b, rtol=1e-13, atol=1e-13), (l, key, np.abs(a - b).max())
+
+
+def _rhs_pair(c, O, G):
+    og = O.ghosts(0)
+    gg = G.ghost_info(0)
+    O.set_rhs(c.f, W.points_eval(c.g, og["q"], c.d))
+    G.set_data(c.f, W.points_eval(c.g, gg["q"].cpu().numpy(), c.d))
+    return O.rhs(0)
+
+
+def _close(a, b, tol=1e-12):
+    scale = max(np.abs(a).max(), np.abs(b).max(), 1e-300)
+    return np.abs(a - b).max() <= tol * scale
+
+
+@pytest.mark.parametrize("name", ["circle65", "flower3d_65", "spheres_65", "line1d_129", "fullbox2d_33"])
+def test_step_parity(name):
+    c, O, G = build_pair(name)
+    rhs0 = _rhs_pair(c, O, G)
+    rng = np.random.default_rng(11)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for l in range(min(2, O.L - 1)):
+        cls = O.classes(l)
+        nn = cls.size
+        rhs = rhs0 if l == 0 else np.where(unknowns(cls), rng.standard_normal(nn), 0.0)
+        u = np.where(unknowns(cls), rng.uniform(-1, 1, nn), 0.0)
+        u[cls == oracle.BOXDIR] = rng.uniform(-1, 1, (cls == oracle.BOXDIR).sum())
+        # smoothing
+        uo = u.copy()
+        O.smooth(l, uo, rhs, steps=3)
+        ug = dev(u)
+        G.level_smooth(l, ug, dev(rhs), 3)
+        assert _close(uo, ug.cpu().numpy()), f"smooth level {l}"
+        # residual
+        ro = O.residual(l, u, rhs)
+        rg = torch.zeros(nn, dtype=torch.float64, device="cuda")
+        ng = G.level_residual(l, dev(u), dev(rhs), rg, with_norm=True)
+        assert _close(ro, rg.cpu().numpy())
+        assert abs(ng - O.norm(l, ro)) <= 1e-12 * O.norm(l, ro)
+        # extension of the residual, then restriction
+        ve = ro.copy()
+        O.extend(l, ve)
+        vg = rg.clone()
+        G.level_extend(l, vg)
+        assert _close(ve, vg.cpu().numpy()), f"extend level {l}"
+        rc_o = O.restrict(l, ve)
+        rc_g = torch.zeros(O.nodes(l + 1), dtype=torch.float64, device="cuda")
+        G.level_restrict(l, vg, rc_g)
+        cc = O.classes(l + 1)
+        m = unknowns(cc)
+        assert _close(rc_o[m], rc_g.cpu().numpy()[m]), f"restrict level {l}"
+        # prolongation of a random coarse error
+        ec = np.where(m, rng.standard_normal(cc.size), 0.0)
+        eo, uo = ec.copy(), u.copy()
+        O.prolong(l, eo, uo)
+        eg, ugp = dev(ec), dev(u)
+        G.level_prolong(l, eg, ugp)
+        assert _close(eo, eg.cpu().numpy()), f"coarse extension level {l}"
+        assert _close(uo, ugp.cpu().numpy()), f"prolong level {l}"
+    # coarsest solve
+    L = O.L - 1
+    cls = O.classes(L)
+    rhs = np.where(unknowns(cls), rng.standard_normal(cls.size), 0.0)
+    uo = np.zeros(cls.size)
+    O.coarse_solve(uo, rhs)
+    ug = torch.zeros(cls.size, dtype=torch.float64, device="cuda")
+    G.coarse_solve(ug, dev(rhs))
+    assert _close(uo, ug.cpu().numpy(), 1e-11)
+
+
+def solve_pair(name, tol=1e-10, **opt):
+    c, O, G = build_pair(name, **opt)
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = c.gB.copy()
+    uo[unknowns(cls)] = 0.0
+    it, ho = O.solve(uo, tol)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hg = G.solve(ug, tol)
+    return c, O, G, it, ho, uo, st, hg, ug.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_parity_fp64(name):
+    c, O, G, it, ho, uo, st, hg, ug = solve_pair(name)
+    assert it > 0 and st.status == 0
+    assert st.cycles == it, (st.cycles, it)
+    keep = ho / ho[0] > 1e-13
+    assert np.allclose(hg[keep], ho[keep], rtol=1e-8, atol=0)
+    assert _close(uo, ug, 1e-12), np.abs(uo - ug).max()
+
+
+@pytest.mark.parametrize("mode,const", [(1, 1.0), (2, 1.75)])
+def test_solve_parity_dtau_modes(mode, const):
+    c, O, G, it, ho, uo, st, hg, ug = solve_pair("circle65", dtau_mode=mode, dtau_const=const)
+    assert st.cycles == it and _close(uo, ug, 1e-12)
+
+
+def test_vcycle_and_residual_norm_match_oracle():
+    c, O, G = build_pair("flower3d_65")
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = c.gB.copy()
+    uo[unknowns(cls)] = 0.0
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    for _ in range(2):
+        O.vcycle(uo)
+        G.vcycle(ug)
+    assert _close(uo, ug.cpu().numpy(), 1e-12)
+    rn_o = O.norm(0, O.residual(0, uo))
+    assert abs(G.residual_norm(ug) - rn_o) <= 1e-10 * rn_o
