@@ -147,9 +147,12 @@ class Problem:
         self.L = lib().or_num_levels(self.h)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None) and _lib is not None:
+                _lib.or_destroy(self.h)
+        except Exception:
+            pass
+        self.h = None
 
     # --- geometry ---------------------------------------------------------
     def nodes(self, l: int = 0) -> int:
@@ -264,7 +267,7 @@ class Problem:
         """In place on u.  Returns (cycles or -1, residual history)."""
         assert u.dtype == np.float64 and u.flags.c_contiguous
         mc = self.opts.max_cycles if max_cycles is None else max_cycles
-        hist = np.full(mc + 1, np.nan)
+        hist = np.full(mc + 1, -1.0)  # norms are >= 0: -1 marks entries never written
         it = lib().or_solve(self.h, _p(u), float(tol), mc, _p(hist))
-        n = (it if it >= 0 else mc) + 1
+        n = (it + 1) if it >= 0 else int(np.argmax(hist == -1.0)) if np.any(hist == -1.0) else mc + 1
         return it, hist[: n]

@@ -276,12 +276,33 @@ static int or_block_valid(const or_level *L, const int I[3], const int s[3], con
     return 1;
 }
 
+/* c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block) */
+static int or_block_dominant(const or_level *L, const int I[3], const int s[3], const int w[3], const double tau[3], double f) {
+    double c0 = 1.0, off = 0.0;
+    int m[3];
+    for (m[2] = 0; m[2] < w[2]; m[2]++)
+        for (m[1] = 0; m[1] < w[1]; m[1]++)
+            for (m[0] = 0; m[0] < w[0]; m[0]++) {
+                int J[3];
+                double wgt = 1.0;
+                for (int k = 0; k < 3; k++) {
+                    J[k] = I[k] - m[k] * s[k];
+                    wgt *= or_lagrange(w[k], m[k], tau[k]);
+                }
+                if (m[0] == 0 && m[1] == 0 && m[2] == 0)
+                    c0 = wgt;
+                else if (L->cls[or_index(L, J)] == OR_GHOST)
+                    off += fabs(wgt);
+            }
+    return c0 >= f * off;
+}
+
 /*
  * Geometry of one ghost point G (Sec. 2.3, eqs. (BCh), (rel), (DtauOptTheta)):
  * normal n, upwind signs, stencil widths, projection Q = G - eta h n with
  * phi~(Q) = 0, local coordinates tau of Q, theta~ = |G-Q|/h = eta, Delta tau.
  */
-static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
+static void or_ghost_geometry(or_level *L, int level, long gi, const or_options *o) {
     static const int cand3[7][3] = {{3, 3, 3}, {2, 2, 2}, {3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     static const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     static const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
@@ -335,21 +356,6 @@ static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
         }
     }
 
-    /* first valid width vector (entries assigned to axes in dominance order) */
-    const int(*cand)[3] = d == 3 ? cand3 : (d == 2 ? cand2 : cand1);
-    int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
-    int w[3] = {1, 1, 1};
-    for (int c = 0; c < ncand; c++) {
-        int wt[3] = {1, 1, 1};
-        for (int r = 0; r < d; r++) wt[ord[r]] = cand[c][r];
-        if (or_block_valid(L, I, s, wt)) {
-            w[0] = wt[0];
-            w[1] = wt[1];
-            w[2] = wt[2];
-            break;
-        }
-    }
-
     /* root of phi~(G - eta h n) = 0 on the 3^d upwind block; an axis whose
      * block leaves the box is flipped for the interpolant only */
     int sp[3] = {s[0], s[1], s[2]};
@@ -363,15 +369,12 @@ static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
     if (phiG == 0.0) {
         eta = 0.0;
     } else {
-        static const double his[3] = {1.0, 1.5, 2.0};
+        /* eta is sought in [0, 1] (Sec. 2.3): bracket at eta = 1 */
         double hi = -1.0;
-        for (int c = 0; c < 3; c++) {
+        {
             double t[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < d; k++) t[k] = his[c] * n[k] * sp[k];
-            if (or_phi_tilde(L, I, sp, t) < 0.0) {
-                hi = his[c];
-                break;
-            }
+            for (int k = 0; k < d; k++) t[k] = n[k] * sp[k];
+            if (or_phi_tilde(L, I, sp, t) < 0.0) hi = 1.0;
         }
         if (hi > 0.0) {
             double lo = 0.0;
@@ -392,6 +395,29 @@ static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
         }
     }
 
+    /* first admissible width vector (entries assigned to axes in dominance
+     * order): block inside the box, made of INSIDE/GHOST nodes, and a row
+     * whose own weight c_0 is at least f times the sum of the |weights| of
+     * the other ghosts of the block: f = 1 on coarse levels (their ghost rows,
+     * relaxed together, then form a diagonally dominant block), f = 1/2 on
+     * the finest level (only strongly crossed pairs of ghost rows, where the
+     * geometry is under-resolved, lose the full stencil) */
+    const int(*cand)[3] = d == 3 ? cand3 : (d == 2 ? cand2 : cand1);
+    int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
+    int w[3] = {1, 1, 1};
+    for (int c = 0; c < ncand; c++) {
+        int wt[3] = {1, 1, 1};
+        for (int r = 0; r < d; r++) wt[ord[r]] = cand[c][r];
+        if (!or_block_valid(L, I, s, wt)) continue;
+        double tt[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(n[k]) : 0.0;
+        if (!or_block_dominant(L, I, s, wt, tt, level > 0 ? 1.0 : 0.5)) continue;
+        w[0] = wt[0];
+        w[1] = wt[1];
+        w[2] = wt[2];
+        break;
+    }
+
     for (int k = 0; k < 3; k++) {
         L->gw[3 * gi + k] = w[k];
         L->gs[3 * gi + k] = s[k];
@@ -402,7 +428,17 @@ static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
     }
     L->geta[gi] = eta;
     L->gfb[gi] = fb;
-    L->gdtau[gi] = or_dtau(d, eta, o->dtau_mode, o->dtau_const);
+    double dt = or_dtau(d, eta, o->dtau_mode, o->dtau_const);
+    /* never relax a ghost row beyond its own Gauss-Seidel step dtau = 1/c_0
+     * (the value the relaxation reduces to at theta = 0, Sec. 1.1); on the
+     * quadratic row of the BLFA this bound is inactive in 2D and within 3%
+     * in 3D, it only tames the shortened stencils */
+    if (o->dtau_mode != OR_DTAU_CONST) {
+        double c0 = 1.0;
+        for (int k = 0; k < 3; k++) c0 *= or_lagrange(w[k], 0, L->gtau[3 * gi + k]);
+        if (c0 > 0.0 && dt * c0 > 1.0) dt = 1.0 / c0;
+    }
+    L->gdtau[gi] = dt;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -913,7 +949,7 @@ static void or_level_alloc(or_level *L, int d, int N) {
     L->e = (double *)calloc(L->nn, sizeof(double));
 }
 
-static void or_level_geometry(or_level *L, const or_options *o) {
+static void or_level_geometry(or_level *L, int level, const or_options *o) {
     or_classify(L->d, L->N, L->phi, L->cls);
     L->ni = L->ng = 0;
     for (long p = 0; p < L->nn; p++) {
@@ -933,7 +969,7 @@ static void or_level_geometry(or_level *L, const or_options *o) {
     long c = 0;
     for (long p = 0; p < L->nn; p++)
         if (L->cls[p] == OR_GHOST) L->gidx[c++] = p;
-    for (long gi = 0; gi < L->ng; gi++) or_ghost_geometry(L, gi, o);
+    for (long gi = 0; gi < L->ng; gi++) or_ghost_geometry(L, level, gi, o);
 }
 
 /*
@@ -974,7 +1010,7 @@ or_problem *or_setup(int d, int N, const double *phi, const or_options *opt) {
             C->phi[pc] = F->phi[or_index(F, I)];
         }
     }
-    for (int l = 0; l < L; l++) or_level_geometry(&P->lev[l], opt);
+    for (int l = 0; l < L; l++) or_level_geometry(&P->lev[l], l, opt);
     or_coarse_factor(P);
     return P;
 }

@@ -34,13 +34,14 @@ bcmg_status fail(bcmg_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(BCMG_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// finest-level red-black sweep timing (bcmg_timing_*)
+// finest-level red-black sweep timing (bcmg_timing_*): event pairs are
+// recorded around the sweep launches when a batch graph is captured, so every
+// replay re-records them; their durations are summed after each replay.
 struct Timing {
     bool on = false;
     long long launches = 0;
     double ms = 0.0;
     long long nodes = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 } g_timing;
 
 }  // namespace
@@ -140,6 +141,8 @@ struct bcmg_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_cycles = 0;
+    bool graph_timed = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // timing events recorded by the graph
 };
 
 namespace {
@@ -256,7 +259,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gdelta, ng)))
         return st;
     launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
-    launch_ghost_geometry(d, V.N, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
+    launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
                           V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, s);
     // extension band (only levels that restrict or receive a prolongation need it)
     {
@@ -766,6 +769,11 @@ static void drop_graph(bcmg_batch *b) {
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_cycles = 0;
+    for (auto &pr : b->tev) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    b->tev.clear();
 }
 
 bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
@@ -965,10 +973,9 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
 
 static void timed_sweep(bcmg_batch *b, int a, int colour) {
     const Lists &L = b->lv[a];
-    const bool fine = g_timing.on && a == b->A - 1;
+    const bool fine = b->graph_timed && a == b->A - 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (fine) {
-        g_timing.nodes = b->fine_inside;
         hipEventCreate(&e0);
         hipEventCreate(&e1);
         hipEventRecord(e0, b->stream);
@@ -976,7 +983,7 @@ static void timed_sweep(bcmg_batch *b, int a, int colour) {
     launch_rb_sweep(b->d, b->fp32, b->d_desc, L.segs, L.nseg, colour, b->d_state, b->stream);
     if (fine) {
         hipEventRecord(e1, b->stream);
-        g_timing.pending.push_back({e0, e1});
+        b->tev.push_back({e0, e1});
     }
 }
 
@@ -1104,13 +1111,9 @@ static bcmg_status batch_launch_cycles(bcmg_batch *b, int cycles) {
         bcmg_status st = batch_rebuild(b);
         if (st) return st;
     }
-    if (g_timing.on) {
-        for (int c = 0; c < cycles; c++) launch_cycle(b);
-        HIPCHK(hipGetLastError());
-        return BCMG_OK;
-    }
-    if (!b->exec || b->graph_cycles != cycles) {
+    if (!b->exec || b->graph_cycles != cycles || b->graph_timed != g_timing.on) {
         drop_graph(b);
+        b->graph_timed = g_timing.on;
         HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < cycles; c++) launch_cycle(b);
         hipError_t e = hipStreamEndCapture(b->stream, &b->graph);
@@ -1130,6 +1133,15 @@ bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host)
     if (st) return st;
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState) * b->cap, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
+    if (b->graph_timed) {
+        for (auto &pr : b->tev) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            g_timing.ms += ms;
+            g_timing.launches++;
+        }
+        g_timing.nodes = b->fine_inside;
+    }
     if (active_host)
         for (int s = 0; s < b->cap; s++) active_host[s] = b->prob[s] && b->h_state[s].active ? 1 : 0;
     return BCMG_OK;
@@ -1259,11 +1271,6 @@ bcmg_status bcmg_residual_norm(bcmg_problem *P, const double *u, double *norm_ho
 
 // ------------------------------------------------------------ timing
 bcmg_status bcmg_timing_enable(int32_t on) {
-    for (auto &pr : g_timing.pending) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
-    }
-    g_timing.pending.clear();
     g_timing.on = on != 0;
     g_timing.launches = 0;
     g_timing.ms = 0.0;
@@ -1271,16 +1278,6 @@ bcmg_status bcmg_timing_enable(int32_t on) {
 }
 
 bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *nodes) {
-    for (auto &pr : g_timing.pending) {
-        HIPCHK(hipEventSynchronize(pr.second));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        g_timing.ms += ms;
-        g_timing.launches++;
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
-    }
-    g_timing.pending.clear();
     if (launches) *launches = g_timing.launches;
     if (total_ms) *total_ms = g_timing.ms;
     if (nodes) *nodes = g_timing.nodes;

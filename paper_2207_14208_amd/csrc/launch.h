@@ -36,9 +36,9 @@ void launch_classify(int d, int n, const double *phi, uint8_t *cls, hipStream_t 
 int compact_blocks(long long nn);
 void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
                     int *total_dev, hipStream_t s);
-void launch_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx, int ng,
-                           int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau, double *geta,
-                           double *gn, double *gq, int *gfb, hipStream_t s);
+void launch_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls, const int *gidx,
+                           int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
+                           double *geta, double *gn, double *gq, int *gfb, hipStream_t s);
 void launch_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng, int K, uint8_t *mark,
                       hipStream_t s);
 void launch_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,

@@ -223,6 +223,28 @@ __device__ bool block_valid(const uint8_t *cls, int n, int d, const int I[3], co
     return true;
 }
 
+// c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block)
+__device__ bool block_dominant(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3],
+                               const double tau[3], double f) {
+    double c0 = 1.0, off = 0.0;
+    for (int m2 = 0; m2 < w[2]; m2++)
+        for (int m1 = 0; m1 < w[1]; m1++)
+            for (int m0 = 0; m0 < w[0]; m0++) {
+                const int m[3] = {m0, m1, m2};
+                int J[3];
+                double wgt = 1.0;
+                for (int k = 0; k < 3; k++) {
+                    J[k] = I[k] - m[k] * s[k];
+                    wgt *= lag(w[k], m[k], tau[k]);
+                }
+                if (m0 == 0 && m1 == 0 && m2 == 0)
+                    c0 = wgt;
+                else if (cls[index_of(J, n, d)] == C_GHOST)
+                    off += fabs(wgt);
+            }
+    return c0 >= f * off;
+}
+
 __device__ double dtau_of(int d, double theta, int mode, double cnst) {
     if (mode == BCMG_DTAU_CONST) return cnst;
     double t = theta < 1.0 ? theta : 1.0;
@@ -244,13 +266,16 @@ __device__ double dtau_of(int d, double theta, int mode, double cnst) {
     return 2.0 / (gmin + gmax);
 }
 
-// One ghost G: discrete normal, upwind signs, axis dominance, first valid
-// stencil widths, root eta of phi~(G - eta h n) = 0 by bracketing and 60
-// bisections, Q, tau and dtau(theta~ = eta).  Sec. 2.3 eqs. BCh, rel,
+// One ghost G: discrete normal, upwind signs, axis dominance, root eta in
+// [0,1] of phi~(G - eta h n) = 0 (bracket at 1, 60 bisections), first
+// admissible stencil widths (in the box, INSIDE/GHOST nodes only, row weight
+// on G at least f times its |weight| on the block's other ghosts: f = 1/2 on
+// the finest level, 1 on coarse levels), Q, tau and dtau(theta~ = eta)
+// bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 2.3 eqs. BCh, rel,
 // DtauOptTheta, Remark exptheta2D.
-__global__ void k_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx,
-                                 int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
-                                 double *geta, double *gn, double *gq, int *gfb) {
+__global__ void k_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls,
+                                 const int *gidx, int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau,
+                                 double *gdtau, double *geta, double *gn, double *gq, int *gfb) {
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
     const int n = N + 1;
@@ -292,22 +317,6 @@ __global__ void k_ghost_geometry(int d, int N, double h, const double *phi, cons
             ord[b - 1] = ord[b];
             ord[b] = tmp;
         }
-    const int cand3[7][3] = {{3, 3, 3}, {2, 2, 2}, {3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
-    const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
-    const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
-    const int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
-    int w[3] = {1, 1, 1};
-    for (int c = 0; c < ncand; c++) {
-        const int *cd = d == 3 ? cand3[c] : (d == 2 ? cand2[c] : cand1[c]);
-        int wt[3] = {1, 1, 1};
-        for (int r = 0; r < d; r++) wt[ord[r]] = cd[r];
-        if (block_valid(cls, n, d, I, s, wt)) {
-            w[0] = wt[0];
-            w[1] = wt[1];
-            w[2] = wt[2];
-            break;
-        }
-    }
     int sp[3] = {s[0], s[1], s[2]};
     for (int k = 0; k < d; k++) {
         const int far = I[k] - 2 * s[k];
@@ -319,15 +328,11 @@ __global__ void k_ghost_geometry(int d, int N, double h, const double *phi, cons
     if (phiG == 0.0) {
         eta = 0.0;
     } else {
-        const double his[3] = {1.0, 1.5, 2.0};
-        double hi = -1.0;
-        for (int c = 0; c < 3; c++) {
+        double hi = -1.0;  // eta is sought in [0, 1]: bracket at eta = 1
+        {
             double t[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < d; k++) t[k] = his[c] * nv[k] * sp[k];
-            if (phi_tilde(phi, n, d, I, sp, t) < 0.0) {
-                hi = his[c];
-                break;
-            }
+            for (int k = 0; k < d; k++) t[k] = nv[k] * sp[k];
+            if (phi_tilde(phi, n, d, I, sp, t) < 0.0) hi = 1.0;
         }
         if (hi > 0.0) {
             double lo = 0.0;
@@ -347,6 +352,24 @@ __global__ void k_ghost_geometry(int d, int N, double h, const double *phi, cons
             fb = 1;
         }
     }
+    const int cand3[7][3] = {{3, 3, 3}, {2, 2, 2}, {3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
+    const int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
+    int w[3] = {1, 1, 1};
+    for (int c = 0; c < ncand; c++) {
+        const int *cd = d == 3 ? cand3[c] : (d == 2 ? cand2[c] : cand1[c]);
+        int wt[3] = {1, 1, 1};
+        for (int r = 0; r < d; r++) wt[ord[r]] = cd[r];
+        if (!block_valid(cls, n, d, I, s, wt)) continue;
+        double tt[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(nv[k]) : 0.0;
+        if (!block_dominant(cls, n, d, I, s, wt, tt, level > 0 ? 1.0 : 0.5)) continue;
+        w[0] = wt[0];
+        w[1] = wt[1];
+        w[2] = wt[2];
+        break;
+    }
     int code = 0;
     for (int k = 0; k < 3; k++) {
         code |= (w[k] & 3) << (2 * k);
@@ -359,14 +382,20 @@ __global__ void k_ghost_geometry(int d, int N, double h, const double *phi, cons
     gcode[gi] = code;
     geta[gi] = eta;
     gfb[gi] = fb;
-    gdtau[gi] = dtau_of(d, eta, dtau_mode, dtau_const);
+    double dt = dtau_of(d, eta, dtau_mode, dtau_const);
+    if (dtau_mode != BCMG_DTAU_CONST) {  // at most the row's Gauss-Seidel step 1/c_0
+        double c0 = 1.0;
+        for (int k = 0; k < 3; k++) c0 *= lag(w[k], 0, gtau[3 * gi + k]);
+        if (c0 > 0.0 && dt * c0 > 1.0) dt = 1.0 / c0;
+    }
+    gdtau[gi] = dt;
 }
 
-void launch_ghost_geometry(int d, int N, double h, const double *phi, const uint8_t *cls, const int *gidx, int ng,
-                           int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau, double *geta,
-                           double *gn, double *gq, int *gfb, hipStream_t s) {
+void launch_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls, const int *gidx,
+                           int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
+                           double *geta, double *gn, double *gq, int *gfb, hipStream_t s) {
     if (ng <= 0) return;
-    hipLaunchKernelGGL(k_ghost_geometry, dim3((ng + 127) / 128), dim3(128), 0, s, d, N, h, phi, cls, gidx, ng,
+    hipLaunchKernelGGL(k_ghost_geometry, dim3((ng + 127) / 128), dim3(128), 0, s, d, N, level, h, phi, cls, gidx, ng,
                        dtau_mode, dtau_const, gcode, gtau, gdtau, geta, gn, gq, gfb);
 }
 

@@ -1,0 +1,97 @@
+"""GPU tests of the mixed-precision solve and of batches (needs an MI355X).
+
+Mixed precision (FP32 cycle on the correction, FP64 residual, update and
+coarse solve): converges to the same relative residual as FP64 and stays
+within 1e-8 (relative, max norm) of the oracle's FP64 solution solved to
+1e-12.  Batches: every problem gives the same bits alone and in a batch of
+different sizes, and matches the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_14208_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def oracle_solution(c, tol=1e-12):
+    O = oracle.Problem(c.d, c.N, c.phi)
+    og = O.ghosts(0)
+    O.set_rhs(c.f, W.points_eval(c.g, og["q"], c.d))
+    cls = O.classes(0)
+    u = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    it, h = O.solve(u, tol, 300)
+    return O, u, cls, it, h
+
+
+def gpu_problem(c, **opt):
+    from paper_2207_14208_amd.solver import Problem
+    G = Problem(c.d, c.N, c.phi, **opt)
+    gg = G.ghost_info(0)
+    G.set_data(c.f, W.points_eval(c.g, gg["q"].cpu().numpy(), c.d))
+    return G
+
+
+@pytest.mark.parametrize("name", ["circle65", "ellipsoid33", "flower3d65"])
+def test_mixed_precision_accuracy(name):
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    c = {"circle65": W.circle_65, "ellipsoid33": lambda: W.ellipsoid(32), "flower3d65": lambda: W.flower3d(64)}[name]()
+    O, ustar, cls, it, _ = oracle_solution(c)
+    G = gpu_problem(c, precision=N.MIXED)
+    u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hist = G.solve(u, 1e-10)
+    assert st.status == 0, st
+    Gd = gpu_problem(c)
+    ud = Gd.initial_guess(torch.from_numpy(c.gB).cuda())
+    std, _ = Gd.solve(ud, 1e-10)
+    assert abs(st.cycles - std.cycles) <= 2, (st.cycles, std.cycles)
+    m = (cls == oracle.INSIDE) | (cls == oracle.GHOST)
+    err = np.abs(u.cpu().numpy()[m] - ustar[m]).max() / np.abs(ustar[m]).max()
+    assert err <= 1e-8, err
+    # the final residual is an FP64 residual of the FP64 iterate
+    rn = O.norm(0, O.residual(0, u.cpu().numpy()))
+    assert rn <= 1.01 * 1e-10 * st.r0
+
+
+def test_batch_same_alone_and_in_mix():
+    _need_gpu()
+    from paper_2207_14208_amd.solver import Batch
+    params = [(65, 0.45, 0.05, 3), (129, 0.35, 0.09, 7), (33, 0.55, 0.02, 4), (257, 0.5, 0.1, 8), (65, 0.3, 0.0, 5)]
+    cases = [W.star_case(i, *p) for i, p in enumerate(params)]
+    alone = []
+    for c in cases:
+        G = gpu_problem(c)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        st, h = G.solve(u, 1e-10)
+        assert st.status == 0
+        alone.append((st, u.cpu().numpy()))
+    B = Batch(8)
+    probs, us = [], []
+    for c in cases:
+        G = gpu_problem(c)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        probs.append(G)
+        us.append(u)
+    slots = [B.add(G, u, 1e-10) for G, u in zip(probs, us)]
+    B.run(1, 200)
+    for (st_a, u_a), s, u in zip(alone, slots, us):
+        st, h = B.stats(s)
+        assert st.status == 0 and st.cycles == st_a.cycles
+        assert np.array_equal(u.cpu().numpy(), u_a)
+    # and each matches the oracle after the same number of cycles
+    for c, (st_a, u_a) in zip(cases[:3], alone[:3]):
+        O = oracle.Problem(c.d, c.N, c.phi)
+        og = O.ghosts(0)
+        O.set_rhs(c.f, W.points_eval(c.g, og["q"], c.d))
+        cls = O.classes(0)
+        uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+        O.solve(uo, 0.0, st_a.cycles)
+        assert np.abs(uo - u_a).max() <= 1e-12 * np.abs(uo).max()

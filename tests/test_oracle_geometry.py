@@ -124,7 +124,8 @@ def test_rectangle_reduces_to_1d_coefficients(theta, d):
         got = _row_coeffs(P, 0, p, [p, p - 1, p - 2])
         assert np.allclose(got, want, atol=1e-12)
         assert g["eta"][k] == pytest.approx(theta, abs=1e-12)
-        assert g["dtau"][k] == pytest.approx(oracle.dtau(d, theta), rel=1e-12)
+        # dtau_OPT(theta), bounded by the row's Gauss-Seidel step 1/c_0
+        assert g["dtau"][k] == pytest.approx(min(oracle.dtau(d, theta), 1.0 / want[0]), rel=1e-12)
     # and no other entries in such a row: A e_all = sum of the three
     ones = np.ones(P.nodes(0))
     Aone = P.apply_A(0, ones)
@@ -174,7 +175,8 @@ def _grad(phi, I, d, N, h):
 def test_width_selection_reading(case):
     """Each ghost uses the first candidate width vector (entries assigned to
     axes in order of decreasing |grad phi_k|) whose upwind block lies in the
-    box and holds only INSIDE/GHOST nodes."""
+    box, holds only INSIDE/GHOST nodes, and whose row weight on G is at least
+    half of its total |weight| on the other ghosts of the block."""
     if case == "circle65":
         c = W.circle_65()
         d, N, phi = 2, c.N, c.phi
@@ -209,12 +211,33 @@ def test_width_selection_reading(case):
                 if cls[tuple(J[::-1])] not in (oracle.INSIDE, oracle.GHOST):
                     return False
             return True
+        eta, nrm = g["eta"][k], g["n"][k, :d]
+
+        def lag(w, m, t):
+            if w == 1:
+                return 1.0
+            if w == 2:
+                return 1 - t if m == 0 else t
+            return [(1 - t) * (2 - t) / 2, t * (2 - t), t * (t - 1) / 2][m]
+
+        def dominant(wv):
+            # c_0 >= 1/2 of the |weights| on the other ghosts of the block (finest level)
+            tau = [eta * abs(nrm[a]) if wv[a] >= 2 else 0.0 for a in range(d)]
+            c0, off = None, 0.0
+            for m in itertools.product(*[range(wv[a]) for a in range(d)]):
+                wgt = np.prod([lag(wv[a], m[a], tau[a]) for a in range(d)])
+                J = I - np.array(m) * s
+                if not any(m):
+                    c0 = wgt
+                elif cls[tuple(J[::-1])] == oracle.GHOST:
+                    off += abs(wgt)
+            return c0 >= 0.5 * off
         chosen = None
         for cand in CANDS[d]:
             wv = [0] * d
             for r in range(d):
                 wv[order[r]] = cand[r]
-            if valid(wv):
+            if valid(wv) and dominant(wv):
                 chosen = wv
                 break
         assert list(g["w"][k, :d]) == chosen
