@@ -9,11 +9,12 @@ dependent ghost relaxation down to a 5^3 grid, solved from u = 0 to
 before the timed region; setup (classification, ghost geometry, extension
 band, coarse inverse) is done once and reported separately.
 
-A step is one full solve.  After the timed steps the same solves are replayed
-with HIP events recorded around every finest-level red-black sweep (inside
-the replayed graph, on the solver's stream) to get the sweep's average
-duration for the roofline line; the oracle (plain C, FP64) is timed on a
-bounded sample of the same workload for the CPU baseline.
+A step is one full solve (V-cycles replayed from a captured hipGraph).  After
+the timed steps the same solves are run once more as direct launches with HIP
+events recorded around every finest-level red-black sweep on the solver's
+stream (events recorded inside a graph cannot be timed) to get the sweep's
+average duration for the roofline line; the oracle (plain C, FP64) is timed
+on a bounded sample of the same workload for the CPU baseline.
 
 Prints one JSON line.
 """
@@ -38,6 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=256, help="intervals per axis (257^3 nodes by default)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles in the CPU sample")
     return ap.parse_args()
@@ -68,7 +70,7 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    G = Problem(3, N, phi, precision=prec)
+    G = Problem(3, N, phi, precision=prec, max_cycles=args.max_cycles)
     gi = G.ghost_info(0)
     q = gi["q"]
     gq = torch.exp(q[:, 0] + q[:, 1] + q[:, 2])  # Dirichlet data g = exp(x+y+z) at the projections Q
@@ -106,7 +108,7 @@ def main():
     inside = cls == NAT.INSIDE
     err_inf = (u[inside] - ue[inside]).abs().max().item()
 
-    # roofline of the finest-level red-black sweep: HIP events in the replayed graph
+    # roofline of the finest-level red-black sweep: HIP events around each launch
     timing_enable(True)
     n_rep = max(2, min(args.steps, 5))
     for _ in range(n_rep):

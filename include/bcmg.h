@@ -247,9 +247,12 @@ bcmg_status bcmg_problem_bytes(const bcmg_problem *prob, int64_t *bytes);
 
 /* ---- instrumentation ------------------------------------------------------ */
 
-/* When enabled, every launch of the finest-level red-black sweep kernel is
- * bracketed by HIP events on the problem's stream; bcmg_timing_read returns
- * the number of such launches and their summed duration in ms. */
+/* While enabled (process-wide), batch and solve calls launch their cycles
+ * directly instead of replaying a graph, with a HIP event pair around every
+ * launch of the finest-level red-black sweep on the solver's stream;
+ * bcmg_timing_read returns the number of timed launches, their summed
+ * duration in ms and the INSIDE nodes of the finest level swept per launch.
+ * Enabling or disabling resets the counters. */
 bcmg_status bcmg_timing_enable(int32_t on);
 bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *inside_nodes_per_launch);
 

@@ -34,9 +34,10 @@ bcmg_status fail(bcmg_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(BCMG_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// finest-level red-black sweep timing (bcmg_timing_*): event pairs are
-// recorded around the sweep launches when a batch graph is captured, so every
-// replay re-records them; their durations are summed after each replay.
+// finest-level red-black sweep timing (bcmg_timing_*): while enabled, batches
+// launch their cycles directly (no graph: events recorded during capture
+// cannot be timed) with an event pair around every finest-level sweep; the
+// durations are summed after each synchronised step.
 struct Timing {
     bool on = false;
     long long launches = 0;
@@ -134,15 +135,14 @@ struct bcmg_batch {
     std::vector<Lists> lv;
     Item *fsegs = nullptr, *fgch = nullptr;
     int nfseg = 0, nfgch = 0;
-    std::vector<int> sing_slots;  // slots whose coarsest level is singular
-    Item *ssegs = nullptr, *sgch = nullptr;
-    int nsseg = 0, nsgch = 0;
+    int Ac = 0;                    // aligned levels 0..Ac run in the per-problem coarse workgroup
+    CoarseProg *d_progs = nullptr;
+    int nprog = 0;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_cycles = 0;
-    bool graph_timed = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // timing events recorded by the graph
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // timing events of direct launches
 };
 
 namespace {
@@ -790,6 +790,7 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
     hipFree(b->d_eptr);
     hipFree(b->d_items);
     hipFree(b->d_coarse);
+    hipFree(b->d_progs);
     hipFree(b->d_partials);
     if (b->join) hipEventDestroy(b->join);
     if (b->stream) hipStreamDestroy(b->stream);
@@ -894,24 +895,47 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     }
     const int nfgch = (int)(items.size() - fgch0);
     std::vector<int> coarse;
-    b->sing_slots.clear();
     b->fine_inside = 0;
     for (int s = 0; s < b->cap; s++)
         if (b->prob[s]) {
             coarse.push_back(base[s] + b->prob[s]->L - 1);
-            if (b->prob[s]->lev[b->prob[s]->L - 1].singular) b->sing_slots.push_back(s);
             if (b->prob[s]->L == A) b->fine_inside += b->prob[s]->lev[0].ni;
         }
-    // coarsest levels of slots whose coarse matrix is singular: smoothed instead
-    const size_t sseg0 = items.size();
-    for (int s : b->sing_slots) add_segs(base[s] + b->prob[s]->L - 1, b->prob[s]->lev[b->prob[s]->L - 1]);
-    const int nsseg = (int)(items.size() - sseg0);
-    const size_t sgch0 = items.size();
-    for (int s : b->sing_slots) {
-        const int l = b->prob[s]->L - 1;
-        append_chunks(items, base[s] + l, b->prob[s]->lev[l].ng);
+    // aligned level a has N = 4 * 2^a on every problem: levels with at most
+    // kCoarseNodes nodes are cycled by one workgroup per problem
+    int Ac = 0;
+    for (int a2 = 0; a2 < kMaxLevels; a2++) {
+        long long nn = 1;
+        for (int k = 0; k < b->d; k++) nn *= (4LL << a2) + 1;
+        if (nn > kCoarseNodes) break;
+        Ac = a2;
     }
-    const int nsgch = (int)(items.size() - sgch0);
+    b->Ac = Ac;
+    std::vector<CoarseProg> progs;
+    for (int s = 0; s < b->cap; s++) {
+        bcmg_problem *P = b->prob[s];
+        if (!P) continue;
+        CoarseProg cp;
+        memset(&cp, 0, sizeof cp);
+        cp.slot = s;
+        cp.top = std::min(Ac, P->L - 1);
+        for (int a2 = 0; a2 <= cp.top; a2++) {
+            const int l = P->L - 1 - a2;
+            const LevelH &V = P->lev[l];
+            CoarseLevel &cl = cp.lev[a2];
+            cl.desc = base[s] + l;
+            cl.seg = (int)items.size();
+            add_segs(cl.desc, V);
+            cl.nseg = (int)items.size() - cl.seg;
+            cl.gch = (int)items.size();
+            append_chunks(items, cl.desc, V.ng);
+            cl.ngch = (int)items.size() - cl.gch;
+            cl.bch = (int)items.size();
+            append_chunks(items, cl.desc, V.nb);
+            cl.nbch = (int)items.size() - cl.bch;
+        }
+        progs.push_back(cp);
+    }
     // upload
     hipStream_t st = b->stream;
     if (descs.size() > b->desc_cap) {
@@ -926,6 +950,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     }
     hipFree(b->d_coarse);
     HIPCHK(hipMalloc((void **)&b->d_coarse, sizeof(int) * (coarse.size() + 1)));
+    hipFree(b->d_progs);
+    HIPCHK(hipMalloc((void **)&b->d_progs, sizeof(CoarseProg) * (progs.size() + 1)));
     const size_t np = (size_t)nfseg + nfgch + 1;
     if (np > b->partials_cap) {
         hipFree(b->d_partials);
@@ -942,6 +968,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipMemcpyAsync(b->d_outer, outer.data(), sizeof(Desc) * b->cap, hipMemcpyHostToDevice, cs));
     HIPCHK(hipMemcpyAsync(b->d_eptr, eptr.data(), sizeof(float *) * b->cap, hipMemcpyHostToDevice, cs));
     HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), sizeof(NormRange) * b->cap, hipMemcpyHostToDevice, cs));
+    if (!progs.empty())
+        HIPCHK(hipMemcpyAsync(b->d_progs, progs.data(), sizeof(CoarseProg) * progs.size(), hipMemcpyHostToDevice, cs));
     HIPCHK(hipStreamSynchronize(cs));
     b->lv.assign(A, Lists());
     for (int a = 0; a < A; a++) {
@@ -963,17 +991,14 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     b->fgch = b->d_items + fgch0;
     b->nfgch = nfgch;
     b->ncoarse = (int)coarse.size();
-    b->ssegs = b->d_items + sseg0;
-    b->nsseg = nsseg;
-    b->sgch = b->d_items + sgch0;
-    b->nsgch = nsgch;
+    b->nprog = (int)progs.size();
     b->dirty = false;
     return BCMG_OK;
 }
 
 static void timed_sweep(bcmg_batch *b, int a, int colour) {
     const Lists &L = b->lv[a];
-    const bool fine = b->graph_timed && a == b->A - 1;
+    const bool fine = g_timing.on && a == b->A - 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (fine) {
         hipEventCreate(&e0);
@@ -998,7 +1023,7 @@ static void smooth(bcmg_batch *b, int a) {
 static void launch_vcycle(bcmg_batch *b) {
     const int d = b->d, f = b->fp32;
     hipStream_t s = b->stream;
-    for (int a = b->A - 1; a >= 1; a--) {
+    for (int a = b->A - 1; a > b->Ac; a--) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
         for (int i = 0; i < b->nu1; i++) smooth(b, a);
@@ -1006,14 +1031,8 @@ static void launch_vcycle(bcmg_batch *b) {
         launch_extend(d, f, b->d_desc, L.bch, L.nbch, 1, b->K, b->d_state, s);
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, b->d_state, s);
     }
-    launch_coarse(f, b->d_desc, b->d_coarse, b->ncoarse, b->d_state, s);
-    for (int i = 0; i < 50 && !b->sing_slots.empty(); i++) {
-        // singular coarsest matrices: 50 smoothing steps instead of the exact solve
-        launch_rb_sweep(d, f, b->d_desc, b->ssegs, b->nsseg, 0, b->d_state, s);
-        launch_rb_sweep(d, f, b->d_desc, b->ssegs, b->nsseg, 1, b->d_state, s);
-        launch_ghost_relax(d, f, b->d_desc, b->sgch, b->nsgch, b->d_state, s);
-    }
-    for (int a = 1; a < b->A; a++) {
+    launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, b->K, s);
+    for (int a = b->Ac + 1; a < b->A; a++) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
         launch_extend(d, f, b->d_desc, L.cbch, L.ncbch, 0, b->K, b->d_state, s);
@@ -1111,9 +1130,13 @@ static bcmg_status batch_launch_cycles(bcmg_batch *b, int cycles) {
         bcmg_status st = batch_rebuild(b);
         if (st) return st;
     }
-    if (!b->exec || b->graph_cycles != cycles || b->graph_timed != g_timing.on) {
+    if (g_timing.on) {
+        for (int c = 0; c < cycles; c++) launch_cycle(b);
+        HIPCHK(hipGetLastError());
+        return BCMG_OK;
+    }
+    if (!b->exec || b->graph_cycles != cycles) {
         drop_graph(b);
-        b->graph_timed = g_timing.on;
         HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < cycles; c++) launch_cycle(b);
         hipError_t e = hipStreamEndCapture(b->stream, &b->graph);
@@ -1133,13 +1156,17 @@ bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host)
     if (st) return st;
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState) * b->cap, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    if (b->graph_timed) {
+    if (!b->tev.empty()) {
         for (auto &pr : b->tev) {
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            hipError_t e = hipEventElapsedTime(&ms, pr.first, pr.second);
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+            if (e != hipSuccess) continue;
             g_timing.ms += ms;
             g_timing.launches++;
         }
+        b->tev.clear();
         g_timing.nodes = b->fine_inside;
     }
     if (active_host)

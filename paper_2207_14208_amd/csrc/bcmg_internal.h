@@ -19,13 +19,15 @@ namespace bcmg {
 enum : uint8_t { C_OUTSIDE = 0, C_INSIDE = 1, C_GHOST = 2, C_BOXDIR = 3 };
 
 constexpr int kMaxLevels = 16;
-constexpr int kSegLen = 64;     // nodes per row segment = one wavefront
+constexpr int kSegLen = 128;    // nodes per row segment = one wavefront (two per lane)
 constexpr int kChunk = 256;     // ghost / band entries per chunk = one workgroup
 constexpr int kBlock = 256;     // threads per workgroup
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kRefZero = INT32_MIN;       // band reference to a node whose value is 0
 constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
 constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
+// levels with at most this many nodes are cycled by one workgroup per problem
+constexpr long long kCoarseNodes = 1200;
 
 // Work item over a row segment: desc, first node, x0 | len << 16, j | k << 16.
 // Ghost / band chunk: desc, first entry, count, unused.
@@ -66,6 +68,18 @@ struct alignas(16) SlotState {
     double tolsq;   // (rel_tol * ||r^0||)^2
     double refsq;   // max(||r^0||^2, ||r^1||^2): divergence reference
     double lastsq;  // latest ||r||^2
+};
+
+// Work of one level inside the per-problem coarse workgroup: ranges in the
+// batch's item array (segments, ghost chunks, band chunks) and its descriptor.
+struct CoarseLevel {
+    int seg, nseg, gch, ngch, bch, nbch, desc, pad;
+};
+
+// The aligned levels 0..top of one problem (0 = coarsest) run by k_coarse_cycle.
+struct alignas(16) CoarseProg {
+    int slot, top, pad0, pad1;
+    CoarseLevel lev[kMaxLevels];
 };
 
 // Per-slot ranges of the partial sums written by a finest-level residual.

@@ -4,24 +4,37 @@
 // and reads its level descriptor from a table, so the same kernels serve a
 // single problem and a batch of problems of different sizes.
 //
-// Row-segment kernels: one wavefront per segment of <= 64 consecutive nodes
-// of a grid row (coalesced 64 x 8 B accesses); chunk kernels: one workgroup
-// per <= 256 ghost or band entries.
+// Row segments hold up to 128 consecutive nodes of a grid row and are
+// processed by one wavefront (two nodes per lane, or for a red-black sweep the
+// 64 nodes of one colour, one per lane); ghost and band chunks hold up to 256
+// entries, one per thread.  Every gather issues all of its loads before it
+// tests classes (neighbour indices are clamped into the array), so a
+// wavefront waits for memory once per node instead of once per load.
+//
+// The small coarse levels of a problem are cycled by one workgroup of 512
+// threads per problem (k_coarse_cycle) with workgroup barriers between the
+// steps, which replaces a dozen dependent launches per level.
 #include "bcmg_internal.h"
 #include "launch.h"
 
 namespace bcmg {
 
-#define SEG_PROLOGUE                                                  \
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;       \
-    const int sidx = blockIdx.x * kWavesPerBlock + wave;              \
-    if (sidx >= nseg) return;                                         \
-    const Item it = items[sidx];                                      \
-    const Desc &L = descs[it.x];                                      \
-    if (!st[L.slot].active) return;                                   \
-    const int len = it.z >> 16, x0 = it.z & 0xffff;                   \
-    const int yj = it.w & 0xffff, zk = it.w >> 16;                    \
-    const long long p = (long long)it.y + lane;
+struct Seg {
+    long long p0;  // first node
+    int len, x0, yj, zk;
+};
+
+__device__ __forceinline__ Seg seg_of(const Item &it) {
+    Seg s;
+    s.p0 = it.y;
+    s.len = it.z >> 16;
+    s.x0 = it.z & 0xffff;
+    s.yj = it.w & 0xffff;
+    s.zk = it.w >> 16;
+    return s;
+}
+
+__device__ __forceinline__ long long clampi(long long q, long long nn) { return q < 0 ? 0 : (q >= nn ? nn - 1 : q); }
 
 __device__ __forceinline__ double lagrange(int w, int m, double t) {
     if (w == 1) return 1.0;
@@ -32,7 +45,9 @@ __device__ __forceinline__ double lagrange(int w, int m, double t) {
 }
 
 // sum_m w_m u(G - m o s) of ghost g (eq. BCh, Dirichlet), tensor-product
-// Lagrange weights of widths w_k at the local coordinates tau_k of Q.
+// Lagrange weights of widths w_k at the local coordinates tau_k of Q.  The
+// 3^d candidate nodes are loaded first (nodes outside the stencil read G
+// itself), then accumulated in lexicographic order of m.
 template <int D, typename T>
 __device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__restrict__ u) {
     const long long p = L.gidx[g];
@@ -49,97 +64,411 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__res
 #pragma unroll
         for (int m = 0; m < 3; m++) la[k][m] = lagrange(w[k], m, t);
     }
+    constexpr int M1 = D >= 2 ? 3 : 1, M2 = D >= 3 ? 3 : 1;
+    double val[M2][M1][3];
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+            for (int m0 = 0; m0 < 3; m0++) {
+                const bool in = m0 < w[0] && m1 < w[1] && m2 < w[2];
+                const long long q = in ? p - m0 * step[0] - m1 * step[1] - m2 * step[2] : p;
+                val[m2][m1][m0] = (double)u[q];
+            }
     double acc = 0.0;
-    for (int m2 = 0; m2 < w[2]; m2++)
-        for (int m1 = 0; m1 < w[1]; m1++)
-            for (int m0 = 0; m0 < w[0]; m0++) {
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+            for (int m0 = 0; m0 < 3; m0++) {
+                if (!(m0 < w[0] && m1 < w[1] && m2 < w[2])) continue;
                 double wgt = 1.0;
                 wgt *= la[0][m0];
                 wgt *= la[1][m1];
                 wgt *= la[2][m2];
-                acc += wgt * (double)u[p - m0 * step[0] - m1 * step[1] - m2 * step[2]];
+                acc += wgt * val[m2][m1][m0];
             }
     return acc;
 }
 
-// --------------------------------------------------------------------------
-// Interior Gauss-Seidel, one colour (red: i+j+k even).  eq. GSLEX_2D in
-// red-black order: u_P = (h^2 f_P + sum of the 2d neighbours) / (2d).
+// ------------------------------------------------------------ node updates
+// Interior Gauss-Seidel on the nodes of one colour of a segment (red:
+// i+j+k even), one node per lane.  eq. GSLEX_2D in red-black order:
+// u_P = (h^2 f_P + sum of the 2d neighbours) / (2d).
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void k_rb_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
-                                                     int nseg, int colour, const SlotState *__restrict__ st) {
-    SEG_PROLOGUE
-    if (lane >= len) return;
-    if (((x0 + lane + yj + zk) & 1) != colour) return;
-    if (L.cls[p] != C_INSIDE) return;
+__device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, int colour) {
+    const Seg s = seg_of(it);
+    const int q = (((s.x0 + s.yj + s.zk) & 1) == colour ? 0 : 1) + 2 * lane;
+    if (q >= s.len) return;
+    const long long p = s.p0 + q;
     T *__restrict__ u = (T *)L.u;
     const T *__restrict__ f = (const T *)L.rhs;
-    T s = u[p + 1] + u[p - 1];
-    if (D >= 2) s += u[p + L.sy] + u[p - L.sy];
-    if (D >= 3) s += u[p + L.sz] + u[p - L.sz];
-    u[p] = ((T)L.h2 * f[p] + s) / (T)(2 * D);
+    const long long nn = L.nn;
+    const uint8_t c = L.cls[p];
+    const T fp = f[p];
+    const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
+    T ym = 0, yp = 0, zm = 0, zp = 0;
+    if (D >= 2) {
+        ym = u[clampi(p - L.sy, nn)];
+        yp = u[clampi(p + L.sy, nn)];
+    }
+    if (D >= 3) {
+        zm = u[clampi(p - L.sz, nn)];
+        zp = u[clampi(p + L.sz, nn)];
+    }
+    T sum = xp + xm;
+    if (D >= 2) sum += yp + ym;
+    if (D >= 3) sum += zp + zm;
+    if (c != C_INSIDE) return;
+    u[p] = ((T)L.h2 * fp + sum) / (T)(2 * D);
 }
 
-// Ghost relaxation, first half: increments from the current values (eq. rel
-// with P_GG = I/dtau: new interior values, old ghost values).
+// Residual of the INSIDE rows of a segment (two nodes per lane); returns the
+// lane's sum of r^2.
+template <int D, typename Tu, typename Tr>
+__device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane) {
+    const Seg s = seg_of(it);
+    double r2 = 0.0;
+    const Tu *__restrict__ u = (const Tu *)L.u;
+    const Tu *__restrict__ f = (const Tu *)L.rhs;
+    const long long nn = L.nn;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = lane + 64 * h;
+        if (q >= s.len) continue;
+        const long long p = s.p0 + q;
+        const uint8_t c = L.cls[p];
+        const double up = (double)u[p], fp = (double)f[p];
+        const double xm = (double)u[clampi(p - 1, nn)], xp = (double)u[clampi(p + 1, nn)];
+        double ym = 0, yp = 0, zm = 0, zp = 0;
+        if (D >= 2) {
+            ym = (double)u[clampi(p - L.sy, nn)];
+            yp = (double)u[clampi(p + L.sy, nn)];
+        }
+        if (D >= 3) {
+            zm = (double)u[clampi(p - L.sz, nn)];
+            zp = (double)u[clampi(p + L.sz, nn)];
+        }
+        if (c != C_INSIDE) continue;
+        double sum = xp + xm;
+        if (D >= 2) sum += yp + ym;
+        if (D >= 3) sum += zp + zm;
+        const double lap = (2.0 * D * up - sum) / L.h2;
+        const double r = fp - lap;
+        ((Tr *)L.r)[p] = (Tr)r;
+        r2 += r * r;
+    }
+    return r2;
+}
+
+// Restriction to one coarse node (fine level F, coarse level C): coarse
+// INSIDE: FW over the 3^d fine box around X = 2J if all of it is INSIDE,
+// else the FW weights of its INSIDE nodes renormalised; coarse GHOST: FW of
+// the extended residual if the box holds no INSIDE node and lies in the
+// grid, else renormalised over its non-INSIDE, non-BOXDIR nodes (eq.
+// coarseFW, Sec. 2.2 FW, Sec. 2.3).  Also zeroes the coarse unknown (initial
+// guess of the coarse correction).
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__ descs,
-                                                        const Item *__restrict__ items,
-                                                        const SlotState *__restrict__ st) {
-    const Item it = items[blockIdx.x];
-    const Desc &L = descs[it.x];
-    if (!st[L.slot].active) return;
-    if ((int)threadIdx.x >= it.z) return;
-    const int g = it.y + threadIdx.x;
+__device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2) {
+    constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
+    const T *__restrict__ r = (const T *)F.r;
+    uint8_t fc[2 * R2 + 1][2 * R1 + 1][3];
+    double rv[2 * R2 + 1][2 * R1 + 1][3];
+    bool inb[2 * R2 + 1][2 * R1 + 1][3];
+    const long long pf = X0 + X1 * F.sy + X2 * F.sz;
+#pragma unroll
+    for (int m2 = -R2; m2 <= R2; m2++)
+#pragma unroll
+        for (int m1 = -R1; m1 <= R1; m1++)
+#pragma unroll
+            for (int m0 = -1; m0 <= 1; m0++) {
+                const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
+                const bool in = J0 >= 0 && J0 <= F.N && (D < 2 || (J1 >= 0 && J1 <= F.N)) &&
+                                (D < 3 || (J2 >= 0 && J2 <= F.N));
+                const long long q = in ? pf + m0 + m1 * F.sy + m2 * F.sz : pf;
+                inb[m2 + R2][m1 + R1][m0 + 1] = in;
+                fc[m2 + R2][m1 + R1][m0 + 1] = F.cls[q];
+                rv[m2 + R2][m1 + R1][m0 + 1] = (double)r[q];
+            }
+    const uint8_t cc = C.cls[pc];
+    if (cc != C_INSIDE && cc != C_GHOST) return;
+    ((T *)C.u)[pc] = (T)0;
+    double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
+    bool all_ok = true;
+#pragma unroll
+    for (int m2 = -R2; m2 <= R2; m2++)
+#pragma unroll
+        for (int m1 = -R1; m1 <= R1; m1++)
+#pragma unroll
+            for (int m0 = -1; m0 <= 1; m0++) {
+                double wgt = 1.0;
+                wgt *= (m0 == 0 ? 0.5 : 0.25);
+                if (D >= 2) wgt *= (m1 == 0 ? 0.5 : 0.25);
+                if (D >= 3) wgt *= (m2 == 0 ? 0.5 : 0.25);
+                if (!inb[m2 + R2][m1 + R1][m0 + 1]) {
+                    all_ok = false;
+                    continue;
+                }
+                const uint8_t c = fc[m2 + R2][m1 + R1][m0 + 1];
+                bool take;
+                if (cc == C_INSIDE) {
+                    take = c == C_INSIDE;
+                    if (!take) all_ok = false;
+                } else {
+                    take = c != C_INSIDE && c != C_BOXDIR;
+                    if (c == C_INSIDE) all_ok = false;
+                }
+                const double v = rv[m2 + R2][m1 + R1][m0 + 1];
+                full += wgt * v;
+                if (take) {
+                    sel += wgt * v;
+                    selw += wgt;
+                    msum += v;
+                    mcnt += 1.0;
+                }
+            }
+    double out;
+    if (all_ok)
+        out = full;
+    else if (C.restrict_mode == BCMG_RESTRICT_PLAIN_MEAN)
+        out = mcnt > 0.0 ? msum / mcnt : 0.0;
+    else
+        out = selw > 0.0 ? sel / selw : 0.0;
+    ((T *)C.rhs)[pc] = (T)out;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane) {
+    const Seg s = seg_of(it);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = lane + 64 * h;
+        if (q >= s.len) continue;
+        restrict_node<D, T>(C, F, s.p0 + q, 2 * (s.x0 + q), 2 * s.yj, 2 * s.zk);
+    }
+}
+
+// Prolongation and correction: multilinear interpolation of the (extended)
+// coarse error to INSIDE and GHOST nodes, u += e (Sec. 1.1 interpolation,
+// Sec. 2.2 bilinear interpolation, Sec. 2.3).
+template <int D, typename T>
+__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2) {
+    const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
+    const int B0 = (I0 - h0) / 2, B1 = (I1 - h1) / 2, B2 = (I2 - h2) / 2;
+    const T *__restrict__ ec = (const T *)C.u;
+    constexpr int M1 = D >= 2 ? 2 : 1, M2 = D >= 3 ? 2 : 1;
+    double ev[M2][M1][2];
+    const long long b = B0 + B1 * C.sy + B2 * C.sz;
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+            for (int m0 = 0; m0 < 2; m0++) {
+                const bool in = m0 <= h0 && m1 <= h1 && m2 <= h2;
+                ev[m2][m1][m0] = (double)ec[in ? b + m0 + m1 * C.sy + m2 * C.sz : b];
+            }
+    T *u = (T *)F.u;
+    const uint8_t fc = F.cls[p];
+    const double up = (double)u[p];
+    if (fc != C_INSIDE && fc != C_GHOST) return;
+    double e = 0.0;
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+            for (int m0 = 0; m0 < 2; m0++) {
+                if (!(m0 <= h0 && m1 <= h1 && m2 <= h2)) continue;
+                double wgt = 1.0;
+                if (h0) wgt *= 0.5;
+                if (h1) wgt *= 0.5;
+                if (h2) wgt *= 0.5;
+                e += wgt * ev[m2][m1][m0];
+            }
+    u[p] = (T)(up + e);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane) {
+    const Seg s = seg_of(it);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = lane + 64 * h;
+        if (q >= s.len) continue;
+        prolong_node<D, T>(F, C, s.p0 + q, s.x0 + q, s.yj, s.zk);
+    }
+}
+
+// Ghost relaxation (eq. rel with P_GG = I/dtau: new interior values, old ghost
+// values): increment, then u_G += increment in a second pass.
+template <int D, typename T>
+__device__ __forceinline__ void ghost_delta(const Desc &L, int g) {
     const T *u = (const T *)L.u;
     const T *rhs = (const T *)L.rhs;
+    const double rg = (double)rhs[L.gidx[g]];
     const double row = ghost_row<D, T>(L, g, u);
-    L.gdelta[g] = L.gdtau[g] * ((double)rhs[L.gidx[g]] - row);
+    L.gdelta[g] = L.gdtau[g] * (rg - row);
 }
 
-// Ghost relaxation, second half: u_G += increment.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__ descs,
-                                                        const Item *__restrict__ items,
-                                                        const SlotState *__restrict__ st) {
-    const Item it = items[blockIdx.x];
-    const Desc &L = descs[it.x];
-    if (!st[L.slot].active) return;
-    if ((int)threadIdx.x >= it.z) return;
-    const int g = it.y + threadIdx.x;
+__device__ __forceinline__ void ghost_apply(const Desc &L, int g) {
     T *u = (T *)L.u;
     const long long p = L.gidx[g];
     u[p] = (T)((double)u[p] + L.gdelta[g]);
 }
 
-// --------------------------------------------------------------------------
-// Residual r = rhs - A u on INSIDE rows (segment blocks) and GHOST rows (chunk
-// blocks), optionally with partial sums of r^2 in a fixed order: one partial
-// per segment wavefront, then one per ghost chunk.
+template <int D, typename Tu, typename Tr>
+__device__ __forceinline__ double ghost_residual(const Desc &L, int g) {
+    const long long pg = L.gidx[g];
+    const double rg = (double)((const Tu *)L.rhs)[pg];
+    const double r = rg - ghost_row<D, Tu>(L, g, (const Tu *)L.u);
+    ((Tr *)L.r)[pg] = (Tr)r;
+    return r * r;
+}
+
+// Normal extension, one Jacobi sweep at band node b: v(X) = sum_k |n_k|
+// v(X - s_k e_k) / sum_k |n_k| (Sec. 2.3 transfer operators).  Sweep j of K
+// reads the band values of sweep j-1 (0 for j = 1) from a ping-pong buffer
+// and writes the other one; the last sweep writes the field itself.  GHOST
+// references read the fixed field, BOXDIR and beyond-band references are 0;
+// a zero weight sum gives the mean of the GHOST nodes of the 3^d box.
+template <int D, typename T>
+__device__ double ext_fallback(const Desc &L, const T *field, int b) {
+    long long x = L.bidx[b];
+    int I[3] = {0, 0, 0};
+    for (int k = 0; k < D; k++) {
+        I[k] = (int)(x % L.n);
+        x /= L.n;
+    }
+    double sum = 0.0;
+    int cnt = 0;
+    const int lo2 = D >= 3 ? -1 : 0, hi2 = D >= 3 ? 1 : 0, lo1 = D >= 2 ? -1 : 0, hi1 = D >= 2 ? 1 : 0;
+    for (int m2 = lo2; m2 <= hi2; m2++)
+        for (int m1 = lo1; m1 <= hi1; m1++)
+            for (int m0 = -1; m0 <= 1; m0++) {
+                const int J0 = I[0] + m0, J1 = I[1] + m1, J2 = I[2] + m2;
+                if (J0 < 0 || J0 > L.N || (D >= 2 && (J1 < 0 || J1 > L.N)) || (D >= 3 && (J2 < 0 || J2 > L.N)))
+                    continue;
+                const long long q = J0 + J1 * L.sy + J2 * L.sz;
+                if (L.cls[q] == C_GHOST) {
+                    sum += (double)field[q];
+                    cnt++;
+                }
+            }
+    return cnt > 0 ? sum / cnt : 0.0;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void ext_sweep_node(const Desc &L, int which, int j, int K, int b) {
+    T *field = (T *)(which ? L.r : L.u);
+    const T *prev = (const T *)((j & 1) ? L.bufB : L.bufA);  // written by sweep j-1
+    T *next = (T *)((j & 1) ? L.bufA : L.bufB);
+    const int r0 = L.bref[3 * b];
+    double v;
+    if (r0 == kRefFallback) {
+        v = ext_fallback<D, T>(L, field, b);
+    } else {
+        double val[3], wk[3];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const int ref = L.bref[3 * b + k];
+            wk[k] = L.bw[3 * b + k];
+            if (ref >= 0)
+                val[k] = j >= 2 ? (double)prev[ref] : 0.0;
+            else if (ref == kRefZero)
+                val[k] = 0.0;
+            else
+                val[k] = (double)field[-(long long)ref - 1];
+        }
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            num += wk[k] * val[k];
+            den += wk[k];
+        }
+        v = den > 0.0 ? num / den : 0.0;
+    }
+    if (j == K)
+        field[L.bidx[b]] = (T)v;
+    else
+        next[b] = (T)v;
+}
+
+// Coarsest level: x = A^{-1} b over INSIDE then GHOST unknowns, in FP64, by
+// the threads of one workgroup (b staged in LDS).
+template <typename T>
+__device__ void coarse_solve_block(const Desc &L, double *b) {
+    const int nc = L.nc;
+    const T *rhs = (const T *)L.rhs;
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) b[t] = (double)rhs[L.cmap[t]];
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        double x = 0.0;
+        const double *row = L.ainv + (long long)t * nc;
+        for (int j = 0; j < nc; j++) x += row[j] * b[j];
+        ((T *)L.u)[L.cmap[t]] = (T)x;
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- kernels
+#define SEG_ITEM                                                  \
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   \
+    const int sidx = blockIdx.x * kWavesPerBlock + wave;          \
+    if (sidx >= nseg) return;                                     \
+    const Item it = items[sidx];                                  \
+    const Desc &L = descs[it.x];                                  \
+    if (!st[L.slot].active) return;
+
+#define CHUNK_ITEM                                                \
+    const Item it = items[blockIdx.x];                            \
+    const Desc &L = descs[it.x];                                  \
+    if (!st[L.slot].active) return;                               \
+    if ((int)threadIdx.x >= it.z) return;                         \
+    const int e = it.y + threadIdx.x;
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_rb_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
+                                                     int nseg, int colour, const SlotState *__restrict__ st) {
+    SEG_ITEM
+    seg_rb<D, T>(L, it, lane, colour);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__ descs,
+                                                        const Item *__restrict__ items,
+                                                        const SlotState *__restrict__ st) {
+    CHUNK_ITEM
+    ghost_delta<D, T>(L, e);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__ descs,
+                                                        const Item *__restrict__ items,
+                                                        const SlotState *__restrict__ st) {
+    CHUNK_ITEM
+    ghost_apply<T>(L, e);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
+// Residual on INSIDE rows (segment blocks) and GHOST rows (chunk blocks);
+// with NORM, one partial sum of r^2 per segment, then one per ghost chunk,
+// each reduced in a fixed order.
 template <int D, typename Tu, typename Tr, bool NORM>
 __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st, double *__restrict__ partials) {
     if ((int)blockIdx.x < nseg_blocks) {
-        SEG_PROLOGUE
-        double r2 = 0.0;
-        if (lane < len && L.cls[p] == C_INSIDE) {
-            const Tu *__restrict__ u = (const Tu *)L.u;
-            const Tu *__restrict__ f = (const Tu *)L.rhs;
-            double s = (double)u[p + 1] + (double)u[p - 1];
-            if (D >= 2) s += (double)u[p + L.sy] + (double)u[p - L.sy];
-            if (D >= 3) s += (double)u[p + L.sz] + (double)u[p - L.sz];
-            const double lap = (2.0 * D * (double)u[p] - s) / L.h2;
-            const double r = (double)f[p] - lap;
-            ((Tr *)L.r)[p] = (Tr)r;
-            r2 = r * r;
-        }
+        SEG_ITEM
+        double r2 = seg_residual<D, Tu, Tr>(L, it, lane);
         if (NORM) {
             r2 = wave_sum(r2);
             if (lane == 0) partials[sidx] = r2;
@@ -151,13 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     const Desc &L = descs[it.x];
     if (!st[L.slot].active) return;
     double r2 = 0.0;
-    if ((int)threadIdx.x < it.z) {
-        const int g = it.y + threadIdx.x;
-        const long long pg = L.gidx[g];
-        const double r = (double)((const Tu *)L.rhs)[pg] - ghost_row<D, Tu>(L, g, (const Tu *)L.u);
-        ((Tr *)L.r)[pg] = (Tr)r;
-        r2 = r * r;
-    }
+    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr>(L, it.y + threadIdx.x);
     if (NORM) {
         __shared__ double ws[kWavesPerBlock];
         r2 = wave_sum(r2);
@@ -171,27 +494,30 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     }
 }
 
-// Per-slot sum of the partials in a fixed order, then the convergence test.
-// mode 0: ||r^0|| (start of a solve); mode 1: after a cycle; mode 2: only
-// store the norm (residual query).
-__global__ __launch_bounds__(kBlock) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
-                                                        const double *__restrict__ partials, int nseg_total,
-                                                        SlotState *__restrict__ st, const double *__restrict__ rtol2,
-                                                        double *__restrict__ hist, int hist_stride, int mode,
-                                                        double *__restrict__ out) {
+// Per-slot sum of the partials in a fixed order (each thread a contiguous
+// run, then a tree), then the convergence test.  mode 0: ||r^0|| of slots
+// waiting for it; mode 1: after a cycle; mode 2: only store the norm.
+constexpr int kNormThreads = 1024;
+__global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
+                                                              const double *__restrict__ partials, int nseg_total,
+                                                              SlotState *__restrict__ st,
+                                                              const double *__restrict__ rtol2,
+                                                              double *__restrict__ hist, int hist_stride, int mode,
+                                                              double *__restrict__ out) {
     const int s = blockIdx.x;
     if (s >= nslots) return;
     if (mode == 1 && st[s].active != 1) return;
-    if (mode == 0 && st[s].active != 2) return;  // only slots waiting for ||r^0||
+    if (mode == 0 && st[s].active != 2) return;
     const NormRange R = ranges[s];
-    const int nA = R.seg_end - R.seg_beg, nB = R.gch_end - R.gch_beg;
+    const int nA = R.seg_end - R.seg_beg, nB = R.gch_end - R.gch_beg, n = nA + nB;
+    const int per = (n + kNormThreads - 1) / kNormThreads;
+    const int beg = threadIdx.x * per, end = min(n, beg + per);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nA + nB; i += kBlock)
-        acc += i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
-    __shared__ double red[kBlock];
+    for (int i = beg; i < end; i++) acc += i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
+    __shared__ double red[kNormThreads];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -229,239 +555,186 @@ __global__ __launch_bounds__(kBlock) void k_norm_finish(const NormRange *__restr
     }
 }
 
-// --------------------------------------------------------------------------
-// Normal extension, one Jacobi sweep over the band: v(X) = sum_k |n_k|
-// v(X - s_k e_k) / sum_k |n_k| (Sec. 2.3 transfer operators).  Sweep j of K
-// reads the band values of sweep j-1 (0 for j = 1) and writes a ping-pong
-// buffer, the last sweep writes the field itself.
+// One extension sweep over the band chunks.
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_ext_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                       int which, int j, int K, const SlotState *__restrict__ st) {
-    const Item it = items[blockIdx.x];
-    const Desc &L = descs[it.x];
-    if (!st[L.slot].active) return;
-    if ((int)threadIdx.x >= it.z) return;
-    const int b = it.y + threadIdx.x;
-    T *field = (T *)(which ? L.r : L.u);
-    const T *prev = (const T *)((j & 1) ? L.bufB : L.bufA);  // written by sweep j-1
-    T *next = (T *)((j & 1) ? L.bufA : L.bufB);
-    const int r0 = L.bref[3 * b];
-    double v;
-    if (r0 == kRefFallback) {
-        // zero weight sum: mean of the GHOST nodes of the 3^d box
-        long long x = L.bidx[b];
-        int I[3] = {0, 0, 0};
-        for (int k = 0; k < D; k++) {
-            I[k] = (int)(x % L.n);
-            x /= L.n;
-        }
-        double sum = 0.0;
-        int cnt = 0;
-        const int lo2 = D >= 3 ? -1 : 0, hi2 = D >= 3 ? 1 : 0, lo1 = D >= 2 ? -1 : 0, hi1 = D >= 2 ? 1 : 0;
-        for (int m2 = lo2; m2 <= hi2; m2++)
-            for (int m1 = lo1; m1 <= hi1; m1++)
-                for (int m0 = -1; m0 <= 1; m0++) {
-                    const int J0 = I[0] + m0, J1 = I[1] + m1, J2 = I[2] + m2;
-                    if (J0 < 0 || J0 > L.N || (D >= 2 && (J1 < 0 || J1 > L.N)) || (D >= 3 && (J2 < 0 || J2 > L.N)))
-                        continue;
-                    const long long q = J0 + J1 * L.sy + J2 * L.sz;
-                    if (L.cls[q] == C_GHOST) {
-                        sum += (double)field[q];
-                        cnt++;
-                    }
-                }
-        v = cnt > 0 ? sum / cnt : 0.0;
-    } else {
-        double num = 0.0, den = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            const int ref = L.bref[3 * b + k];
-            const double wk = L.bw[3 * b + k];
-            double val;
-            if (ref >= 0)
-                val = j >= 2 ? (double)prev[ref] : 0.0;
-            else if (ref == kRefZero)
-                val = 0.0;
-            else
-                val = (double)field[-(long long)ref - 1];
-            num += wk * val;
-            den += wk;
-        }
-        v = den > 0.0 ? num / den : 0.0;
-    }
-    if (j == K)
-        field[L.bidx[b]] = (T)v;
-    else
-        next[b] = (T)v;
+    CHUNK_ITEM
+    ext_sweep_node<D, T>(L, which, j, K, e);
 }
 
-// --------------------------------------------------------------------------
-// Restriction to the coarse level of the item (fine level = descriptor - 1):
-// coarse INSIDE: FW over the 3^d fine box if all INSIDE, else FW weights of
-// the INSIDE nodes renormalised; coarse GHOST: FW of the extended residual if
-// the box holds no INSIDE node and lies in the grid, else renormalised over its
-// non-INSIDE, non-BOXDIR nodes (eq. coarseFW, Sec. 2.2 FW, Sec. 2.3).  Also
-// zeroes the coarse unknowns (initial guess of the coarse correction).
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const SlotState *__restrict__ st) {
-    SEG_PROLOGUE
-    if (lane >= len) return;
-    const Desc &C = L;
-    const Desc &F = descs[it.x - 1];
-    const uint8_t cc = C.cls[p];
-    if (cc != C_INSIDE && cc != C_GHOST) return;
-    ((T *)C.u)[p] = (T)0;
-    const int X0 = 2 * (x0 + lane), X1 = 2 * yj, X2 = 2 * zk;
-    const T *__restrict__ r = (const T *)F.r;
-    double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
-    bool all_ok = true;
-    const int lo2 = D >= 3 ? -1 : 0, hi2 = D >= 3 ? 1 : 0, lo1 = D >= 2 ? -1 : 0, hi1 = D >= 2 ? 1 : 0;
-    for (int m2 = lo2; m2 <= hi2; m2++)
-        for (int m1 = lo1; m1 <= hi1; m1++)
-            for (int m0 = -1; m0 <= 1; m0++) {
-                double wgt = 1.0;
-                wgt *= (m0 == 0 ? 0.5 : 0.25);
-                if (D >= 2) wgt *= (m1 == 0 ? 0.5 : 0.25);
-                if (D >= 3) wgt *= (m2 == 0 ? 0.5 : 0.25);
-                const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
-                if (J0 < 0 || J0 > F.N || (D >= 2 && (J1 < 0 || J1 > F.N)) || (D >= 3 && (J2 < 0 || J2 > F.N))) {
-                    all_ok = false;
-                    continue;
-                }
-                const long long q = J0 + J1 * F.sy + J2 * F.sz;
-                const uint8_t fc = F.cls[q];
-                bool take;
-                if (cc == C_INSIDE) {
-                    take = fc == C_INSIDE;
-                    if (!take) all_ok = false;
-                } else {
-                    take = fc != C_INSIDE && fc != C_BOXDIR;
-                    if (fc == C_INSIDE) all_ok = false;
-                }
-                const double rv = (double)r[q];
-                full += wgt * rv;
-                if (take) {
-                    sel += wgt * rv;
-                    selw += wgt;
-                    msum += rv;
-                    mcnt += 1.0;
-                }
-            }
-    double out;
-    if (all_ok)
-        out = full;
-    else if (C.restrict_mode == BCMG_RESTRICT_PLAIN_MEAN)
-        out = mcnt > 0.0 ? msum / mcnt : 0.0;
-    else
-        out = selw > 0.0 ? sel / selw : 0.0;
-    ((T *)C.rhs)[p] = (T)out;
+    SEG_ITEM
+    seg_restrict<D, T>(L, descs[it.x - 1], it, lane);
 }
 
-// Prolongation and correction on the fine level of the item (coarse level =
-// descriptor + 1): multilinear interpolation of the (extended) coarse error
-// to INSIDE and GHOST nodes, u += e (Sec. 1.1 interpolation, Sec. 2.2, Sec. 2.3).
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                     int nseg, const SlotState *__restrict__ st) {
-    SEG_PROLOGUE
-    if (lane >= len) return;
-    const Desc &F = L;
-    const Desc &C = descs[it.x + 1];
-    const uint8_t fc = F.cls[p];
-    if (fc != C_INSIDE && fc != C_GHOST) return;
-    const int I0 = x0 + lane, I1 = yj, I2 = zk;
-    const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
-    const int B0 = (I0 - h0) / 2, B1 = (I1 - h1) / 2, B2 = (I2 - h2) / 2;
-    const T *__restrict__ ec = (const T *)C.u;
-    double e = 0.0;
-    for (int m2 = 0; m2 <= h2; m2++)
-        for (int m1 = 0; m1 <= h1; m1++)
-            for (int m0 = 0; m0 <= h0; m0++) {
-                double wgt = 1.0;
-                if (h0) wgt *= 0.5;
-                if (h1) wgt *= 0.5;
-                if (h2) wgt *= 0.5;
-                e += wgt * (double)ec[(B0 + m0) + (B1 + m1) * C.sy + (B2 + m2) * C.sz];
-            }
-    T *u = (T *)F.u;
-    u[p] = (T)((double)u[p] + e);
+    SEG_ITEM
+    seg_prolong<D, T>(L, descs[it.x + 1], it, lane);
 }
 
-// --------------------------------------------------------------------------
-// Coarsest level: x = A^{-1} b over INSIDE then GHOST unknowns, in FP64.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(const Desc *__restrict__ descs, const int *__restrict__ list,
                                                    const SlotState *__restrict__ st) {
     const Desc &L = descs[list[blockIdx.x]];
     if (!st[L.slot].active) return;
-    const int nc = L.nc;
-    if (nc == 0 || L.singular) return;
+    if (L.nc == 0 || L.singular) return;
     __shared__ double b[kCoarseMax];
-    const T *rhs = (const T *)L.rhs;
-    for (int t = threadIdx.x; t < nc; t += kBlock) b[t] = (double)rhs[L.cmap[t]];
-    __syncthreads();
-    for (int t = threadIdx.x; t < nc; t += kBlock) {
-        double x = 0.0;
-        const double *row = L.ainv + (long long)t * nc;
-        for (int j = 0; j < nc; j++) x += row[j] * b[j];
-        ((T *)L.u)[L.cmap[t]] = (T)x;
-    }
+    coarse_solve_block<T>(L, b);
 }
 
-// --------------------------------------------------------------------------
 // Iterative refinement: u64 += e32 on INSIDE and GHOST nodes, e32 = 0.
 __global__ __launch_bounds__(kBlock) void k_ir_update(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                       int nseg, const SlotState *__restrict__ st,
                                                       float *const *__restrict__ eptr) {
-    SEG_PROLOGUE
-    if (lane >= len) return;
-    const uint8_t c = L.cls[p];
-    if (c != C_INSIDE && c != C_GHOST) return;
-    float *e = eptr[it.x];
+    SEG_ITEM
+    const Seg s = seg_of(it);
+    float *ev = eptr[it.x];
     double *u = (double *)L.u;
-    u[p] += (double)e[p];
-    e[p] = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = lane + 64 * h;
+        if (q >= s.len) continue;
+        const long long p = s.p0 + q;
+        const uint8_t c = L.cls[p];
+        if (c != C_INSIDE && c != C_GHOST) continue;
+        u[p] += (double)ev[p];
+        ev[p] = 0.0f;
+    }
 }
 
-// --------------------------------------------------------------------------
-// launchers
+// ------------------------------------------------- coarse levels, one block
+// One workgroup per problem runs the part of the V-cycle on its aligned
+// levels 0..top (top = min(its finest level, the batch's coarse threshold)):
+// pre-smoothing, residual, extension and restriction down to the coarsest
+// grid, the exact coarse solve (or 50 smoothing steps when the coarsest
+// matrix is singular), then extension, prolongation and post-smoothing back
+// up.  Steps are separated by workgroup barriers only.
+constexpr int kCoarseThreads = 512;
+constexpr int kCoarseWaves = kCoarseThreads / 64;
+
+template <int D, typename T>
+__device__ void blk_smooth(const Desc *descs, const Item *items, const CoarseLevel &lv) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int colour = 0; colour < 2; colour++) {
+        for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
+            const Item it = items[lv.seg + s];
+            seg_rb<D, T>(descs[it.x], it, lane, colour);
+        }
+        __syncthreads();
+    }
+    const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
+    for (int c = grp; c < lv.ngch; c += ngrp) {
+        const Item it = items[lv.gch + c];
+        if (t < it.z) ghost_delta<D, T>(descs[it.x], it.y + t);
+    }
+    __syncthreads();
+    for (int c = grp; c < lv.ngch; c += ngrp) {
+        const Item it = items[lv.gch + c];
+        if (t < it.z) ghost_apply<T>(descs[it.x], it.y + t);
+    }
+    __syncthreads();
+}
+
+template <int D, typename T>
+__device__ void blk_extend(const Desc *descs, const Item *items, const CoarseLevel &lv, int which, int K) {
+    const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
+    for (int j = 1; j <= K; j++) {
+        for (int c = grp; c < lv.nbch; c += ngrp) {
+            const Item it = items[lv.bch + c];
+            if (t < it.z) ext_sweep_node<D, T>(descs[it.x], which, j, K, it.y + t);
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__restrict__ descs,
+                                                                 const Item *__restrict__ items,
+                                                                 const CoarseProg *__restrict__ progs,
+                                                                 const SlotState *__restrict__ st, int nu1, int nu2,
+                                                                 int K) {
+    const CoarseProg &P = progs[blockIdx.x];
+    if (!st[P.slot].active) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
+    __shared__ double b[kCoarseMax];
+    for (int a = P.top; a >= 1; a--) {
+        const CoarseLevel &lv = P.lev[a];
+        for (int i = 0; i < nu1; i++) blk_smooth<D, T>(descs, items, lv);
+        for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
+            const Item it = items[lv.seg + s];
+            seg_residual<D, T, T>(descs[it.x], it, lane);
+        }
+        for (int c = grp; c < lv.ngch; c += ngrp) {
+            const Item it = items[lv.gch + c];
+            if (t < it.z) ghost_residual<D, T, T>(descs[it.x], it.y + t);
+        }
+        __syncthreads();
+        blk_extend<D, T>(descs, items, lv, 1, K);
+        const CoarseLevel &cv = P.lev[a - 1];
+        for (int s = wave; s < cv.nseg; s += kCoarseWaves) {
+            const Item it = items[cv.seg + s];
+            seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane);
+        }
+        __syncthreads();
+    }
+    {
+        const CoarseLevel &lv = P.lev[0];
+        const Desc &L = descs[lv.desc];
+        if (L.nc > 0 && !L.singular) {
+            coarse_solve_block<T>(L, b);
+        } else if (L.nc > 0) {
+            for (int i = 0; i < 50; i++) blk_smooth<D, T>(descs, items, lv);
+        }
+    }
+    for (int a = 1; a <= P.top; a++) {
+        const CoarseLevel &lv = P.lev[a];
+        blk_extend<D, T>(descs, items, P.lev[a - 1], 0, K);
+        for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
+            const Item it = items[lv.seg + s];
+            seg_prolong<D, T>(descs[it.x], descs[it.x + 1], it, lane);
+        }
+        __syncthreads();
+        for (int i = 0; i < nu2; i++) blk_smooth<D, T>(descs, items, lv);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
 static inline int blocks_for_segs(int nseg) { return (nseg + kWavesPerBlock - 1) / kWavesPerBlock; }
 
-template <typename T>
-static void rb_sweep_t(int d, const Desc *descs, const Item *items, int nseg, int colour, const SlotState *st,
-                       hipStream_t s) {
-    if (nseg <= 0) return;
-    dim3 g(blocks_for_segs(nseg)), b(kBlock);
-    if (d == 1) hipLaunchKernelGGL((k_rb_sweep<1, T>), g, b, 0, s, descs, items, nseg, colour, st);
-    if (d == 2) hipLaunchKernelGGL((k_rb_sweep<2, T>), g, b, 0, s, descs, items, nseg, colour, st);
-    if (d == 3) hipLaunchKernelGGL((k_rb_sweep<3, T>), g, b, 0, s, descs, items, nseg, colour, st);
-}
+#define DISPATCH_D(d, KERNEL, T, ...)                                          \
+    do {                                                                       \
+        if ((d) == 1) hipLaunchKernelGGL((KERNEL<1, T>), __VA_ARGS__);         \
+        if ((d) == 2) hipLaunchKernelGGL((KERNEL<2, T>), __VA_ARGS__);         \
+        if ((d) == 3) hipLaunchKernelGGL((KERNEL<3, T>), __VA_ARGS__);         \
+    } while (0)
 
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s) {
+    if (nseg <= 0) return;
+    dim3 g(blocks_for_segs(nseg)), b(kBlock);
     if (fp32)
-        rb_sweep_t<float>(d, descs, items, nseg, colour, st, s);
+        DISPATCH_D(d, k_rb_sweep, float, g, b, 0, s, descs, items, nseg, colour, st);
     else
-        rb_sweep_t<double>(d, descs, items, nseg, colour, st, s);
-}
-
-template <typename T>
-static void ghost_relax_t(int d, const Desc *descs, const Item *gch, int ngch, const SlotState *st, hipStream_t s) {
-    if (ngch <= 0) return;
-    dim3 g(ngch), b(kBlock);
-    if (d == 1) hipLaunchKernelGGL((k_ghost_delta<1, T>), g, b, 0, s, descs, gch, st);
-    if (d == 2) hipLaunchKernelGGL((k_ghost_delta<2, T>), g, b, 0, s, descs, gch, st);
-    if (d == 3) hipLaunchKernelGGL((k_ghost_delta<3, T>), g, b, 0, s, descs, gch, st);
-    hipLaunchKernelGGL((k_ghost_apply<T>), g, b, 0, s, descs, gch, st);
+        DISPATCH_D(d, k_rb_sweep, double, g, b, 0, s, descs, items, nseg, colour, st);
 }
 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
                         hipStream_t s) {
-    if (fp32)
-        ghost_relax_t<float>(d, descs, gch, ngch, st, s);
-    else
-        ghost_relax_t<double>(d, descs, gch, ngch, st, s);
+    if (ngch <= 0) return;
+    dim3 g(ngch), b(kBlock);
+    if (fp32) {
+        DISPATCH_D(d, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
+        hipLaunchKernelGGL((k_ghost_apply<float>), g, b, 0, s, descs, gch, st);
+    } else {
+        DISPATCH_D(d, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
+        hipLaunchKernelGGL((k_ghost_apply<double>), g, b, 0, s, descs, gch, st);
+    }
 }
 
 template <typename Tu, typename Tr, bool NORM>
@@ -495,62 +768,40 @@ void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, con
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s) {
     if (nslots <= 0) return;
-    hipLaunchKernelGGL(k_norm_finish, dim3(nslots), dim3(kBlock), 0, s, ranges, nslots, partials, nseg_total, st, rtol2,
-                       hist, hist_stride, mode, out);
-}
-
-template <typename T>
-static void extend_t(int d, const Desc *descs, const Item *bch, int nbch, int which, int K, const SlotState *st,
-                     hipStream_t s) {
-    if (nbch <= 0) return;
-    dim3 g(nbch), b(kBlock);
-    for (int j = 1; j <= K; j++) {
-        if (d == 1) hipLaunchKernelGGL((k_ext_sweep<1, T>), g, b, 0, s, descs, bch, which, j, K, st);
-        if (d == 2) hipLaunchKernelGGL((k_ext_sweep<2, T>), g, b, 0, s, descs, bch, which, j, K, st);
-        if (d == 3) hipLaunchKernelGGL((k_ext_sweep<3, T>), g, b, 0, s, descs, bch, which, j, K, st);
-    }
+    hipLaunchKernelGGL(k_norm_finish, dim3(nslots), dim3(kNormThreads), 0, s, ranges, nslots, partials, nseg_total,
+                       st, rtol2, hist, hist_stride, mode, out);
 }
 
 void launch_extend(int d, int fp32, const Desc *descs, const Item *bch, int nbch, int which, int K,
                    const SlotState *st, hipStream_t s) {
-    if (fp32)
-        extend_t<float>(d, descs, bch, nbch, which, K, st, s);
-    else
-        extend_t<double>(d, descs, bch, nbch, which, K, st, s);
-}
-
-template <typename T>
-static void restrict_t(int d, const Desc *descs, const Item *csegs, int nseg, const SlotState *st, hipStream_t s) {
-    if (nseg <= 0) return;
-    dim3 g(blocks_for_segs(nseg)), b(kBlock);
-    if (d == 1) hipLaunchKernelGGL((k_restrict<1, T>), g, b, 0, s, descs, csegs, nseg, st);
-    if (d == 2) hipLaunchKernelGGL((k_restrict<2, T>), g, b, 0, s, descs, csegs, nseg, st);
-    if (d == 3) hipLaunchKernelGGL((k_restrict<3, T>), g, b, 0, s, descs, csegs, nseg, st);
+    if (nbch <= 0) return;
+    dim3 g(nbch), b(kBlock);
+    for (int j = 1; j <= K; j++) {
+        if (fp32)
+            DISPATCH_D(d, k_ext_sweep, float, g, b, 0, s, descs, bch, which, j, K, st);
+        else
+            DISPATCH_D(d, k_ext_sweep, double, g, b, 0, s, descs, bch, which, j, K, st);
+    }
 }
 
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const SlotState *st,
                      hipStream_t s) {
-    if (fp32)
-        restrict_t<float>(d, descs, csegs, nseg, st, s);
-    else
-        restrict_t<double>(d, descs, csegs, nseg, st, s);
-}
-
-template <typename T>
-static void prolong_t(int d, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st, hipStream_t s) {
     if (nseg <= 0) return;
     dim3 g(blocks_for_segs(nseg)), b(kBlock);
-    if (d == 1) hipLaunchKernelGGL((k_prolong<1, T>), g, b, 0, s, descs, fsegs, nseg, st);
-    if (d == 2) hipLaunchKernelGGL((k_prolong<2, T>), g, b, 0, s, descs, fsegs, nseg, st);
-    if (d == 3) hipLaunchKernelGGL((k_prolong<3, T>), g, b, 0, s, descs, fsegs, nseg, st);
+    if (fp32)
+        DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, st);
+    else
+        DISPATCH_D(d, k_restrict, double, g, b, 0, s, descs, csegs, nseg, st);
 }
 
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
                     hipStream_t s) {
+    if (nseg <= 0) return;
+    dim3 g(blocks_for_segs(nseg)), b(kBlock);
     if (fp32)
-        prolong_t<float>(d, descs, fsegs, nseg, st, s);
+        DISPATCH_D(d, k_prolong, float, g, b, 0, s, descs, fsegs, nseg, st);
     else
-        prolong_t<double>(d, descs, fsegs, nseg, st, s);
+        DISPATCH_D(d, k_prolong, double, g, b, 0, s, descs, fsegs, nseg, st);
 }
 
 void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s) {
@@ -559,6 +810,16 @@ void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const Sl
         hipLaunchKernelGGL((k_coarse<float>), dim3(n), dim3(kBlock), 0, s, descs, list, st);
     else
         hipLaunchKernelGGL((k_coarse<double>), dim3(n), dim3(kBlock), 0, s, descs, list, st);
+}
+
+void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
+                         const SlotState *st, int nu1, int nu2, int K, hipStream_t s) {
+    if (nprog <= 0) return;
+    dim3 g(nprog), b(kCoarseThreads);
+    if (fp32)
+        DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2, K);
+    else
+        DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2, K);
 }
 
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,

@@ -23,6 +23,9 @@ void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int 
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
                     hipStream_t s);
 void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s);
+// one workgroup per program: the V-cycle on the program's coarse levels
+void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
+                         const SlotState *st, int nu1, int nu2, int K, hipStream_t s);
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
                       hipStream_t s);
 
