@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles in the CPU sample")
+    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served"], default="flower257",
+                    help="flower257: the headline single solve; mixed513: 513^3 FP64 against mixed precision; "
+                         "batched: 512 2D star problems; served: the continuous-batching request loop")
+    ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
+    ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     return ap.parse_args()
 
 
@@ -51,6 +56,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design is "
                                    "described in DESIGN.md and not implemented)"}))
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "mixed513":
+        return bench_mixed(args)
+    if args.workload == "served":
+        return bench_served(args)
     import numpy as np
     import torch
 
@@ -189,6 +200,146 @@ def main():
             "r0": r0,
         }
     print(json.dumps(out))
+
+
+def _flower_problem(N, prec, max_cycles):
+    import torch
+
+    from paper_2207_14208_amd import workloads as W
+    from paper_2207_14208_amd.solver import Problem
+    case = W.flower3d(N)
+    G = Problem(3, N, torch.from_numpy(case.phi).cuda(), precision=prec, max_cycles=max_cycles)
+    q = G.ghost_info(0)["q"]
+    G.set_data(torch.from_numpy(case.f).cuda(), torch.exp(q[:, 0] + q[:, 1] + q[:, 2]))
+    return case, G
+
+
+def bench_mixed(args):
+    """513^3 flower: the plain FP64 solve against the mixed-precision solve
+    (FP32 cycle on the correction, FP64 residual, update and coarse solve),
+    both to ||r|| <= 1e-10 ||r0||; error of the mixed result against the FP64
+    result and against the exact solution."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd import workloads as W
+    N = 512 if args.N == 256 else args.N
+    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
+           "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,
+           "warmup": args.warmup}
+    res = {}
+    sols = {}
+    for name, prec in (("fp64", NAT.FP64), ("mixed", NAT.MIXED)):
+        case, G = _flower_problem(N, prec, args.max_cycles)
+        info = G.level_info(0)
+        unknowns = info["n_inside"] + info["n_ghost"]
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            u.zero_()
+            G.solve(u, 1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u.zero_()
+            st, hist = G.solve(u, 1e-10)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        res[name] = {"unknowns_per_s": unknowns / el, "ms_per_solve": el * 1e3, "cycles": st.cycles,
+                     "status": st.status, "rel_residual": st.r_final / st.r0}
+        cls = G.classes(0)
+        m = (cls == NAT.INSIDE) | (cls == NAT.GHOST)
+        sols[name] = u[m].clone()
+        if name == "mixed":
+            ue = torch.from_numpy(W.sample(3, N, case.u_exact)).cuda()[m]
+            res[name]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
+                                                 sols["fp64"].abs().max()).item()
+            res[name]["max_err_vs_exact"] = (sols["mixed"] - ue).abs().max().item()
+            res["fp64"]["max_err_vs_exact"] = (sols["fp64"] - ue).abs().max().item()
+        out["config"] = {"workload": f"3D flower, {N + 1}^3 nodes, u=exp(x+y+z), FP64 vs mixed V(2,1) to 1e-10",
+                         "unknowns": unknowns, "levels": G.levels}
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    out["value"] = res["mixed"]["unknowns_per_s"]
+    out["ms_per_step"] = res["mixed"]["ms_per_solve"]
+    out["dtype"] = "f32+f64"
+    out["fp64"] = res["fp64"]
+    out["mixed"] = res["mixed"]
+    out["speedup_mixed_vs_fp64"] = res["mixed"]["unknowns_per_s"] / res["fp64"]["unknowns_per_s"]
+    print(json.dumps(out))
+
+
+def bench_batched(args):
+    """512 independent 2D star problems (sides 65..1025, seed 2207),
+    mixed precision, solved together by the batched engine (hipGraph-replayed
+    cycles, per-problem coarse workgroups, autotuned row tile, coarse
+    threshold and cycles per replay), against the same problems solved one
+    after another by the plain FP64 solver."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd import autotune
+    from paper_2207_14208_amd import workloads as W
+    from paper_2207_14208_amd.batching import BatchConfig, BatchSolver, make_problem
+
+    t0 = time.perf_counter()
+    sample = [W.star_case(i, *p) for i, p in enumerate(W.star_params(24, seed=1))]
+    tuned = autotune.tune(sample, NAT.MIXED, cycles=4, use_cache=False)
+    tune_s = time.perf_counter() - t0
+    params = W.star_params(args.problems, seed=2207)
+    cases = [W.star_case(i, *p) for i, p in enumerate(params)]
+    cfg = BatchConfig(seg_len=tuned["seg_len"], coarse_nodes=tuned["coarse_nodes"],
+                      cycles_per_step=tuned["cycles_per_step"], precision=NAT.MIXED, max_cycles=args.max_cycles)
+    t1 = time.perf_counter()
+    bs = BatchSolver(cases, cfg)
+    setup_s = time.perf_counter() - t1
+    for _ in range(args.warmup):
+        bs.reset()
+        bs.run()
+    times = []
+    for _ in range(args.steps):
+        bs.reset()
+        r = bs.run()
+        times.append(r.elapsed_s)
+    el = float(np.median(times))
+    ok = sum(1 for s in r.status if s == 0)
+    # plain FP64 solver, one problem after another (same problems, same tolerance)
+    plain_el = 0.0
+    plain_cycles = []
+    for c in cases:
+        G, u, _ = make_problem(c, BatchConfig(seg_len=128, precision=NAT.FP64, max_cycles=args.max_cycles))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st, _ = G.solve(u, 1e-10)
+        torch.cuda.synchronize()
+        plain_el += time.perf_counter() - ts
+        plain_cycles.append(st.cycles)
+        G.close()
+    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
+           "value": r.unknowns / el, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic (seeded star domains and manufactured solution)",
+           "config": {"workload": f"{args.problems} 2D star problems, sides 65..1025 (seed 2207), mixed precision, "
+                                  "batched V(2,1) to rel. residual 1e-10",
+                      "problems": args.problems, "unknowns": r.unknowns, "converged": ok,
+                      "cycles_min_median_max": [int(np.min(r.cycles)), int(np.median(r.cycles)), int(np.max(r.cycles))],
+                      "tuned": {k: tuned[k] for k in ("seg_len", "coarse_nodes", "cycles_per_step")},
+                      "tune_s": tune_s, "setup_s": setup_s},
+           "effective_hbm": {"alg_bytes": r.alg_bytes, "GBps": r.alg_bytes / el / 1e9,
+                             "frac_of_8TBps": r.alg_bytes / el / 8e12},
+           "plain_fp64_one_by_one": {"unknowns_per_s": r.unknowns / plain_el, "seconds": plain_el,
+                                     "cycles_median": int(np.median(plain_cycles))},
+           "speedup_vs_plain": (r.unknowns / el) / (r.unknowns / plain_el)}
+    print(json.dumps(out))
+    bs.close()
+
+
+def bench_served(args):
+    from paper_2207_14208_amd import serving
+    print(json.dumps(serving.bench(args)))
 
 
 if __name__ == "__main__":

@@ -79,6 +79,7 @@ typedef struct {
     double dtau_const;     /* used by BCMG_DTAU_CONST */
     int32_t ext_iters;     /* K: Jacobi sweeps of the normal extension (default 4, 1..8) */
     int32_t restrict_mode; /* BCMG_RESTRICT_* */
+    int32_t seg_len;       /* row tile: nodes per row segment handled by one wavefront (64 or 128, default 128) */
 } bcmg_options;
 
 typedef struct {
@@ -97,7 +98,8 @@ const char *bcmg_last_error(void);
 int32_t bcmg_version(void);
 
 /* Fill *opt with the defaults: V(2,1), coarsest N = 4, 100 cycles, FP64,
- * exponential-form dtau (Remark exptheta2D), K = 4, renormalised FW. */
+ * exponential-form dtau (Remark exptheta2D), K = 4, renormalised FW,
+ * 128-node row segments. */
 bcmg_status bcmg_default_options(bcmg_options *opt);
 
 /*
@@ -225,6 +227,10 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b);
  * computes ||r^0|| and returns the slot. */
 bcmg_status bcmg_batch_add(bcmg_batch *b, bcmg_problem *prob, double *u_dev, double rel_tol, int32_t *slot);
 
+/* Restart every occupied slot from the current contents of its u_dev
+ * (recomputes ||r^0||); work lists and graphs are kept. */
+bcmg_status bcmg_batch_restart(bcmg_batch *b);
+
 /* Drop a slot (its problem and u_dev are released to the caller). */
 bcmg_status bcmg_batch_remove(bcmg_batch *b, int32_t slot);
 
@@ -241,6 +247,11 @@ bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stat
 
 /* Device bytes a problem of this size would need (for admission control). */
 bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64_t *bytes);
+
+/* Batch tuning parameters (take effect at the next step). */
+#define BCMG_PARAM_COARSE_NODES 1 /* levels with at most this many nodes run in one workgroup per problem (default 1200) */
+
+bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value);
 
 /* Bytes of device memory held by a problem. */
 bcmg_status bcmg_problem_bytes(const bcmg_problem *prob, int64_t *bytes);

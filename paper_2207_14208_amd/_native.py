@@ -18,12 +18,13 @@ OUTSIDE, INSIDE, GHOST, BOXDIR = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 DTAU_OPT_EXP, DTAU_OPT_POLY, DTAU_CONST = 0, 1, 2
 RESTRICT_RENORM_FW, RESTRICT_PLAIN_MEAN = 0, 1
+PARAM_COARSE_NODES = 1
 
 
 class bcmg_options(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("coarsest_N", C.c_int32), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("dtau_mode", C.c_int32), ("dtau_const", C.c_double),
-                ("ext_iters", C.c_int32), ("restrict_mode", C.c_int32)]
+                ("ext_iters", C.c_int32), ("restrict_mode", C.c_int32), ("seg_len", C.c_int32)]
 
 
 class bcmg_solve_stats(C.Structure):
@@ -65,10 +66,12 @@ PROTOTYPES = {
     "bcmg_batch_destroy": (i32, [vp]),
     "bcmg_batch_add": (i32, [vp, vp, vp, dbl, P(i32)]),
     "bcmg_batch_remove": (i32, [vp, i32]),
+    "bcmg_batch_restart": (i32, [vp]),
     "bcmg_batch_step": (i32, [vp, i32, vp]),
     "bcmg_batch_run": (i32, [vp, i32, i32]),
     "bcmg_batch_stats": (i32, [vp, i32, P(bcmg_solve_stats), vp]),
     "bcmg_estimate_bytes": (i32, [i32, i32, i32, P(i64)]),
+    "bcmg_batch_set_param": (i32, [vp, i32, i64]),
     "bcmg_problem_bytes": (i32, [vp, P(i64)]),
     "bcmg_timing_enable": (i32, [i32]),
     "bcmg_timing_read": (i32, [P(i64), P(dbl), P(i64)]),

@@ -136,6 +136,7 @@ struct bcmg_batch {
     Item *fsegs = nullptr, *fgch = nullptr;
     int nfseg = 0, nfgch = 0;
     int Ac = 0;                    // aligned levels 0..Ac run in the per-problem coarse workgroup
+    long long coarse_nodes = kCoarseNodes;
     CoarseProg *d_progs = nullptr;
     int nprog = 0;
     bool dirty = true;
@@ -302,8 +303,8 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
             if (lo < 0) continue;
             const int j = d >= 2 ? (int)(r % V.n) : 0;
             const int k = d >= 3 ? (int)(r / V.n) : 0;
-            for (int x = lo; x <= hi; x += kSegLen) {
-                const int len = std::min(kSegLen, hi - x + 1);
+            for (int x = lo; x <= hi; x += P->opt.seg_len) {
+                const int len = std::min(P->opt.seg_len, hi - x + 1);
                 V.segs.push_back(seg_item(0, r * V.n + x, x, len, j, k));
             }
         }
@@ -414,6 +415,7 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->dtau_const = 1.0;
     o->ext_iters = 4;
     o->restrict_mode = BCMG_RESTRICT_RENORM_FW;
+    o->seg_len = kSegLen;
     return BCMG_OK;
 }
 
@@ -433,6 +435,7 @@ static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
         return fail(BCMG_ERR_INVALID, "dtau_const must be positive");
     if (o->ext_iters < 1 || o->ext_iters > 8) return fail(BCMG_ERR_INVALID, "ext_iters must be in 1..8");
     if (o->restrict_mode != 0 && o->restrict_mode != 1) return fail(BCMG_ERR_INVALID, "bad restrict_mode");
+    if (o->seg_len != 64 && o->seg_len != 128) return fail(BCMG_ERR_INVALID, "seg_len must be 64 or 128");
     return BCMG_OK;
 }
 
@@ -902,12 +905,12 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
             if (b->prob[s]->L == A) b->fine_inside += b->prob[s]->lev[0].ni;
         }
     // aligned level a has N = 4 * 2^a on every problem: levels with at most
-    // kCoarseNodes nodes are cycled by one workgroup per problem
+    // coarse_nodes nodes are cycled by one workgroup per problem
     int Ac = 0;
     for (int a2 = 0; a2 < kMaxLevels; a2++) {
         long long nn = 1;
         for (int k = 0; k < b->d; k++) nn *= (4LL << a2) + 1;
-        if (nn > kCoarseNodes) break;
+        if (nn > b->coarse_nodes) break;
         Ac = a2;
     }
     b->Ac = Ac;
@@ -1111,6 +1114,42 @@ bcmg_status bcmg_batch_add(bcmg_batch *b, bcmg_problem *P, double *u, double rto
     if ((st = batch_init_slot(b, s, rtol))) return st;
     if (slot) *slot = s;
     return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_restart(bcmg_batch *b) {
+    if (!b) return fail(BCMG_ERR_INVALID, "null batch");
+    bcmg_status st = batch_join(b);
+    if (st) return st;
+    if (b->dirty && (st = batch_rebuild(b))) return st;
+    std::vector<SlotState> s0(b->cap);
+    std::vector<double> r2(b->cap, 0.0);
+    for (int s = 0; s < b->cap; s++) {
+        memset(&s0[s], 0, sizeof(SlotState));
+        if (!b->prob[s]) continue;
+        s0[s].active = 2;
+        s0[s].max_cycles = b->prob[s]->opt.max_cycles;
+        r2[s] = b->rtol[s] * b->rtol[s];
+        if (b->prob[s]->fp32)
+            HIPCHK(hipMemsetAsync(b->prob[s]->lev[0].u, 0, b->prob[s]->lev[0].nn * 4, b->stream));
+    }
+    HIPCHK(hipMemcpyAsync(b->d_state, s0.data(), sizeof(SlotState) * b->cap, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_rtol2, r2.data(), sizeof(double) * b->cap, hipMemcpyHostToDevice, b->stream));
+    launch_outer_residual(b, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value) {
+    if (!b) return fail(BCMG_ERR_INVALID, "null batch");
+    if (param == BCMG_PARAM_COARSE_NODES) {
+        if (value < 0 || value > 100000000) return fail(BCMG_ERR_INVALID, "coarse_nodes out of range");
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->coarse_nodes = value;
+        b->dirty = true;
+        return BCMG_OK;
+    }
+    return fail(BCMG_ERR_INVALID, "unknown parameter %d", param);
 }
 
 bcmg_status bcmg_batch_remove(bcmg_batch *b, int32_t slot) {

@@ -184,6 +184,12 @@ class Batch:
         self.slots[s.value] = (prob, u)
         return s.value
 
+    def restart(self):
+        check(lib().bcmg_batch_restart(self.h))
+
+    def set_param(self, param: int, value: int):
+        check(lib().bcmg_batch_set_param(self.h, param, int(value)))
+
     def remove(self, slot: int):
         check(lib().bcmg_batch_remove(self.h, slot))
         self.slots.pop(slot, None)

@@ -258,3 +258,48 @@ def random_guess(n: int, seed: int = 0) -> Array:
     """U(-1, 1) initial guess (convergence-factor protocol, Sec. 1.2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=n)
+
+
+# ------------------------------------------------------- device-side sampling
+def sphere_request_params(rng: np.random.Generator, sides=(33, 65, 129, 257)) -> dict:
+    """The draws of one served request, in order: side ~ U{sides}; m ~ U{4..64};
+    centres ~ U[-0.7,0.7]^3; radii ~ U[0.05,0.2]; the 8 terms of the random
+    smooth f (k ~ U{0..3}^3, a ~ U[-1,1], psi ~ U[0,2pi))."""
+    side = int(sides[rng.integers(0, len(sides))])
+    m = int(rng.integers(4, 65))
+    centres = rng.uniform(-0.7, 0.7, size=(m, 3))
+    radii = rng.uniform(0.05, 0.2, size=m)
+    ks = rng.integers(0, 4, size=(8, 3))
+    amps = rng.uniform(-1.0, 1.0, size=8)
+    phases = rng.uniform(0.0, 2 * math.pi, size=8)
+    return dict(side=side, m=m, centres=centres, radii=radii, ks=ks, amps=amps, phases=phases)
+
+
+def sample_sphere_request_torch(p: dict, device="cuda"):
+    """phi = min_i(|x - c_i| - r_i) and f = sum_q a_q cos(pi k_q . x + psi_q) on
+    the (side)^3 nodes, FP64, evaluated with torch on `device` (x fastest)."""
+    import torch
+    n = p["side"]
+    x = -1.0 + torch.arange(n, dtype=torch.float64, device=device) * (2.0 / (n - 1))
+    Z, Y, X = torch.meshgrid(x, x, x, indexing="ij")
+    phi = torch.full_like(X, float("inf"))
+    for (cx, cy, cz), r in zip(p["centres"], p["radii"]):
+        phi = torch.minimum(phi, torch.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2) - r)
+    f = torch.zeros_like(X)
+    for q in range(len(p["amps"])):
+        k = p["ks"][q]
+        f = f + p["amps"][q] * torch.cos(math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + p["phases"][q])
+    return phi.reshape(-1).contiguous(), f.reshape(-1).contiguous()
+
+
+def sample_sphere_request_numpy(p: dict):
+    """The same phi and f as sample_sphere_request_torch, with numpy on the host."""
+    X, Y, Z = node_coords(3, p["side"] - 1)
+    phi = np.full(X.shape, np.inf)
+    for (cx, cy, cz), r in zip(p["centres"], p["radii"]):
+        phi = np.minimum(phi, np.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2) - r)
+    f = np.zeros_like(X)
+    for q in range(len(p["amps"])):
+        k = p["ks"][q]
+        f = f + p["amps"][q] * np.cos(math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + p["phases"][q])
+    return phi.ravel(), f.ravel()
