@@ -6,14 +6,14 @@
  * MI355X (gfx950).  Every step of the cycle runs as a HIP kernel on the
  * device; the host only validates arguments, sizes buffers and launches.
  *
- * Problem (Sec. 2, eq. mainProblem2D; Sec. 2.3; Sec. 3):
+ * Problem (Sec. 3, eq. mainProblem2D; Sec. 3.3; Sec. 4):
  *   box D = [-1,1]^d, d in {1,2,3}, nodes x_i = -1 + i h, h = 2/N, i = 0..N;
  *   Omega = {phi < 0};  -Laplace(u) = f in Omega;  u = g on the curved
  *   boundary (ghost-point Dirichlet rows, eq. BCh);  u = g_B on nodes of the
  *   box faces inside Omega (eliminated Dirichlet nodes).
  *
  * Node arrays are dense, (N+1)^d entries, x fastest (index i + n j + n^2 k,
- * n = N+1).  Node classes (Sec. 2.3 partition of D_h):
+ * n = N+1).  Node classes (Sec. 3.3 partition of D_h):
  *   BCMG_OUTSIDE 0  inactive node
  *   BCMG_INSIDE  1  phi < 0, not on a box face: interior unknown
  *   BCMG_GHOST   2  phi >= 0 with an INSIDE axis neighbour: ghost unknown
@@ -108,7 +108,7 @@ bcmg_status bcmg_default_options(bcmg_options *opt);
  *   and N <= 4096 (1D/2D) or 1024 (3D).
  *   phi_dev: (N+1)^dim FP64 node values, x fastest; read during the call only.
  *     Coarse levels take phi by injection (every coarse node is a fine node) and
- *     are classified on their own (Sec. 2.3: a node may be inactive on one
+ *     are classified on their own (Sec. 3.3: a node may be inactive on one
  *     level and a ghost on the next).
  *   stream: hipStream_t for every later call on this problem (NULL = default).
  * Per level the setup classifies nodes, compacts the ghost list in ascending
@@ -164,7 +164,7 @@ bcmg_status bcmg_fill_boundary(bcmg_problem *prob, const double *gbox_dev, doubl
 
 /* One V(nu1,nu2) cycle on u_dev (finest level, FP64, in place).  INSIDE and
  * GHOST entries are the unknowns, BOXDIR entries must hold g_B, other entries
- * are never read or written.  Sec. 1.1 (TGCS and its gamma = 1 recursion). */
+ * are never read or written.  Sec. 2.1 (TGCS and its gamma = 1 recursion). */
 bcmg_status bcmg_vcycle(bcmg_problem *prob, double *u_dev);
 
 /* ||f - A u||_2 over INSIDE and GHOST rows of the finest level (host result). */
@@ -172,7 +172,7 @@ bcmg_status bcmg_residual_norm(bcmg_problem *prob, const double *u_dev, double *
 
 /*
  * Solve in place from the given u_dev until ||r^m|| <= rel_tol ||r^0||
- * (residual normalised by the first iteration, Sec. 2.3 comparison with AGMG).
+ * (residual normalised by the first iteration, Sec. 3.3 comparison with AGMG).
  * In BCMG_MIXED mode each cycle is an FP64 residual, an FP32 V-cycle on the
  * correction with an FP64 coarse solve, and an FP64 update (iterative
  * refinement).  hist_host (max_cycles+1 doubles, may be NULL) receives
@@ -194,18 +194,18 @@ bcmg_status bcmg_level_residual(bcmg_problem *prob, int32_t level, const double 
                                 double *r_dev, double *norm_host);
 
 /* Normal extension of the GHOST values of v into the OUTSIDE nodes within
- * Chebyshev distance K of a ghost (K upwind Jacobi sweeps from 0, Sec. 2.3
+ * Chebyshev distance K of a ghost (K upwind Jacobi sweeps from 0, Sec. 3.3
  * transfer operators); other OUTSIDE entries of v must already be 0. */
 bcmg_status bcmg_level_extend(bcmg_problem *prob, int32_t level, double *v_dev);
 
 /* rhs_coarse (level+1) from the extended residual r_fine (level), eq.
- * coarseFW and Sec. 2.3: renormalised FW kept separate for interior and ghost
+ * coarseFW and Sec. 3.3: renormalised FW kept separate for interior and ghost
  * rows.  Written on coarse INSIDE and GHOST nodes only. */
 bcmg_status bcmg_level_restrict(bcmg_problem *prob, int32_t level, const double *rfine_dev, double *rhs_coarse_dev);
 
 /* u_fine += P e_coarse on fine INSIDE and GHOST nodes (multilinear); e_coarse
  * (level+1) must hold 0 on BOXDIR and OUTSIDE nodes; its OUTSIDE band entries
- * are overwritten by the extension first (Sec. 2.3). */
+ * are overwritten by the extension first (Sec. 3.3). */
 bcmg_status bcmg_level_prolong(bcmg_problem *prob, int32_t level, double *ecoarse_dev, double *ufine_dev);
 
 /* Exact solve on the coarsest level (dense inverse built at setup; BOXDIR

@@ -12,12 +12,12 @@
  * Every loop runs over the whole node box in lexicographic order (x fastest),
  * exactly as the definitions read; nothing is blocked, fused or reordered.
  *
- * Node classes (Sec. 2.3 "Non-rectangular domains", partition of D_h):
+ * Node classes (Sec. 3.3 "Non-rectangular domains", partition of D_h):
  *   OUTSIDE  inactive node (I_h)
  *   INSIDE   phi < 0 and not on a face of the box (Omega_h)
  *   GHOST    not INSIDE, phi >= 0, with an INSIDE axis neighbour (Gamma_h)
  *   BOXDIR   phi < 0 on a face of the box: eliminated Dirichlet node
- *            (Sec. 2, eq. (mainProblem2D), value g_B)
+ *            (Sec. 3, eq. (mainProblem2D), value g_B)
  */
 #include <math.h>
 #include <stdio.h>
@@ -45,7 +45,7 @@
 #define OR_MAXLEV 16
 
 typedef struct {
-    int nu1, nu2;        /* pre- and post-smoothing steps (Sec. 1.1) */
+    int nu1, nu2;        /* pre- and post-smoothing steps (Sec. 2.1) */
     int coarsest_N;      /* intervals per axis on the coarsest grid */
     int max_cycles;
     int dtau_mode;       /* OPT_EXP (Remark exptheta2D), OPT_POLY (eq. dtauoptLFA), CONST */
@@ -149,7 +149,7 @@ static void or_coeff(double t, double c[3]) {
  *        vertices V = A_1..A_d with p(A_i) = acosh(1+i) (i<d), p(A_d) = acosh(2d-1).
  *  EXP:  Remark exptheta2D: G0 = exp(-p theta); G0 is monotone in p so the
  *        extremes are at p = acosh(2) and p = acosh(2d-1).
- *  theta is clamped to [0,1] (the analysis assumes 0 <= theta < 1, Sec. 1).
+ *  theta is clamped to [0,1] (the analysis assumes 0 <= theta < 1, Sec. 2).
  *  d = 1: p = acosh(1) = 0 and every form gives 1.
  */
 double or_dtau(int d, double theta, int mode, double dtau_const) {
@@ -178,7 +178,7 @@ double or_dtau(int d, double theta, int mode, double dtau_const) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Classification (Sec. 2.3: D_h = Omega_h U Gamma_h U I_h; Sec. 2 eliminated */
+/* Classification (Sec. 3.3: D_h = Omega_h U Gamma_h U I_h; Sec. 3 eliminated */
 /* Dirichlet nodes on the box faces).                                         */
 void or_classify(int d, int N, const double *phi, unsigned char *cls) {
     or_level L;
@@ -213,7 +213,7 @@ void or_classify(int d, int N, const double *phi, unsigned char *cls) {
 }
 
 /* Discrete gradient of phi at a node: central differences, one-sided on a
- * box face (Sec. 2.3: the normal is a finite-difference approximation of
+ * box face (Sec. 3.3: the normal is a finite-difference approximation of
  * grad phi / |grad phi| centred at the ghost point). */
 static void or_grad(const or_level *L, const int I[3], double g[3]) {
     g[0] = g[1] = g[2] = 0.0;
@@ -231,7 +231,7 @@ static void or_grad(const or_level *L, const int I[3], double g[3]) {
 }
 
 /* Lagrange basis on nodes 0..w-1 evaluated at t (eq. coeff for w = 3,
- * the s = 2 coefficients of Sec. 1 for w = 2). */
+ * the s = 2 coefficients of Sec. 2 for w = 2). */
 static double or_lagrange(int w, int m, double t) {
     if (w == 1) return 1.0;
     if (w == 2) return m == 0 ? 1.0 - t : t;
@@ -298,7 +298,7 @@ static int or_block_dominant(const or_level *L, const int I[3], const int s[3], 
 }
 
 /*
- * Geometry of one ghost point G (Sec. 2.3, eqs. (BCh), (rel), (DtauOptTheta)):
+ * Geometry of one ghost point G (Sec. 3.3, eqs. (BCh), (rel), (DtauOptTheta)):
  * normal n, upwind signs, stencil widths, projection Q = G - eta h n with
  * phi~(Q) = 0, local coordinates tau of Q, theta~ = |G-Q|/h = eta, Delta tau.
  */
@@ -369,7 +369,7 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
     if (phiG == 0.0) {
         eta = 0.0;
     } else {
-        /* eta is sought in [0, 1] (Sec. 2.3): bracket at eta = 1 */
+        /* eta is sought in [0, 1] (Sec. 3.3): bracket at eta = 1 */
         double hi = -1.0;
         {
             double t[3] = {0.0, 0.0, 0.0};
@@ -430,7 +430,7 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
     L->gfb[gi] = fb;
     double dt = or_dtau(d, eta, o->dtau_mode, o->dtau_const);
     /* never relax a ghost row beyond its own Gauss-Seidel step dtau = 1/c_0
-     * (the value the relaxation reduces to at theta = 0, Sec. 1.1); on the
+     * (the value the relaxation reduces to at theta = 0, Sec. 2.1); on the
      * quadratic row of the BLFA this bound is inactive in 2D and within 3%
      * in 3D, it only tames the shortened stencils */
     if (o->dtau_mode != OR_DTAU_CONST) {
@@ -484,7 +484,7 @@ void or_apply_A(or_problem *P, int l, const double *u, double *Au) {
     for (long gi = 0; gi < L->ng; gi++) Au[L->gidx[gi]] = or_ghost_row(L, gi, u);
 }
 
-/* Residual r = rhs - A u on INSIDE and GHOST rows, 0 elsewhere (Sec. 1.1) */
+/* Residual r = rhs - A u on INSIDE and GHOST rows, 0 elsewhere (Sec. 2.1) */
 void or_residual(or_problem *P, int l, const double *u, const double *rhs, double *r) {
     or_level *L = &P->lev[l];
     for (long p = 0; p < L->nn; p++) r[p] = 0.0;
@@ -544,7 +544,7 @@ void or_smooth(or_problem *P, int l, double *u, const double *rhs) {
 
 /*
  * Extension of ghost values into the inactive nodes along the normal
- * (Sec. 2.3 "Transfer operators": a few pseudo-time steps of
+ * (Sec. 3.3 "Transfer operators": a few pseudo-time steps of
  * dr/dsigma + dr/dn = 0).  Reading: K Jacobi sweeps of the steady upwind
  * form v(X) = sum_k |n_k| v(X - s_k e_k) / sum_k |n_k| on every OUTSIDE
  * node, starting from v = 0; out-of-box terms dropped, BOXDIR values 0,
@@ -611,8 +611,8 @@ void or_extend(or_problem *P, int l, double *v) {
 }
 
 /*
- * Restriction fine level l -> coarse level l+1 (Sec. 1.1 eq. coarseFW,
- * Sec. 2.2 nine-point FW, Sec. 2.3 "Transfer operators").  rfine must hold
+ * Restriction fine level l -> coarse level l+1 (Sec. 2.1 eq. coarseFW,
+ * Sec. 3.2 nine-point FW, Sec. 3.3 "Transfer operators").  rfine must hold
  * the residual of level l already extended into the OUTSIDE nodes.
  *   coarse INSIDE: FW over the 3^d fine box around X = 2J if all of it is
  *     INSIDE, else the FW weights of its INSIDE nodes renormalised to 1.
@@ -692,8 +692,8 @@ void or_restrict(or_problem *P, int l, const double *rfine, double *rc) {
 }
 
 /*
- * Prolongation and correction, coarse level l+1 -> fine level l (Sec. 1.1
- * interpolation operator, Sec. 2.2 bilinear interpolation, Sec. 2.3: after
+ * Prolongation and correction, coarse level l+1 -> fine level l (Sec. 2.1
+ * interpolation operator, Sec. 3.2 bilinear interpolation, Sec. 3.3: after
  * extending the coarse error into the inactive nodes).  ec is modified:
  * BOXDIR entries are set to 0 and OUTSIDE entries receive the extension.
  */
@@ -729,7 +729,7 @@ void or_prolong(or_problem *P, int l, double *ec, double *u) {
 
 /* ------------------------------------------------------------------------- */
 /* Coarsest-level solve: Gaussian elimination with partial pivoting on the   */
-/* dense INSIDE U GHOST rows (Sec. 1.1: solved exactly on the coarse grid).  */
+/* dense INSIDE U GHOST rows (Sec. 2.1: solved exactly on the coarse grid).  */
 
 static void or_coarse_factor(or_problem *P) {
     or_level *L = &P->lev[P->L - 1];
@@ -856,7 +856,7 @@ void or_coarse_solve(or_problem *P, double *u, const double *rhs) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Cycles (Sec. 1.1: TGCS, and its recursion with gamma = 1: the V-cycle)     */
+/* Cycles (Sec. 2.1: TGCS, and its recursion with gamma = 1: the V-cycle)     */
 
 static void or_vcycle_level(or_problem *P, int l, double *u, const double *rhs);
 
@@ -899,7 +899,7 @@ void or_vcycle(or_problem *P, double *u) { or_vcycle_level(P, 0, u, P->lev[0].rh
 
 /*
  * Solve from the given u (BOXDIR entries hold g_B) until
- * |r_m| / |r_0| <= tol (Sec. 2.3, comparison with AGMG: residual normalised
+ * |r_m| / |r_0| <= tol (Sec. 3.3, comparison with AGMG: residual normalised
  * by the first iteration).  hist (max_cycles+1 entries, may be NULL)
  * receives |r_m|.  Returns the number of cycles, or -1 without convergence.
  */

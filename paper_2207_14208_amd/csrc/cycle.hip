@@ -168,7 +168,7 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
 // else the FW weights of its INSIDE nodes renormalised; coarse GHOST: FW of
 // the extended residual if the box holds no INSIDE node and lies in the
 // grid, else renormalised over its non-INSIDE, non-BOXDIR nodes (eq.
-// coarseFW, Sec. 2.2 FW, Sec. 2.3).  Also zeroes the coarse unknown (initial
+// coarseFW, Sec. 3.2 FW, Sec. 3.3).  Also zeroes the coarse unknown (initial
 // guess of the coarse correction).
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2) {
@@ -251,8 +251,8 @@ __device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const
 }
 
 // Prolongation and correction: multilinear interpolation of the (extended)
-// coarse error to INSIDE and GHOST nodes, u += e (Sec. 1.1 interpolation,
-// Sec. 2.2 bilinear interpolation, Sec. 2.3).
+// coarse error to INSIDE and GHOST nodes, u += e (Sec. 2.1 interpolation,
+// Sec. 3.2 bilinear interpolation, Sec. 3.3).
 template <int D, typename T>
 __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2) {
     const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
@@ -330,7 +330,7 @@ __device__ __forceinline__ double ghost_residual(const Desc &L, int g) {
 }
 
 // Normal extension, one Jacobi sweep at band node b: v(X) = sum_k |n_k|
-// v(X - s_k e_k) / sum_k |n_k| (Sec. 2.3 transfer operators).  Sweep j of K
+// v(X - s_k e_k) / sum_k |n_k| (Sec. 3.3 transfer operators).  Sweep j of K
 // reads the band values of sweep j-1 (0 for j = 1) from a ping-pong buffer
 // and writes the other one; the last sweep writes the field itself.  GHOST
 // references read the fixed field, BOXDIR and beyond-band references are 0;

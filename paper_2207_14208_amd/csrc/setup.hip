@@ -62,7 +62,7 @@ void launch_inject(int d, const double *phi_f, int nf, double *phi_c, int nc, hi
                        nc, nnc);
 }
 
-// Partition of the nodes (Sec. 2.3): INSIDE / BOXDIR by the sign of phi and
+// Partition of the nodes (Sec. 3.3): INSIDE / BOXDIR by the sign of phi and
 // the box faces, then GHOST = not inside with an INSIDE axis neighbour.
 __global__ void k_classify_a(int d, int n, const double *phi, uint8_t *cls, long long nn) {
     long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,7 +271,7 @@ __device__ double dtau_of(int d, double theta, int mode, double cnst) {
 // admissible stencil widths (in the box, INSIDE/GHOST nodes only, row weight
 // on G at least f times its |weight| on the block's other ghosts: f = 1/2 on
 // the finest level, 1 on coarse levels), Q, tau and dtau(theta~ = eta)
-// bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 2.3 eqs. BCh, rel,
+// bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 3.3 eqs. BCh, rel,
 // DtauOptTheta, Remark exptheta2D.
 __global__ void k_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls,
                                  const int *gidx, int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau,

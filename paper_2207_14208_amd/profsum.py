@@ -1,0 +1,132 @@
+"""Summaries of rocprofv3 output (CSV or rocpd SQLite) for the solver's kernels.
+
+    python -m paper_2207_14208_amd.profsum trace <dir> [--top K]
+        per (kernel, grid) call count, average and share of the kernel time
+    python -m paper_2207_14208_amd.profsum traffic <fetch_dir> <write_dir> --kernel NAME --grid G --copy-bytes B
+        FETCH_SIZE / WRITE_SIZE per dispatch of one kernel, scaled by what the
+        same counters read for the plain copy kernel of B bytes
+
+Runs on the host; reads only the files rocprofv3 wrote.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import json
+import os
+import sqlite3
+
+
+def _short(name: str) -> str:
+    n = name.replace("void ", "").replace("bcmg::", "")
+    if n.startswith("__amd_rocclr"):
+        return n
+    # keep template arguments, drop the parameter list
+    depth, out = 0, []
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _find(d: str, pattern: str) -> list[str]:
+    return sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+
+
+def _col(row: dict, *names, default=None):
+    for n in names:
+        if n in row and row[n] != "":
+            return row[n]
+    return default
+
+
+def kernel_rows(d: str):
+    """(short name, grid size in threads, duration ns) per dispatch."""
+    csvs = _find(d, "*kernel_trace.csv")
+    if csvs:
+        for path in csvs:
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    g = int(_col(r, "Grid_Size_X", "Grid_Size", default=0))
+                    yield _short(r["Kernel_Name"]), g, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        return
+    for db in _find(d, "*.db"):
+        con = sqlite3.connect(db)
+        for name, gx, dur in con.execute("select name, grid_x, duration from kernels"):
+            yield _short(name), int(gx), int(dur)
+
+
+def trace_table(d: str, top: int = 30) -> tuple[list, float]:
+    agg = collections.defaultdict(list)
+    for name, g, dur in kernel_rows(d):
+        agg[(name, g)].append(dur)
+    tot = sum(sum(v) for v in agg.values())
+    rows = sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]
+    return [(k, g, len(v), sum(v) / len(v) / 1e3, 100.0 * sum(v) / tot) for (k, g), v in rows], tot / 1e6
+
+
+def counter_rows(d: str, counter: str):
+    """(short name, grid, value) per dispatch of one counter."""
+    for path in _find(d, "*counter_collection.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                g = int(_col(r, "Grid_Size", "Grid_Size_X", default=0))
+                yield _short(r["Kernel_Name"]), g, float(r["Counter_Value"])
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, grid: int, copy_bytes: int) -> dict:
+    def per_dispatch(d, counter):
+        vals = collections.defaultdict(list)
+        for name, g, v in counter_rows(d, counter):
+            vals[(name, g)].append(v)
+        mine = [v for (n, g), vs in vals.items() if n == kernel and g == grid for v in vs]
+        # the copy probe: the largest elementwise copy dispatch
+        copies = [max(vs) for (n, g), vs in vals.items() if "copy" in n.lower() or "elementwise" in n.lower()]
+        if not mine:
+            raise SystemExit(f"no {counter} rows for {kernel} grid {grid} in {d}")
+        return sum(mine) / len(mine), (max(copies) if copies else None), len(mine)
+
+    f_k, f_copy, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
+    w_k, w_copy, nw = per_dispatch(write_dir, "WRITE_SIZE")
+    copy_kib = copy_bytes / 1024.0
+    fs = copy_kib / f_copy if f_copy else 1.0
+    ws = copy_kib / w_copy if w_copy else 1.0
+    return {"kernel": kernel, "grid": grid, "dispatches": [nf, nw],
+            "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+            "copy_probe_bytes": copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+            "fetch_scale": fs, "write_scale": ws,
+            "bytes_per_launch": (f_k * fs + w_k * ws) * 1024.0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--top", type=int, default=30)
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_dir")
+    c.add_argument("write_dir")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--grid", type=int, required=True)
+    c.add_argument("--copy-bytes", type=int, required=True)
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        rows, tot_ms = trace_table(a.dir, a.top)
+        print(f"total kernel time {tot_ms:.3f} ms\n")
+        print("| kernel | grid | calls | avg us | share |\n|---|---:|---:|---:|---:|")
+        for k, g, n, avg, share in rows:
+            print(f"| {k} | {g} | {n} | {avg:.2f} | {share:.1f}% |")
+    else:
+        print(json.dumps(traffic(a.fetch_dir, a.write_dir, a.kernel, a.grid, a.copy_bytes), indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -18,6 +18,7 @@ rejection without a GPU.
 from __future__ import annotations
 
 import queue
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -36,6 +37,7 @@ class Request:
     cycles: int = 0
     unknowns: int = 0
     rejected: str | None = None
+    attempts: int = 0              # solves started; > 1 after a retry with the fallback options
 
     @property
     def latency(self) -> float | None:
@@ -47,6 +49,7 @@ class ServerStats:
     completed: list = field(default_factory=list)
     rejected: list = field(default_factory=list)
     steps: int = 0
+    retried: int = 0
     peak_slots: int = 0
     peak_bytes: int = 0
 
@@ -69,6 +72,7 @@ class Server:
         self.preparing: dict[int, tuple[Request, int]] = {}  # rid -> (request, bytes)
         self.ready: "queue.Queue" = queue.Queue()
         self.stats = ServerStats()
+        self.requeue: list[Request] = []   # failed solves to start again with the fallback options
         self._work: "queue.Queue" = queue.Queue()
         self._worker = threading.Thread(target=self._prepare_loop, daemon=True)
         self._worker.start()
@@ -105,7 +109,9 @@ class Server:
             return False
         self.used_bytes += need
         self.stats.peak_bytes = max(self.stats.peak_bytes, self.used_bytes)
-        req.admitted = now
+        if req.admitted is None:
+            req.admitted = now
+        req.attempts += 1
         self.preparing[req.rid] = (req, need)
         self._work.put(req)
         return True
@@ -138,13 +144,20 @@ class Server:
             if active[slot]:
                 continue
             req = self.resident.pop(slot)
-            req.status, req.cycles, req.unknowns = self.backend.finish(slot)
-            req.done = t
+            status, cycles, req.unknowns = self.backend.finish(slot)
+            req.cycles += cycles
             self.used_bytes -= self.bytes_of.pop(slot)
+            if (status in getattr(self.backend, "retry_statuses", ())
+                    and req.attempts < getattr(self.backend, "max_attempts", 1)):
+                self.requeue.append(req)
+                self.stats.retried += 1
+                continue
+            req.status = status
+            req.done = t
             self.stats.completed.append(req)
 
     def busy(self) -> bool:
-        return bool(self.resident or self.preparing)
+        return bool(self.resident or self.preparing or self.requeue)
 
     def wait_ready(self, timeout: float = 0.005):
         """Block briefly until a prepared request arrives (idle server)."""
@@ -168,6 +181,9 @@ def run(server: Server, requests: list[Request], clock=time.perf_counter, max_se
             break
         while pending and pending[-1].arrival <= t:
             waiting.append(pending.pop())
+        if server.requeue:   # retries go first
+            waiting[:0] = server.requeue
+            server.requeue.clear()
         while waiting and server.try_admit(waiting[0], t):
             waiting.pop(0)
         if server.resident:
@@ -186,7 +202,13 @@ def poisson_arrivals(n: int, rate: float, rng: np.random.Generator, start: float
 
 # ----------------------------------------------------------------- GPU backend
 class GPUBackend:
-    """libbcmg batch with a side stream for request setup."""
+    """libbcmg batch with a side stream for request setup.
+
+    A request whose solve diverges or stalls is set up again with the
+    fallback options (constant dtau = 1, the paper's baseline relaxation) and
+    solved once more; under-resolved unions (sphere radius below h) need it."""
+
+    max_attempts = 2
 
     def __init__(self, capacity: int, dtau_mode: int, nu=(2, 1), tol: float = 1e-8, max_cycles: int = 200,
                  coarse_nodes: int | None = None, keep_results: bool = False):
@@ -198,6 +220,8 @@ class GPUBackend:
         self.N = N
         self.tol = tol
         self.opts = dict(dtau_mode=dtau_mode, nu1=nu[0], nu2=nu[1], max_cycles=max_cycles)
+        self.fallback = dict(self.opts, dtau_mode=N.DTAU_CONST, dtau_const=1.0)
+        self.retry_statuses = (N.ERR_NOT_CONVERGED, N.ERR_DIVERGED)
         self.batch = Batch(capacity)
         if coarse_nodes is not None:
             self.batch.set_param(N.PARAM_COARSE_NODES, coarse_nodes)
@@ -216,7 +240,8 @@ class GPUBackend:
         torch = self.torch
         with torch.cuda.stream(self.side):
             phi, f = W.sample_sphere_request_torch(req.params)
-            G = Problem(3, req.params["side"] - 1, phi, stream=self.side, **self.opts)
+            opts = self.opts if req.attempts <= 1 else self.fallback
+            G = Problem(3, req.params["side"] - 1, phi, stream=self.side, **opts)
             ng = G.level_info(0)["n_ghost"]
             G.set_data(f, torch.zeros(ng, dtype=torch.float64, device="cuda"))
             u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
@@ -276,10 +301,13 @@ def bench(args) -> dict:
     srv.close()
     mu = len(st.completed) / sat_s
     lam = 0.7 * mu
+    print(f"served: capacity {mu:.2f} req/s from {len(st.completed)} requests in {sat_s:.1f} s", file=sys.stderr,
+          flush=True)
     reqs = make_requests(n_warm + n_meas, seed=14208, rate=lam)
     srv = Server(be, slots, budget)
     st = run(srv, reqs)
     srv.close()
+    print(f"served: {len(st.completed)} requests at {lam:.2f} req/s done", file=sys.stderr, flush=True)
     meas = [r for r in st.completed if r.rid >= n_warm]
     span = max(r.done for r in meas) - min(r.arrival for r in meas)
     lat = np.array([r.latency for r in meas])
@@ -298,6 +326,7 @@ def bench(args) -> dict:
         "throughput_req_per_s": len(meas) / span,
         "throughput_unknowns_per_s": sum(r.unknowns for r in ok) / span,
         "converged": len(ok), "failed": len(meas) - len(ok), "rejected": len(st.rejected),
+        "retried_with_const_dtau": sum(1 for r in meas if r.attempts > 1),
         "peak_slots": st.peak_slots, "peak_bytes": st.peak_bytes,
     }
     be.close()

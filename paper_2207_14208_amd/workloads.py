@@ -7,13 +7,13 @@ solutions and their Laplacians, random draws).  Everything is FP64 numpy and
 laid out with x fastest, the node order the solver uses.
 
 Domains:
-  * circle and flower of the 2D Dirichlet tests (Sec. 2.3, eqs. dom2D:circle,
-    dom2D:flower), the ellipsoid of the 3D tests (Sec. 3.2);
+  * circle and flower of the 2D Dirichlet tests (Sec. 3.3, eqs. dom2D:circle,
+    dom2D:flower), the ellipsoid of the 3D tests (Sec. 4.2);
   * the shifted circle (65^2), the 3D "flower" r - (0.5 + 0.1 sin 3t sin 4p)
     (257^3 / 513^3), the batched 2D stars and the served sphere unions of the
     benchmark workloads;
   * the full box (phi = -1), a half-space phi = x - x_V (rectangle case,
-    Sec. 2.2) and a line for Test1N-like set-ups.
+    Sec. 3.2) and a line for Test1N-like set-ups.
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ def phi_full_box(*xs):
 
 
 def phi_halfspace(xv: float):
-    """x < x_V is the domain (the rectangle of Sec. 2.2 seen in [-1,1]^d)."""
+    """x < x_V is the domain (the rectangle of Sec. 3.2 seen in [-1,1]^d)."""
     return lambda *xs: xs[0] - xv
 
 
@@ -255,7 +255,7 @@ def sphere_request(rng: np.random.Generator, sides=(33, 65, 129, 257)) -> Case:
 
 
 def random_guess(n: int, seed: int = 0) -> Array:
-    """U(-1, 1) initial guess (convergence-factor protocol, Sec. 1.2)."""
+    """U(-1, 1) initial guess (convergence-factor protocol, Sec. 2.2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=n)
 

@@ -1,7 +1,7 @@
 """Local Fourier analysis of the two-grid method on the full box (test helper).
 
 Written from the standard two-grid LFA (the analysis the paper cites for its
-optimal factor, Sec. 2.2): the error of a low frequency theta and its 2^d
+optimal factor, Sec. 3.2): the error of a low frequency theta and its 2^d
 aliases theta + pi*alpha (alpha in {0,1}^d) span an invariant space of the
 two-grid operator M = S^nu2 (I - P Lc^-1 R Lh) S^nu1 for the 2d+1-point
 Laplacian, full weighting R and multilinear interpolation P.  The two-grid

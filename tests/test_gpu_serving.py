@@ -33,14 +33,17 @@ def test_served_requests_match_solo_solves_and_oracle():
     for r in st.completed:
         p = r.params
         phi, f = W.sample_sphere_request_torch(p)
-        G = Problem(3, p["side"] - 1, phi, dtau_mode=N.DTAU_OPT_POLY, max_cycles=200)
+        opts = be.opts if r.attempts == 1 else be.fallback
+        G = Problem(3, p["side"] - 1, phi, **opts)
         ng = G.level_info(0)["n_ghost"]
         G.set_data(f, torch.zeros(ng, dtype=torch.float64, device="cuda"))
         u = G.initial_guess()
         s, _ = G.solve(u, 1e-8)
-        assert (s.status, s.cycles) == (r.status, r.cycles), r.rid
+        assert s.status == r.status, r.rid
+        if r.attempts == 1:
+            assert s.cycles == r.cycles, r.rid
         assert torch.equal(u, be.results[r.rid]), r.rid
-    small = [r for r in st.completed if r.params["side"] == 33 and r.status == 0][:2]
+    small = [r for r in st.completed if r.params["side"] == 33 and r.status == 0 and r.attempts == 1][:2]
     assert small
     for r in small:
         phi, f = W.sample_sphere_request_torch(r.params)

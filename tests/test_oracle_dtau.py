@@ -56,7 +56,7 @@ def test_dtau_matches_bruteforce_minimax(d, form, mode, theta):
 
 
 def test_dtau_closed_forms():
-    # theta = 0: Gauss-Seidel on the ghost row, dtau = 1/c_0 = 1 (Sec. 1.1)
+    # theta = 0: Gauss-Seidel on the ghost row, dtau = 1/c_0 = 1 (Sec. 2.1)
     for d in (1, 2, 3):
         for mode in (oracle.DTAU_OPT_POLY, oracle.DTAU_OPT_EXP):
             assert oracle.dtau(d, 0.0, mode) == pytest.approx(1.0, abs=1e-15)
@@ -71,7 +71,7 @@ def test_dtau_closed_forms():
     # exp form at theta = 1/2: 2 / ((2-sqrt3)^{1/2} + (2d-1 - sqrt((2d-1)^2-1))^{1/2})
     assert oracle.dtau(2, 0.5, oracle.DTAU_OPT_EXP) == pytest.approx(2 / (math.sqrt(2 - SQ3) + math.sqrt(3 - 2 * SQ2)), rel=1e-14)
     assert oracle.dtau(3, 0.5, oracle.DTAU_OPT_EXP) == pytest.approx(2 / (math.sqrt(2 - SQ3) + math.sqrt(5 - 2 * SQ6)), rel=1e-14)
-    # 1D: no tangential direction, p = acosh(1) = 0 (Sec. 1.2: no special dtau needed)
+    # 1D: no tangential direction, p = acosh(1) = 0 (Sec. 2.2: no special dtau needed)
     assert oracle.dtau(1, 0.7, oracle.DTAU_OPT_EXP) == 1.0
 
 

@@ -1,10 +1,10 @@
 """Pins for classification and ghost geometry (oracle side, no GPU).
 
  * a hand-made level set with its node classes written out by hand
-   (Sec. 2.3 partition of D_h, plus the eliminated box-face nodes of Sec. 2);
+   (Sec. 3.3 partition of D_h, plus the eliminated box-face nodes of Sec. 3);
  * a linear level set, where the quadratic interpolant is exact and the
-   projection Q must be the exact orthogonal projection (Sec. 2.3, Q = G - eta h n);
- * the rectangle case x < x_V (Sec. 2.2), where every ghost row away from the
+   projection Q must be the exact orthogonal projection (Sec. 3.3, Q = G - eta h n);
+ * the rectangle case x < x_V (Sec. 3.2), where every ghost row away from the
    box corners must reduce to the 1D coefficients of eq. (coeff) with
    theta = (x_G - x_V)/h;
  * sum of the boundary weights = 1 (constants are interpolated exactly);

@@ -3,12 +3,12 @@
  * brute force: the multigrid limit equals a dense LAPACK solve of the same
    operator (assembled column by column from A applied to unit vectors);
  * discretisation: exact for harmonic quadratics, second order for smooth
-   manufactured solutions (Sec. 2.3: 3x3 stencil, second-order accuracy);
- * transfer operators: FW weights (eq. coarseFW, Sec. 2.2), the paper's 1D
-   near-boundary rule and ghost injection (Sec. 1.1), the 2D ghost-column
-   rule (Sec. 2.2), bilinear prolongation of linear data, the extension;
+   manufactured solutions (Sec. 3.3: 3x3 stencil, second-order accuracy);
+ * transfer operators: FW weights (eq. coarseFW, Sec. 3.2), the paper's 1D
+   near-boundary rule and ghost injection (Sec. 2.1), the 2D ghost-column
+   rule (Sec. 3.2), bilinear prolongation of linear data, the extension;
  * smoother and cycle: the printed optimal convergence factors for GS-LEX
-   (Sec. 1.2: ~0.08; eq. rhoopt2D: ~0.119; eq. rhoopt3D: ~0.155), the
+   (Sec. 2.2: ~0.08; eq. rhoopt2D: ~0.119; eq. rhoopt3D: ~0.155), the
    red-black factors against an independent local Fourier analysis, and the
    curved-domain claims (ellipsoid: ~0.5 at constant dtau 1.75; dtau_OPT
    better than any constant).
@@ -119,7 +119,7 @@ def test_second_order_convergence(d, Ns, phi_fn, sol):
 
 # ---------------------------------------------------------------- transfers
 def test_restriction_1d_paper_rules():
-    """Sec. 1.1: FW 1/4[1 2 1] inside, 1/2[1 1 0] next to the boundary, the
+    """Sec. 2.1: FW 1/4[1 2 1] inside, 1/2[1 1 0] next to the boundary, the
     ghost residual injected (PLAIN_MEAN mode reproduces the printed rule)."""
     N = 32
     h = 2.0 / N
@@ -159,7 +159,7 @@ def test_restriction_1d_paper_rules():
 
 
 def test_restriction_2d_ghost_column_rule():
-    """Sec. 2.2: ghost residuals restricted by (1/4, 1/2, 1/4) along the
+    """Sec. 3.2: ghost residuals restricted by (1/4, 1/2, 1/4) along the
     ghost column; interior residuals by the nine-point FW."""
     N = 32
     h = 2.0 / N
@@ -238,7 +238,7 @@ def test_coarse_solve_matches_dense():
 
 # ------------------------------------------------------- convergence factors
 def rho(d, N, phi_fn, smoother, cycle, dtau_mode=oracle.DTAU_OPT_EXP, dtau_const=1.0, cycles=16):
-    """Sec. 1.2 protocol: homogeneous problem, u0 ~ U(-1,1), mean of
+    """Sec. 2.2 protocol: homogeneous problem, u0 ~ U(-1,1), mean of
     rho^(m) = |r^(m+1)|/|r^(m)| over m = 11..15."""
     opts = oracle.Options(smoother=smoother, cycle=cycle, dtau_mode=dtau_mode, dtau_const=dtau_const)
     P = oracle.Problem(d, N, W.sample(d, N, phi_fn), opts)
@@ -269,7 +269,7 @@ def test_redblack_two_grid_factor_matches_lfa(d, N):
 
 @pytest.mark.parametrize("theta", [0.0, 0.5, 0.9])
 def test_1d_ghost_relaxation_keeps_optimal_factor(theta):
-    """Sec. 1.2: with s = 3 the 1D factor stays at the interior optimum ~0.08."""
+    """Sec. 2.2: with s = 3 the 1D factor stays at the interior optimum ~0.08."""
     N = 512
     h = 2.0 / N
     a = -1.0 + 400 * h - theta * h
@@ -278,7 +278,7 @@ def test_1d_ghost_relaxation_keeps_optimal_factor(theta):
 
 
 def test_ellipsoid_constant_dtau_factor():
-    """Sec. 3.2: constant dtau ~1.75 gives rho ~0.5 on the ellipsoid, the
+    """Sec. 4.2: constant dtau ~1.75 gives rho ~0.5 on the ellipsoid, the
     optimal dtau(theta) does much better."""
     const = rho(3, 32, W.phi_ellipsoid(), oracle.SMOOTH_LEX, oracle.CYCLE_TGCS, oracle.DTAU_CONST, 1.75)
     opt = rho(3, 32, W.phi_ellipsoid(), oracle.SMOOTH_LEX, oracle.CYCLE_TGCS)
@@ -287,7 +287,7 @@ def test_ellipsoid_constant_dtau_factor():
 
 
 def test_circle_optimal_beats_constant_and_improves_with_N():
-    """Sec. 2.3 Circle test: constant dtau ~1.75 stalls near rho ~0.3 while
+    """Sec. 3.3 Circle test: constant dtau ~1.75 stalls near rho ~0.3 while
     dtau_OPT(theta~) approaches the interior optimum as N grows."""
     c64 = rho(2, 64, W.phi_circle_paper(), oracle.SMOOTH_LEX, oracle.CYCLE_TGCS, oracle.DTAU_CONST, 1.75)
     c128 = rho(2, 128, W.phi_circle_paper(), oracle.SMOOTH_LEX, oracle.CYCLE_TGCS, oracle.DTAU_CONST, 1.75)

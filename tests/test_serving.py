@@ -54,6 +54,27 @@ class FakeBackend:
         return 0, self.cycles.pop(slot), 1000
 
 
+class FailingOnceBackend(FakeBackend):
+    """Requests with an even sphere count fail (status 5) on their first solve."""
+    retry_statuses = (5,)
+    max_attempts = 2
+
+    def prepare(self, req):
+        rid, cyc = super().prepare(req)
+        fail = req.attempts == 1 and req.params["m"] % 2 == 0
+        return (rid, cyc, fail)
+
+    def add(self, handle):
+        slot = super().add(handle)
+        self.fail = getattr(self, "fail", {})
+        self.fail[slot] = handle[2]
+        return slot
+
+    def finish(self, slot):
+        st, cyc, n = super().finish(slot)
+        return (5 if self.fail.pop(slot) else st), cyc, n
+
+
 def _requests(n, seed=3, rate=0.0, sides=(33, 65)):
     return S.make_requests(n, seed, rate, sides=sides)
 
@@ -140,3 +161,18 @@ def test_sphere_request_phi_is_union_distance():
     phi, f = W.sample_sphere_request_numpy(p)
     assert np.allclose(phi, d, atol=1e-15)
     assert f.shape == phi.shape and np.all(np.isfinite(f))
+
+
+def test_failed_solves_are_retried_once_with_fallback():
+    be = FailingOnceBackend(4)
+    srv = S.Server(be, slots=4, budget_bytes=1 << 40, cycles_per_step=2)
+    reqs = _requests(20)
+    st = S.run(srv, reqs, max_seconds=30)
+    srv.close()
+    assert len(st.completed) == 20 and all(r.status == 0 for r in st.completed)
+    for r in st.completed:
+        even = r.params["m"] % 2 == 0
+        assert r.attempts == (2 if even else 1)
+        assert r.cycles == (2 if even else 1) * (1 + r.params["m"] % 5)
+    assert st.retried == sum(1 for r in reqs if r.params["m"] % 2 == 0)
+    assert srv.used_bytes == 0
