@@ -31,15 +31,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rb_sweep_flower257_fp64_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_14208_amd", "csrc", "cycle.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2207_14208_amd", "csrc", f) for f in ("seg.h", "rb_sweep.h")]
 
 
-def kernel_fingerprint(path: str = KERNEL_SRC) -> str:
-    """sha256 of the kernel source with comments and white space removed."""
+def kernel_fingerprint(paths=KERNEL_SRC) -> str:
+    """sha256 of the red-black sweep's source (the kernel and the segment
+    helpers it uses) with comments and white space removed."""
     import hashlib
     import re
-    with open(path) as fh:
-        src = fh.read()
+    src = ""
+    for path in paths:
+        with open(path) as fh:
+            src += fh.read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
     return hashlib.sha256(re.sub(r"\s+", "", src).encode()).hexdigest()

@@ -56,10 +56,13 @@ struct LevelH {
     double *phi = nullptr;
     int *gidx = nullptr, *gcode = nullptr, *gfb = nullptr;
     double *gtau = nullptr, *gdtau = nullptr, *geta = nullptr, *gn = nullptr, *gq = nullptr;
-    int *bidx = nullptr, *bref = nullptr;
-    double *bw = nullptr;
-    void *u = nullptr, *rhs = nullptr, *r = nullptr, *bufA = nullptr, *bufB = nullptr;
-    double *gdelta = nullptr;
+    int *bidx = nullptr;
+    int *eptr = nullptr, *eidx = nullptr;  // extension rows (CSR over ghost-list indices)
+    double *ecoef = nullptr;
+    int *rptr = nullptr, *ridx = nullptr;  // restriction rows of this level's ghosts (levels >= 1)
+    double *rcoef = nullptr;
+    void *u = nullptr, *rhs = nullptr, *r = nullptr;
+    double *gnew = nullptr;
     std::vector<Item> segs;  // desc field 0; patched when copied into a table
     // coarsest level
     int nc = 0, singular = 0;
@@ -99,8 +102,10 @@ struct Lists {
     int nbch = 0;
     Item *csegs = nullptr;
     int ncseg = 0;
-    Item *cbch = nullptr;
+    Item *cbch = nullptr;  // band chunks of the next coarser level (its extension before prolongation)
     int ncbch = 0;
+    Item *cgch = nullptr;  // ghost chunks of the next coarser level (restriction)
+    int ncgch = 0;
 };
 
 struct bcmg_batch {
@@ -220,14 +225,16 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
     D.gtau = V.gtau;
     D.gdtau = V.gdtau;
     D.bidx = V.bidx;
-    D.bref = V.bref;
-    D.bw = V.bw;
+    D.eptr = V.eptr;
+    D.eidx = V.eidx;
+    D.ecoef = V.ecoef;
+    D.rptr = V.rptr;
+    D.ridx = V.ridx;
+    D.rcoef = V.rcoef;
     D.u = u;
     D.rhs = rhs;
     D.r = r;
-    D.gdelta = V.gdelta;
-    D.bufA = V.bufA;
-    D.bufB = V.bufB;
+    D.gnew = V.gnew;
     D.nc = V.nc;
     D.singular = V.singular;
     D.ainv = V.ainv;
@@ -238,6 +245,82 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
 }
 
 // ------------------------------------------------------------------ setup
+// Extension rows of a level: K sweeps of count, prefix sum and write; the
+// rows of the last sweep are kept (see k_erow).
+bcmg_status build_ext_rows(bcmg_problem *P, LevelH &V, const int *bref, const double *bw, int *h_total) {
+    hipStream_t s = P->stream;
+    const int nb = (int)V.nb, K = P->opt.ext_iters;
+    bcmg_status st;
+    if (nb == 0 || K == 0) {  // eptr is zero-filled: every row empty
+        if ((st = dalloc_t(P, &V.eidx, 1)) || (st = dalloc_t(P, &V.ecoef, 1))) return st;
+        return BCMG_OK;
+    }
+    int *counts = nullptr, *pptr = nullptr, *pidx = nullptr;
+    double *pcf = nullptr;
+    HIPCHK(hipMallocAsync((void **)&counts, sizeof(int) * nb, s));
+    for (int j = 1; j <= K; j++) {
+        int *optr = j == K ? V.eptr : nullptr;
+        if (!optr) HIPCHK(hipMallocAsync((void **)&optr, sizeof(int) * (nb + 1), s));
+        launch_erow(P->d, V.N, V.cls, V.gidx, (int)V.ng, V.bidx, nb, bref, bw, j, pptr, pidx, pcf, nullptr, counts,
+                    nullptr, nullptr, s);
+        launch_scan(counts, nb, optr, s);
+        HIPCHK(hipMemcpyAsync(h_total, optr + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const size_t tot = (size_t)std::max(*h_total, 1);
+        int *oidx = nullptr;
+        double *ocf = nullptr;
+        if (j == K) {
+            if ((st = dalloc_t(P, &V.eidx, tot)) || (st = dalloc_t(P, &V.ecoef, tot))) return st;
+            oidx = V.eidx;
+            ocf = V.ecoef;
+        } else {
+            HIPCHK(hipMallocAsync((void **)&oidx, sizeof(int) * tot, s));
+            HIPCHK(hipMallocAsync((void **)&ocf, sizeof(double) * tot, s));
+        }
+        launch_erow(P->d, V.N, V.cls, V.gidx, (int)V.ng, V.bidx, nb, bref, bw, j, pptr, pidx, pcf, optr, counts,
+                    oidx, ocf, s);
+        if (pptr) {
+            HIPCHK(hipFreeAsync(pptr, s));
+            HIPCHK(hipFreeAsync(pidx, s));
+            HIPCHK(hipFreeAsync(pcf, s));
+        }
+        pptr = j == K ? nullptr : optr;
+        pidx = j == K ? nullptr : oidx;
+        pcf = j == K ? nullptr : ocf;
+    }
+    HIPCHK(hipFreeAsync(counts, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BCMG_OK;
+}
+
+// Restriction rows of the ghosts of level l >= 1 over the ghosts of level l-1.
+bcmg_status build_restrict_rows(bcmg_problem *P, int l, int *h_total) {
+    hipStream_t s = P->stream;
+    LevelH &C = P->lev[l];
+    const LevelH &F = P->lev[l - 1];
+    const int ng = (int)C.ng;
+    bcmg_status st;
+    if ((st = dalloc_t(P, &C.rptr, (size_t)ng + 1))) return st;
+    if (ng == 0) {
+        if ((st = dalloc_t(P, &C.ridx, 1)) || (st = dalloc_t(P, &C.rcoef, 1))) return st;
+        return BCMG_OK;
+    }
+    int *counts = nullptr;
+    HIPCHK(hipMallocAsync((void **)&counts, sizeof(int) * ng, s));
+    launch_rrow(P->d, C.N, C.gidx, ng, F.N, F.cls, F.gidx, (int)F.ng, F.bidx, (int)F.nb, F.eptr, F.eidx, F.ecoef,
+                P->opt.restrict_mode, nullptr, counts, nullptr, nullptr, s);
+    launch_scan(counts, ng, C.rptr, s);
+    HIPCHK(hipMemcpyAsync(h_total, C.rptr + ng, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const size_t tot = (size_t)std::max(*h_total, 1);
+    if ((st = dalloc_t(P, &C.ridx, tot)) || (st = dalloc_t(P, &C.rcoef, tot))) return st;
+    launch_rrow(P->d, C.N, C.gidx, ng, F.N, F.cls, F.gidx, (int)F.ng, F.bidx, (int)F.nb, F.eptr, F.eidx, F.ecoef,
+                P->opt.restrict_mode, C.rptr, counts, C.ridx, C.rcoef, s);
+    HIPCHK(hipFreeAsync(counts, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BCMG_OK;
+}
+
 bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratch_offsets, int *total_dev,
                         int *h_total) {
     LevelH &V = P->lev[l];
@@ -257,7 +340,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     const size_t ng = (size_t)std::max<long long>(V.ng, 1);
     if ((st = dalloc_t(P, &V.gidx, ng)) || (st = dalloc_t(P, &V.gcode, ng)) || (st = dalloc_t(P, &V.gfb, ng)) ||
         (st = dalloc_t(P, &V.gtau, 3 * ng)) || (st = dalloc_t(P, &V.gdtau, ng)) || (st = dalloc_t(P, &V.geta, ng)) ||
-        (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gdelta, ng)))
+        (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gnew, ng)))
         return st;
     launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
     launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
@@ -275,16 +358,21 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         HIPCHK(hipStreamSynchronize(s));
         V.nb = *h_total;
         const size_t nb = (size_t)std::max<long long>(V.nb, 1);
-        const size_t esz = P->fp32 ? 4 : 8;
-        if ((st = dalloc_t(P, &V.bidx, nb)) || (st = dalloc_t(P, &V.bref, 3 * nb)) ||
-            (st = dalloc_t(P, &V.bw, 3 * nb)) || (st = dalloc(P, &V.bufA, nb * esz)) ||
-            (st = dalloc(P, &V.bufB, nb * esz))) {
+        int *bref = nullptr;
+        double *bw = nullptr;
+        if ((st = dalloc_t(P, &V.bidx, nb)) || (st = dalloc_t(P, &V.eptr, nb + 1))) {
             hipFreeAsync(tmp, s);
             return st;
         }
+        HIPCHK(hipMallocAsync((void **)&bref, sizeof(int) * 3 * nb, s));
+        HIPCHK(hipMallocAsync((void **)&bw, sizeof(double) * 3 * nb, s));
         launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, V.bidx, total_dev, s);
-        launch_band_records(d, V.N, V.h, V.phi, V.cls, V.bidx, (int)V.nb, V.bref, V.bw, s);
+        launch_band_records(d, V.N, V.h, V.phi, V.cls, V.bidx, (int)V.nb, bref, bw, s);
         HIPCHK(hipFreeAsync(tmp, s));
+        st = build_ext_rows(P, V, bref, bw, h_total);
+        HIPCHK(hipFreeAsync(bref, s));
+        HIPCHK(hipFreeAsync(bw, s));
+        if (st) return st;
     }
     // row segments of INSIDE/GHOST nodes
     {
@@ -516,6 +604,12 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
             return bail(st);
         }
     }
+    for (int l = 1; l < L; l++) {
+        if ((st = build_restrict_rows(P, l, h_total))) {
+            hipHostFree(h_total);
+            return bail(st);
+        }
+    }
     hipHostFree(h_total);
     if ((st = setup_coarse(P))) return bail(st);
     if ((st = dalloc_t(P, &P->rhs64, P->lev[0].nn))) return bail(st);
@@ -671,8 +765,7 @@ bcmg_status bcmg_level_extend(bcmg_problem *P, int32_t l, double *v) {
     if (!v) return fail(BCMG_ERR_INVALID, "null argument");
     void *pu[1] = {v}, *pr[1] = {P->lev[l].rhs}, *px[1] = {P->lev[l].r};
     if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
-    launch_extend(P->d, 0, P->d_step, P->d_stepitems + P->off_bch[l], P->n_bch[l], 0, P->opt.ext_iters, P->d_stepst,
-                  P->stream);
+    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l], P->n_bch[l], P->d_stepst, P->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
     return BCMG_OK;
@@ -685,7 +778,8 @@ bcmg_status bcmg_level_restrict(bcmg_problem *P, int32_t l, const double *rf, do
     void *pu[2] = {P->lev[l].u ? P->lev[l].u : (void *)rf, P->lev[l + 1].u}, *pr[2] = {P->lev[l].rhs, rc},
          *px[2] = {(void *)rf, P->lev[l + 1].r};
     if ((st = upload_step_descs(P, l, 2, pu, pr, px))) return st;
-    launch_restrict(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l + 1], P->n_seg[l + 1], P->d_stepst, P->stream);
+    launch_restrict(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l + 1], P->n_seg[l + 1],
+                    P->d_stepitems + P->off_gch[l + 1], P->n_gch[l + 1], P->d_stepst, P->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
     return BCMG_OK;
@@ -697,8 +791,7 @@ bcmg_status bcmg_level_prolong(bcmg_problem *P, int32_t l, double *ec, double *u
     if (l + 1 >= P->L || !ec || !uf) return fail(BCMG_ERR_INVALID, "bad argument");
     void *pu[2] = {uf, ec}, *pr[2] = {P->lev[l].rhs, P->lev[l + 1].rhs}, *px[2] = {P->lev[l].r, P->lev[l + 1].r};
     if ((st = upload_step_descs(P, l, 2, pu, pr, px))) return st;
-    launch_extend(P->d, 0, P->d_step, P->d_stepitems + P->off_bch[l + 1], P->n_bch[l + 1], 0, P->opt.ext_iters,
-                  P->d_stepst, P->stream);
+    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l + 1], P->n_bch[l + 1], P->d_stepst, P->stream);
     launch_prolong(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l], P->n_seg[l], P->d_stepst, P->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
@@ -834,8 +927,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     // work lists
     std::vector<Item> items;
     struct Off {
-        size_t seg, gch, bch, cseg, cbch;
-        int nseg, ngch, nbch, ncseg, ncbch;
+        size_t seg, gch, bch, cseg, cbch, cgch;
+        int nseg, ngch, nbch, ncseg, ncbch, ncgch;
     };
     std::vector<Off> off(A);
     auto add_segs = [&](int desc, const LevelH &V) {
@@ -878,6 +971,13 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
                 append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].nb);
             }
         o.ncbch = (int)(items.size() - o.cbch);
+        o.cgch = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L > a && a >= 1) {
+                const int l = b->prob[s]->L - 1 - a;
+                append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].ng);
+            }
+        o.ncgch = (int)(items.size() - o.cgch);
     }
     // finest lists over the outer descriptors, with per-slot norm ranges
     std::vector<NormRange> ranges(b->cap, NormRange{0, 0, 0, 0});
@@ -922,6 +1022,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         memset(&cp, 0, sizeof cp);
         cp.slot = s;
         cp.top = std::min(Ac, P->L - 1);
+        cp.ext_top = cp.top < P->L - 1 ? 1 : 0;
         for (int a2 = 0; a2 <= cp.top; a2++) {
             const int l = P->L - 1 - a2;
             const LevelH &V = P->lev[l];
@@ -988,6 +1089,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         L.ncseg = o.ncseg;
         L.cbch = b->d_items + o.cbch;
         L.ncbch = o.ncbch;
+        L.cgch = b->d_items + o.cgch;
+        L.ncgch = o.ncgch;
     }
     b->fsegs = b->d_items + fseg0;
     b->nfseg = nfseg;
@@ -1015,14 +1118,20 @@ static void timed_sweep(bcmg_batch *b, int a, int colour) {
     }
 }
 
-static void smooth(bcmg_batch *b, int a) {
+// one smoothing step on aligned level a; ext: band chunks to extend into
+// after the ghost step (the level's error before its prolongation)
+static void smooth(bcmg_batch *b, int a, const Item *ext = nullptr, int next = 0) {
     timed_sweep(b, a, 0);
     timed_sweep(b, a, 1);
     const Lists &L = b->lv[a];
-    launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream);
+    launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream, ext, next);
 }
 
-// one V(nu1, nu2) cycle over every slot, levels aligned at the coarsest grid
+// one V(nu1, nu2) cycle over every slot, levels aligned at the coarsest grid.
+// The extension of a level's error into its band (read by the prolongation
+// to the next finer level) rides on the last ghost step of its post-smoothing;
+// the aligned levels 0..Ac are cycled inside k_coarse_cycle, which extends
+// its top level itself.
 static void launch_vcycle(bcmg_batch *b) {
     const int d = b->d, f = b->fp32;
     hipStream_t s = b->stream;
@@ -1031,16 +1140,19 @@ static void launch_vcycle(bcmg_batch *b) {
         if (L.nseg == 0 && L.ngch == 0) continue;
         for (int i = 0; i < b->nu1; i++) smooth(b, a);
         launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s);
-        launch_extend(d, f, b->d_desc, L.bch, L.nbch, 1, b->K, b->d_state, s);
-        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, b->d_state, s);
+        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s);
     }
-    launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, b->K, s);
+    launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s);
     for (int a = b->Ac + 1; a < b->A; a++) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
-        launch_extend(d, f, b->d_desc, L.cbch, L.ncbch, 0, b->K, b->d_state, s);
         launch_prolong(d, f, b->d_desc, L.segs, L.nseg, b->d_state, s);
-        for (int i = 0; i < b->nu2; i++) smooth(b, a);
+        const Lists *U = a + 1 < b->A ? &b->lv[a + 1] : nullptr;  // extension for the next prolongation
+        for (int i = 0; i < b->nu2; i++) {
+            const bool last = i == b->nu2 - 1;
+            smooth(b, a, last && U ? U->cbch : nullptr, last && U ? U->ncbch : 0);
+        }
+        if (b->nu2 == 0 && U) launch_ext_gather(f, b->d_desc, U->cbch, U->ncbch, b->d_state, s);
     }
 }
 

@@ -1,10 +1,14 @@
 // Internal declarations shared by the HIP translation units of libbcmg.
 // Device data layout:
 //   * every level keeps dense node arrays (x fastest): class (uint8), u, rhs, r;
-//   * the work of a launch is a list of items: row segments of <= 64 nodes
+//   * the work of a launch is a list of items: row segments of <= 128 nodes
 //     (one wavefront each) or chunks of <= 256 ghost / band entries (one
 //     workgroup each); each item names a level descriptor, so one launch can
 //     serve many problems and levels at once (batches);
+//   * the normal extension of a level (K upwind Jacobi sweeps from zero) is a
+//     fixed linear map from the ghost values to the band values; it is built
+//     once at setup as sparse rows (CSR) and applied by one gather, and the
+//     restriction of ghost rows is stored the same way over the fine ghosts;
 //   * descriptors of one problem are contiguous, finest first, so the coarse
 //     level of descriptor i is i+1.
 #pragma once
@@ -45,11 +49,14 @@ struct alignas(16) Desc {
     const double *gtau;       // [3*ng]
     const double *gdtau;      // [ng]
     const int *bidx;          // band node indices, ascending
-    const int *bref;          // [3*nb] upwind references
-    const double *bw;         // [3*nb] normalised weights
+    const int *eptr;          // [nb+1] extension rows: v(band b) = sum ecoef * u(ghost eidx)
+    const int *eidx;          //   ghost-list indices, ascending within a row
+    const double *ecoef;
+    const int *rptr;          // [ng+1] restricted value of this level's ghost g (levels >= 1):
+    const int *ridx;          //   sum rcoef * r_fine(ridx), ridx = fine node indices
+    const double *rcoef;
     void *u, *rhs, *r;        // level arrays, element type = cycle precision
-    double *gdelta;           // [ng] ghost increments
-    void *bufA, *bufB;        // [nb] extension ping-pong
+    double *gnew;             // [ng] new ghost values of a Jacobi ghost step
     // coarsest level: dense inverse over INSIDE then GHOST unknowns
     int nc, singular;
     const double *ainv;       // [nc*nc]
@@ -78,7 +85,9 @@ struct CoarseLevel {
 
 // The aligned levels 0..top of one problem (0 = coarsest) run by k_coarse_cycle.
 struct alignas(16) CoarseProg {
-    int slot, top, pad0, pad1;
+    int slot, top;
+    int ext_top;  // 1 if the problem has a finer level above top: extend top's error for its prolongation
+    int pad;
     CoarseLevel lev[kMaxLevels];
 };
 

@@ -16,25 +16,10 @@
 // steps, which replaces a dozen dependent launches per level.
 #include "bcmg_internal.h"
 #include "launch.h"
+#include "rb_sweep.h"
+#include "seg.h"
 
 namespace bcmg {
-
-struct Seg {
-    long long p0;  // first node
-    int len, x0, yj, zk;
-};
-
-__device__ __forceinline__ Seg seg_of(const Item &it) {
-    Seg s;
-    s.p0 = it.y;
-    s.len = it.z >> 16;
-    s.x0 = it.z & 0xffff;
-    s.yj = it.w & 0xffff;
-    s.zk = it.w >> 16;
-    return s;
-}
-
-__device__ __forceinline__ long long clampi(long long q, long long nn) { return q < 0 ? 0 : (q >= nn ? nn - 1 : q); }
 
 __device__ __forceinline__ double lagrange(int w, int m, double t) {
     if (w == 1) return 1.0;
@@ -94,37 +79,6 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__res
 }
 
 // ------------------------------------------------------------ node updates
-// Interior Gauss-Seidel on the nodes of one colour of a segment (red:
-// i+j+k even), one node per lane.  eq. GSLEX_2D in red-black order:
-// u_P = (h^2 f_P + sum of the 2d neighbours) / (2d).
-template <int D, typename T>
-__device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, int colour) {
-    const Seg s = seg_of(it);
-    const int q = (((s.x0 + s.yj + s.zk) & 1) == colour ? 0 : 1) + 2 * lane;
-    if (q >= s.len) return;
-    const long long p = s.p0 + q;
-    T *__restrict__ u = (T *)L.u;
-    const T *__restrict__ f = (const T *)L.rhs;
-    const long long nn = L.nn;
-    const uint8_t c = L.cls[p];
-    const T fp = f[p];
-    const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
-    T ym = 0, yp = 0, zm = 0, zp = 0;
-    if (D >= 2) {
-        ym = u[clampi(p - L.sy, nn)];
-        yp = u[clampi(p + L.sy, nn)];
-    }
-    if (D >= 3) {
-        zm = u[clampi(p - L.sz, nn)];
-        zp = u[clampi(p + L.sz, nn)];
-    }
-    T sum = xp + xm;
-    if (D >= 2) sum += yp + ym;
-    if (D >= 3) sum += zp + zm;
-    if (c != C_INSIDE) return;
-    u[p] = ((T)L.h2 * fp + sum) / (T)(2 * D);
-}
-
 // Residual of the INSIDE rows of a segment (two nodes per lane); returns the
 // lane's sum of r^2.
 template <int D, typename Tu, typename Tr>
@@ -163,13 +117,11 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
     return r2;
 }
 
-// Restriction to one coarse node (fine level F, coarse level C): coarse
-// INSIDE: FW over the 3^d fine box around X = 2J if all of it is INSIDE,
-// else the FW weights of its INSIDE nodes renormalised; coarse GHOST: FW of
-// the extended residual if the box holds no INSIDE node and lies in the
-// grid, else renormalised over its non-INSIDE, non-BOXDIR nodes (eq.
-// coarseFW, Sec. 3.2 FW, Sec. 3.3).  Also zeroes the coarse unknown (initial
-// guess of the coarse correction).
+// Restriction (fine level F, coarse level C; eq. coarseFW, Sec. 3.2 FW,
+// Sec. 3.3).  Coarse INSIDE node: FW over the 3^d fine box around X = 2J if
+// all of it is INSIDE, else the FW weights of its INSIDE nodes renormalised
+// (or their plain mean).  Also zeroes the coarse unknown (initial guess of
+// the coarse correction).  Coarse GHOST nodes are done by restrict_ghost.
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2) {
     constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
@@ -193,7 +145,7 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
                 rv[m2 + R2][m1 + R1][m0 + 1] = (double)r[q];
             }
     const uint8_t cc = C.cls[pc];
-    if (cc != C_INSIDE && cc != C_GHOST) return;
+    if (cc != C_INSIDE) return;
     ((T *)C.u)[pc] = (T)0;
     double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
     bool all_ok = true;
@@ -211,15 +163,8 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
                     all_ok = false;
                     continue;
                 }
-                const uint8_t c = fc[m2 + R2][m1 + R1][m0 + 1];
-                bool take;
-                if (cc == C_INSIDE) {
-                    take = c == C_INSIDE;
-                    if (!take) all_ok = false;
-                } else {
-                    take = c != C_INSIDE && c != C_BOXDIR;
-                    if (c == C_INSIDE) all_ok = false;
-                }
+                const bool take = fc[m2 + R2][m1 + R1][m0 + 1] == C_INSIDE;
+                if (!take) all_ok = false;
                 const double v = rv[m2 + R2][m1 + R1][m0 + 1];
                 full += wgt * v;
                 if (take) {
@@ -237,6 +182,20 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
     else
         out = selw > 0.0 ? sel / selw : 0.0;
     ((T *)C.rhs)[pc] = (T)out;
+}
+
+// Restriction to coarse ghost g: its precomputed row over the fine ghost
+// residuals (FW or renormalised FW of the extended fine residual, with the
+// extension folded in); zeroes the coarse unknown.
+template <typename T>
+__device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g) {
+    const T *__restrict__ r = (const T *)F.r;
+    const int beg = C.rptr[g], end = C.rptr[g + 1];
+    double acc = 0.0;
+    for (int j = beg; j < end; j++) acc += C.rcoef[j] * (double)r[C.ridx[j]];
+    const long long pc = C.gidx[g];
+    ((T *)C.rhs)[pc] = (T)acc;
+    ((T *)C.u)[pc] = (T)0;
 }
 
 template <int D, typename T>
@@ -308,16 +267,15 @@ template <int D, typename T>
 __device__ __forceinline__ void ghost_delta(const Desc &L, int g) {
     const T *u = (const T *)L.u;
     const T *rhs = (const T *)L.rhs;
-    const double rg = (double)rhs[L.gidx[g]];
+    const long long p = L.gidx[g];
+    const double rg = (double)rhs[p];
     const double row = ghost_row<D, T>(L, g, u);
-    L.gdelta[g] = L.gdtau[g] * (rg - row);
+    L.gnew[g] = (double)(T)((double)u[p] + L.gdtau[g] * (rg - row));
 }
 
 template <typename T>
 __device__ __forceinline__ void ghost_apply(const Desc &L, int g) {
-    T *u = (T *)L.u;
-    const long long p = L.gidx[g];
-    u[p] = (T)((double)u[p] + L.gdelta[g]);
+    ((T *)L.u)[L.gidx[g]] = (T)L.gnew[g];
 }
 
 template <int D, typename Tu, typename Tr>
@@ -329,72 +287,20 @@ __device__ __forceinline__ double ghost_residual(const Desc &L, int g) {
     return r * r;
 }
 
-// Normal extension, one Jacobi sweep at band node b: v(X) = sum_k |n_k|
-// v(X - s_k e_k) / sum_k |n_k| (Sec. 3.3 transfer operators).  Sweep j of K
-// reads the band values of sweep j-1 (0 for j = 1) from a ping-pong buffer
-// and writes the other one; the last sweep writes the field itself.  GHOST
-// references read the fixed field, BOXDIR and beyond-band references are 0;
-// a zero weight sum gives the mean of the GHOST nodes of the 3^d box.
-template <int D, typename T>
-__device__ double ext_fallback(const Desc &L, const T *field, int b) {
-    long long x = L.bidx[b];
-    int I[3] = {0, 0, 0};
-    for (int k = 0; k < D; k++) {
-        I[k] = (int)(x % L.n);
-        x /= L.n;
+// Normal extension at band node b (Sec. 3.3 transfer operators): the K
+// upwind Jacobi sweeps from zero, folded at setup into a row over the ghost
+// values; gsrc gives the ghost values in list order (the new values of a
+// ghost step), or null to read them from the field.
+template <typename T>
+__device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *gsrc) {
+    T *field = (T *)L.u;
+    const int beg = L.eptr[b], end = L.eptr[b + 1];
+    double v = 0.0;
+    for (int j = beg; j < end; j++) {
+        const int g = L.eidx[j];
+        v += L.ecoef[j] * (gsrc ? gsrc[g] : (double)field[L.gidx[g]]);
     }
-    double sum = 0.0;
-    int cnt = 0;
-    const int lo2 = D >= 3 ? -1 : 0, hi2 = D >= 3 ? 1 : 0, lo1 = D >= 2 ? -1 : 0, hi1 = D >= 2 ? 1 : 0;
-    for (int m2 = lo2; m2 <= hi2; m2++)
-        for (int m1 = lo1; m1 <= hi1; m1++)
-            for (int m0 = -1; m0 <= 1; m0++) {
-                const int J0 = I[0] + m0, J1 = I[1] + m1, J2 = I[2] + m2;
-                if (J0 < 0 || J0 > L.N || (D >= 2 && (J1 < 0 || J1 > L.N)) || (D >= 3 && (J2 < 0 || J2 > L.N)))
-                    continue;
-                const long long q = J0 + J1 * L.sy + J2 * L.sz;
-                if (L.cls[q] == C_GHOST) {
-                    sum += (double)field[q];
-                    cnt++;
-                }
-            }
-    return cnt > 0 ? sum / cnt : 0.0;
-}
-
-template <int D, typename T>
-__device__ __forceinline__ void ext_sweep_node(const Desc &L, int which, int j, int K, int b) {
-    T *field = (T *)(which ? L.r : L.u);
-    const T *prev = (const T *)((j & 1) ? L.bufB : L.bufA);  // written by sweep j-1
-    T *next = (T *)((j & 1) ? L.bufA : L.bufB);
-    const int r0 = L.bref[3 * b];
-    double v;
-    if (r0 == kRefFallback) {
-        v = ext_fallback<D, T>(L, field, b);
-    } else {
-        double val[3], wk[3];
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            const int ref = L.bref[3 * b + k];
-            wk[k] = L.bw[3 * b + k];
-            if (ref >= 0)
-                val[k] = j >= 2 ? (double)prev[ref] : 0.0;
-            else if (ref == kRefZero)
-                val[k] = 0.0;
-            else
-                val[k] = (double)field[-(long long)ref - 1];
-        }
-        double num = 0.0, den = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            num += wk[k] * val[k];
-            den += wk[k];
-        }
-        v = den > 0.0 ? num / den : 0.0;
-    }
-    if (j == K)
-        field[L.bidx[b]] = (T)v;
-    else
-        next[b] = (T)v;
+    field[L.bidx[b]] = (T)v;
 }
 
 // Coarsest level: x = A^{-1} b over INSIDE then GHOST unknowns, in FP64, by
@@ -415,27 +321,12 @@ __device__ void coarse_solve_block(const Desc &L, double *b) {
 }
 
 // ----------------------------------------------------------------- kernels
-#define SEG_ITEM                                                  \
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   \
-    const int sidx = blockIdx.x * kWavesPerBlock + wave;          \
-    if (sidx >= nseg) return;                                     \
-    const Item it = items[sidx];                                  \
-    const Desc &L = descs[it.x];                                  \
-    if (!st[L.slot].active) return;
-
 #define CHUNK_ITEM                                                \
     const Item it = items[blockIdx.x];                            \
     const Desc &L = descs[it.x];                                  \
     if (!st[L.slot].active) return;                               \
     if ((int)threadIdx.x >= it.z) return;                         \
     const int e = it.y + threadIdx.x;
-
-template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void k_rb_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
-                                                     int nseg, int colour, const SlotState *__restrict__ st) {
-    SEG_ITEM
-    seg_rb<D, T>(L, it, lane, colour);
-}
 
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__ descs,
@@ -445,12 +336,24 @@ __global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__
     ghost_delta<D, T>(L, e);
 }
 
+// Ghost step, second half: the new ghost values into u (chunk blocks), and,
+// in the same launch, the extension of the new field into the band chunks
+// bch (their ghost values come from gnew, which this launch does not write).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__ descs,
-                                                        const Item *__restrict__ items,
+                                                        const Item *__restrict__ items, int ngch,
+                                                        const Item *__restrict__ bch,
                                                         const SlotState *__restrict__ st) {
-    CHUNK_ITEM
-    ghost_apply<T>(L, e);
+    if ((int)blockIdx.x < ngch) {
+        CHUNK_ITEM
+        ghost_apply<T>(L, e);
+        return;
+    }
+    const Item it = bch[blockIdx.x - ngch];
+    const Desc &L = descs[it.x];
+    if (!st[L.slot].active) return;
+    if ((int)threadIdx.x >= it.z) return;
+    ext_gather<T>(L, it.y + threadIdx.x, L.gnew);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -555,19 +458,30 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
     }
 }
 
-// One extension sweep over the band chunks.
-template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void k_ext_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
-                                                      int which, int j, int K, const SlotState *__restrict__ st) {
+// Extension of u into the band chunks (ghost values read from u).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ext_gather(const Desc *__restrict__ descs, const Item *__restrict__ items,
+                                                       const SlotState *__restrict__ st) {
     CHUNK_ITEM
-    ext_sweep_node<D, T>(L, which, j, K, e);
+    ext_gather<T>(L, e, nullptr);
 }
 
+// Restriction: coarse INSIDE rows by segment blocks, then coarse GHOST rows by
+// chunk blocks.
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ descs, const Item *__restrict__ items,
-                                                     int nseg, const SlotState *__restrict__ st) {
-    SEG_ITEM
-    seg_restrict<D, T>(L, descs[it.x - 1], it, lane);
+                                                     int nseg, const Item *__restrict__ gch, int nseg_blocks,
+                                                     const SlotState *__restrict__ st) {
+    if ((int)blockIdx.x < nseg_blocks) {
+        SEG_ITEM
+        seg_restrict<D, T>(L, descs[it.x - 1], it, lane);
+        return;
+    }
+    const Item it = gch[blockIdx.x - nseg_blocks];
+    const Desc &C = descs[it.x];
+    if (!st[C.slot].active) return;
+    if ((int)threadIdx.x >= it.z) return;
+    restrict_ghost<T>(C, descs[it.x - 1], it.y + threadIdx.x);
 }
 
 template <int D, typename T>
@@ -640,24 +554,23 @@ __device__ void blk_smooth(const Desc *descs, const Item *items, const CoarseLev
     __syncthreads();
 }
 
-template <int D, typename T>
-__device__ void blk_extend(const Desc *descs, const Item *items, const CoarseLevel &lv, int which, int K) {
+// Extension of u into the band of one level (after a workgroup barrier).
+template <typename T>
+__device__ void blk_extend(const Desc *descs, const Item *items, const CoarseLevel &lv) {
     const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
-    for (int j = 1; j <= K; j++) {
-        for (int c = grp; c < lv.nbch; c += ngrp) {
-            const Item it = items[lv.bch + c];
-            if (t < it.z) ext_sweep_node<D, T>(descs[it.x], which, j, K, it.y + t);
-        }
-        __syncthreads();
+    for (int c = grp; c < lv.nbch; c += ngrp) {
+        const Item it = items[lv.bch + c];
+        if (t < it.z) ext_gather<T>(descs[it.x], it.y + t, nullptr);
     }
+    __syncthreads();
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__restrict__ descs,
                                                                  const Item *__restrict__ items,
                                                                  const CoarseProg *__restrict__ progs,
-                                                                 const SlotState *__restrict__ st, int nu1, int nu2,
-                                                                 int K) {
+                                                                 const SlotState *__restrict__ st, int nu1,
+                                                                 int nu2) {
     const CoarseProg &P = progs[blockIdx.x];
     if (!st[P.slot].active) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -675,11 +588,14 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
             if (t < it.z) ghost_residual<D, T, T>(descs[it.x], it.y + t);
         }
         __syncthreads();
-        blk_extend<D, T>(descs, items, lv, 1, K);
         const CoarseLevel &cv = P.lev[a - 1];
         for (int s = wave; s < cv.nseg; s += kCoarseWaves) {
             const Item it = items[cv.seg + s];
             seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane);
+        }
+        for (int c = grp; c < cv.ngch; c += ngrp) {
+            const Item it = items[cv.gch + c];
+            if (t < it.z) restrict_ghost<T>(descs[it.x], descs[it.x - 1], it.y + t);
         }
         __syncthreads();
     }
@@ -694,7 +610,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
     }
     for (int a = 1; a <= P.top; a++) {
         const CoarseLevel &lv = P.lev[a];
-        blk_extend<D, T>(descs, items, P.lev[a - 1], 0, K);
+        blk_extend<T>(descs, items, P.lev[a - 1]);
         for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
             const Item it = items[lv.seg + s];
             seg_prolong<D, T>(descs[it.x], descs[it.x + 1], it, lane);
@@ -702,6 +618,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
         __syncthreads();
         for (int i = 0; i < nu2; i++) blk_smooth<D, T>(descs, items, lv);
     }
+    // the error of the top level, extended for the prolongation that follows
+    if (P.ext_top) blk_extend<T>(descs, items, P.lev[P.top]);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -725,15 +643,15 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
 }
 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
-                        hipStream_t s) {
-    if (ngch <= 0) return;
-    dim3 g(ngch), b(kBlock);
+                        hipStream_t s, const Item *bch, int nbch) {
+    if (ngch <= 0 && nbch <= 0) return;
+    dim3 g(ngch), ga(ngch + nbch), b(kBlock);
     if (fp32) {
-        DISPATCH_D(d, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
-        hipLaunchKernelGGL((k_ghost_apply<float>), g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_D(d, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
+        hipLaunchKernelGGL((k_ghost_apply<float>), ga, b, 0, s, descs, gch, ngch, bch, st);
     } else {
-        DISPATCH_D(d, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
-        hipLaunchKernelGGL((k_ghost_apply<double>), g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_D(d, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
+        hipLaunchKernelGGL((k_ghost_apply<double>), ga, b, 0, s, descs, gch, ngch, bch, st);
     }
 }
 
@@ -772,26 +690,23 @@ void launch_norm_finish(const NormRange *ranges, int nslots, const double *parti
                        st, rtol2, hist, hist_stride, mode, out);
 }
 
-void launch_extend(int d, int fp32, const Desc *descs, const Item *bch, int nbch, int which, int K,
-                   const SlotState *st, hipStream_t s) {
+void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, const SlotState *st, hipStream_t s) {
     if (nbch <= 0) return;
-    dim3 g(nbch), b(kBlock);
-    for (int j = 1; j <= K; j++) {
-        if (fp32)
-            DISPATCH_D(d, k_ext_sweep, float, g, b, 0, s, descs, bch, which, j, K, st);
-        else
-            DISPATCH_D(d, k_ext_sweep, double, g, b, 0, s, descs, bch, which, j, K, st);
-    }
+    if (fp32)
+        hipLaunchKernelGGL((k_ext_gather<float>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, st);
+    else
+        hipLaunchKernelGGL((k_ext_gather<double>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, st);
 }
 
-void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const SlotState *st,
-                     hipStream_t s) {
-    if (nseg <= 0) return;
-    dim3 g(blocks_for_segs(nseg)), b(kBlock);
+void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
+                     const SlotState *st, hipStream_t s) {
+    const int sb = blocks_for_segs(nseg);
+    if (sb + ncgch <= 0) return;
+    dim3 g(sb + ncgch), b(kBlock);
     if (fp32)
-        DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, st);
+        DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, cgch, sb, st);
     else
-        DISPATCH_D(d, k_restrict, double, g, b, 0, s, descs, csegs, nseg, st);
+        DISPATCH_D(d, k_restrict, double, g, b, 0, s, descs, csegs, nseg, cgch, sb, st);
 }
 
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
@@ -813,13 +728,13 @@ void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const Sl
 }
 
 void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
-                         const SlotState *st, int nu1, int nu2, int K, hipStream_t s) {
+                         const SlotState *st, int nu1, int nu2, hipStream_t s) {
     if (nprog <= 0) return;
     dim3 g(nprog), b(kCoarseThreads);
     if (fp32)
-        DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2, K);
+        DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2);
     else
-        DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2, K);
+        DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2);
 }
 
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,

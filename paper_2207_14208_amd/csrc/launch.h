@@ -8,24 +8,26 @@ namespace bcmg {
 // ---- cycle kernels (cycle.hip); fp32 selects the element type of u/rhs/r ----
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s);
+// Jacobi ghost step (new values into gnew, then applied); with bch, the
+// applying launch also extends the new field into the band chunks bch.
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
-                        hipStream_t s);
+                        hipStream_t s, const Item *bch = nullptr, int nbch = 0);
 // tu32/tr32: element types of (u, rhs) and r; norm: write partial sums of r^2
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
                      const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s);
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s);
-// which: 0 extends u, 1 extends r
-void launch_extend(int d, int fp32, const Desc *descs, const Item *bch, int nbch, int which, int K,
-                   const SlotState *st, hipStream_t s);
-void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const SlotState *st,
-                     hipStream_t s);
+// extension of u into the band chunks bch (ghost values read from u)
+void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, const SlotState *st, hipStream_t s);
+// restriction into the coarse segments csegs (INSIDE rows) and coarse ghost chunks cgch
+void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
+                     const SlotState *st, hipStream_t s);
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
                     hipStream_t s);
 void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s);
 // one workgroup per program: the V-cycle on the program's coarse levels
 void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
-                         const SlotState *st, int nu1, int nu2, int K, hipStream_t s);
+                         const SlotState *st, int nu1, int nu2, hipStream_t s);
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
                       hipStream_t s);
 
@@ -46,6 +48,13 @@ void launch_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng,
                       hipStream_t s);
 void launch_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,
                          int *bref, double *bw, hipStream_t s);
+void launch_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb, const int *bref,
+                 const double *bw, int j, const int *pptr, const int *pidx, const double *pcf, const int *optr,
+                 int *counts, int *oidx, double *ocf, hipStream_t s);
+void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f, int ngf,
+                 const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
+                 int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf, hipStream_t s);
+void launch_scan(const int *counts, int n, int *ptr, hipStream_t s);
 void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s);
 void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
                          const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s);

@@ -1,0 +1,48 @@
+// Red-black Gauss-Seidel sweep of the interior (INSIDE) rows: one colour of
+// one row segment per wavefront.
+#pragma once
+
+#include "seg.h"
+
+namespace bcmg {
+
+// ------------------------------------------------------------ node updates
+// Interior Gauss-Seidel on the nodes of one colour of a segment (red:
+// i+j+k even), one node per lane.  eq. GSLEX_2D in red-black order:
+// u_P = (h^2 f_P + sum of the 2d neighbours) / (2d).
+template <int D, typename T>
+__device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, int colour) {
+    const Seg s = seg_of(it);
+    const int q = (((s.x0 + s.yj + s.zk) & 1) == colour ? 0 : 1) + 2 * lane;
+    if (q >= s.len) return;
+    const long long p = s.p0 + q;
+    T *__restrict__ u = (T *)L.u;
+    const T *__restrict__ f = (const T *)L.rhs;
+    const long long nn = L.nn;
+    const uint8_t c = L.cls[p];
+    const T fp = f[p];
+    const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
+    T ym = 0, yp = 0, zm = 0, zp = 0;
+    if (D >= 2) {
+        ym = u[clampi(p - L.sy, nn)];
+        yp = u[clampi(p + L.sy, nn)];
+    }
+    if (D >= 3) {
+        zm = u[clampi(p - L.sz, nn)];
+        zp = u[clampi(p + L.sz, nn)];
+    }
+    T sum = xp + xm;
+    if (D >= 2) sum += yp + ym;
+    if (D >= 3) sum += zp + zm;
+    if (c != C_INSIDE) return;
+    u[p] = ((T)L.h2 * fp + sum) / (T)(2 * D);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_rb_sweep(const Desc *__restrict__ descs, const Item *__restrict__ items,
+                                                     int nseg, int colour, const SlotState *__restrict__ st) {
+    SEG_ITEM
+    seg_rb<D, T>(L, it, lane, colour);
+}
+
+}  // namespace bcmg

@@ -491,6 +491,224 @@ void launch_band_records(int d, int N, double h, const double *phi, const uint8_
     hipLaunchKernelGGL(k_band_records, dim3((nb + 127) / 128), dim3(128), 0, s, d, N, h, phi, cls, bidx, nb, bref, bw);
 }
 
+// ------------------------------------------------- extension and restriction rows
+// The normal extension (K upwind Jacobi sweeps from zero, Sec. 3.3 transfer
+// operators) is linear in the ghost values, so its result on the band is a
+// fixed sparse map v(X) = sum_j c_j u(G_j).  The rows are built sweep by sweep
+// (count, prefix sum, write): the row of sweep j at a band node combines, with
+// the weights |n_k| / sum_k |n_k|, the ghosts it references directly and the
+// rows of sweep j-1 of the band nodes it references; a node whose weights sum
+// to zero takes the mean of the GHOST nodes of its 3^d box.  Rows are sorted
+// by ghost-list index without repeats.
+
+constexpr int kMaxSrc = 27;
+
+__device__ int find_sorted(const int *a, int n, int q) {
+    int lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = a[mid];
+        if (v == q) return mid;
+        if (v < q)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+// Merge of ns sorted sparse rows with weights w: returns the number of
+// distinct indices; writes them (mapped through map when given) and their
+// coefficients sum_s w_s c_s when oidx is not null.
+__device__ int merge_rows(const int *const *idx, const double *const *cf, const int *len, const double *w, int ns,
+                          const int *map, int *oidx, double *ocf) {
+    int pos[kMaxSrc];
+    for (int t = 0; t < ns; t++) pos[t] = 0;
+    int n = 0;
+    while (true) {
+        int m = INT32_MAX;
+        for (int t = 0; t < ns; t++)
+            if (pos[t] < len[t] && idx[t][pos[t]] < m) m = idx[t][pos[t]];
+        if (m == INT32_MAX) break;
+        double c = 0.0;
+        for (int t = 0; t < ns; t++)
+            if (pos[t] < len[t] && idx[t][pos[t]] == m) {
+                c += w[t] * cf[t][pos[t]];
+                pos[t]++;
+            }
+        if (oidx) {
+            oidx[n] = map ? map[m] : m;
+            ocf[n] = c;
+        }
+        n++;
+    }
+    return n;
+}
+
+// Sweep j (1..K) of the extension rows of every band node b.  Count mode
+// when optr is null (counts[b] = row length), else write mode.
+__global__ void k_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb,
+                       const int *bref, const double *bw, int j, const int *pptr, const int *pidx,
+                       const double *pcf, const int *optr, int *counts, int *oidx, double *ocf) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int *idx[kMaxSrc];
+    const double *cf[kMaxSrc];
+    int len[kMaxSrc], one[kMaxSrc];
+    double w[kMaxSrc];
+    const double unit = 1.0;
+    int ns = 0;
+    if (bref[3 * b] == kRefFallback) {
+        const int n = N + 1;
+        int I[3];
+        coords(bidx[b], n, d, I);
+        const int r2 = d >= 3 ? 1 : 0, r1 = d >= 2 ? 1 : 0;
+        for (int m2 = -r2; m2 <= r2; m2++)
+            for (int m1 = -r1; m1 <= r1; m1++)
+                for (int m0 = -1; m0 <= 1; m0++) {
+                    const int J[3] = {I[0] + m0, I[1] + m1, I[2] + m2};
+                    if (!in_box(J, N, d)) continue;
+                    const long long q = index_of(J, n, d);
+                    if (cls[q] != C_GHOST) continue;
+                    one[ns] = find_sorted(gidx, ng, (int)q);
+                    idx[ns] = &one[ns];
+                    cf[ns] = &unit;
+                    len[ns] = 1;
+                    ns++;
+                }
+        for (int t = 0; t < ns; t++) w[t] = 1.0 / ns;
+    } else {
+        double den = 0.0;
+        for (int k = 0; k < d; k++) den += bw[3 * b + k];
+        for (int k = 0; k < d; k++) {
+            const int ref = bref[3 * b + k];
+            const double wk = bw[3 * b + k] / den;
+            if (ref == kRefZero) continue;
+            if (ref >= 0) {
+                if (j < 2) continue;  // v^0 = 0 on the band
+                idx[ns] = pidx + pptr[ref];
+                cf[ns] = pcf + pptr[ref];
+                len[ns] = pptr[ref + 1] - pptr[ref];
+            } else {
+                one[ns] = find_sorted(gidx, ng, -1 - ref);
+                idx[ns] = &one[ns];
+                cf[ns] = &unit;
+                len[ns] = 1;
+            }
+            w[ns] = wk;
+            ns++;
+        }
+    }
+    if (!optr) {
+        counts[b] = merge_rows(idx, cf, len, w, ns, nullptr, nullptr, nullptr);
+        return;
+    }
+    merge_rows(idx, cf, len, w, ns, nullptr, oidx + optr[b], ocf + optr[b]);
+}
+
+// Restriction rows of the ghosts of a coarse level (Sec. 3.3: full weighting
+// over the non-INSIDE, non-BOXDIR nodes of the extended fine residual,
+// renormalised unless the fine 3^d box is complete and has no INSIDE node;
+// or the plain mean).  Fine OUTSIDE nodes contribute through their extension
+// rows; the result is a row over fine ghost nodes (node indices, ascending).
+__global__ void k_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f,
+                       int ngf, const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
+                       int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngc) return;
+    const int nc = Nc + 1, nf = Nf + 1;
+    int P[3];
+    coords(gidx_c[g], nc, d, P);
+    const int *idx[kMaxSrc];
+    const double *cf[kMaxSrc];
+    int len[kMaxSrc], one[kMaxSrc];
+    double w[kMaxSrc];
+    const double unit = 1.0;
+    int ns = 0;
+    bool all_ok = true;
+    double selw = 0.0;
+    const int r2 = d >= 3 ? 1 : 0, r1 = d >= 2 ? 1 : 0;
+    for (int m2 = -r2; m2 <= r2; m2++)
+        for (int m1 = -r1; m1 <= r1; m1++)
+            for (int m0 = -1; m0 <= 1; m0++) {
+                const int J[3] = {2 * P[0] + m0, 2 * P[1] + m1, 2 * P[2] + m2};
+                if (!in_box(J, Nf, d)) {
+                    all_ok = false;
+                    continue;
+                }
+                double wgt = m0 == 0 ? 0.5 : 0.25;
+                if (d >= 2) wgt *= m1 == 0 ? 0.5 : 0.25;
+                if (d >= 3) wgt *= m2 == 0 ? 0.5 : 0.25;
+                const long long q = index_of(J, nf, d);
+                const uint8_t c = cls_f[q];
+                if (c == C_INSIDE) {
+                    all_ok = false;
+                    continue;
+                }
+                if (c == C_BOXDIR) continue;
+                selw += wgt;
+                if (c == C_GHOST) {
+                    one[ns] = find_sorted(gidx_f, ngf, (int)q);
+                    idx[ns] = &one[ns];
+                    cf[ns] = &unit;
+                    len[ns] = 1;
+                } else {
+                    const int bb = find_sorted(bidx_f, nbf, (int)q);
+                    if (bb < 0) continue;  // beyond the band: extended value 0
+                    idx[ns] = eidx_f + eptr_f[bb];
+                    cf[ns] = ecf_f + eptr_f[bb];
+                    len[ns] = eptr_f[bb + 1] - eptr_f[bb];
+                }
+                w[ns] = wgt;
+                ns++;
+            }
+    // the number of admissible nodes of the box (for the plain mean) counts
+    // beyond-band OUTSIDE nodes too
+    int cnt = 0;
+    for (int m2 = -r2; m2 <= r2; m2++)
+        for (int m1 = -r1; m1 <= r1; m1++)
+            for (int m0 = -1; m0 <= 1; m0++) {
+                const int J[3] = {2 * P[0] + m0, 2 * P[1] + m1, 2 * P[2] + m2};
+                if (!in_box(J, Nf, d)) continue;
+                const uint8_t c = cls_f[index_of(J, nf, d)];
+                if (c != C_INSIDE && c != C_BOXDIR) cnt++;
+            }
+    if (!all_ok) {
+        for (int t = 0; t < ns; t++) {
+            if (restrict_mode == BCMG_RESTRICT_PLAIN_MEAN)
+                w[t] = 1.0 / cnt;
+            else
+                w[t] = w[t] / selw;
+        }
+    }
+    if (!optr) {
+        counts[g] = merge_rows(idx, cf, len, w, ns, gidx_f, nullptr, nullptr);
+        return;
+    }
+    merge_rows(idx, cf, len, w, ns, gidx_f, oidx + optr[g], ocf + optr[g]);
+}
+
+void launch_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb, const int *bref,
+                 const double *bw, int j, const int *pptr, const int *pidx, const double *pcf, const int *optr,
+                 int *counts, int *oidx, double *ocf, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_erow, dim3((nb + 127) / 128), dim3(128), 0, s, d, N, cls, gidx, ng, bidx, nb, bref, bw, j,
+                       pptr, pidx, pcf, optr, counts, oidx, ocf);
+}
+
+void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f, int ngf,
+                 const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
+                 int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf, hipStream_t s) {
+    if (ngc <= 0) return;
+    hipLaunchKernelGGL(k_rrow, dim3((ngc + 127) / 128), dim3(128), 0, s, d, Nc, gidx_c, ngc, Nf, cls_f, gidx_f, ngf,
+                       bidx_f, nbf, eptr_f, eidx_f, ecf_f, restrict_mode, optr, counts, oidx, ocf);
+}
+
+// Exclusive prefix sum of n counts into ptr[0..n-1], total into ptr[n].
+void launch_scan(const int *counts, int n, int *ptr, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, counts, n, ptr, ptr + n);
+}
+
 // x-extent of the INSIDE/GHOST nodes of each grid row (-1 if none).
 __global__ void k_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, long long rows) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -86,15 +86,16 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, grid: int, copy_bytes: 
         vals = collections.defaultdict(list)
         for name, g, v in counter_rows(d, counter):
             vals[(name, g)].append(v)
-        mine = [v for (n, g), vs in vals.items() if n == kernel and g == grid for v in vs]
+        g_use = grid if grid else max((g for (n, g) in vals if n == kernel), default=0)
+        mine = [v for (n, g), vs in vals.items() if n == kernel and g == g_use for v in vs]
         # the copy probe: the largest elementwise copy dispatch
         copies = [max(vs) for (n, g), vs in vals.items() if "copy" in n.lower() or "elementwise" in n.lower()]
         if not mine:
             raise SystemExit(f"no {counter} rows for {kernel} grid {grid} in {d}")
-        return sum(mine) / len(mine), (max(copies) if copies else None), len(mine)
+        return sum(mine) / len(mine), (max(copies) if copies else None), len(mine), g_use
 
-    f_k, f_copy, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
-    w_k, w_copy, nw = per_dispatch(write_dir, "WRITE_SIZE")
+    f_k, f_copy, nf, grid = per_dispatch(fetch_dir, "FETCH_SIZE")
+    w_k, w_copy, nw, _ = per_dispatch(write_dir, "WRITE_SIZE")
     copy_kib = copy_bytes / 1024.0
     fs = copy_kib / f_copy if f_copy else 1.0
     ws = copy_kib / w_copy if w_copy else 1.0
@@ -115,7 +116,7 @@ def main():
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
     c.add_argument("--kernel", required=True)
-    c.add_argument("--grid", type=int, required=True)
+    c.add_argument("--grid", type=int, default=0, help="grid size in threads (0: the kernel's largest)")
     c.add_argument("--copy-bytes", type=int, required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
