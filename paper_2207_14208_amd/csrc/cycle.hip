@@ -34,9 +34,9 @@ __device__ __forceinline__ double lagrange(int w, int m, double t) {
 // 3^d candidate nodes are loaded first (nodes outside the stencil read G
 // itself), then accumulated in lexicographic order of m.
 template <int D, typename T>
-__device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__restrict__ u) {
-    const long long p = L.gidx[g];
-    const int code = L.gcode[g];
+__device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restrict__ u) {
+    const long long p = ((gcp<int>)L.gidx)[g];
+    const int code = ((gcp<int>)L.gcode)[g];
     int w[3];
     long long step[3];
     double la[3][3];
@@ -45,7 +45,7 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__res
     for (int k = 0; k < 3; k++) {
         w[k] = k < D ? code_w(code, k) : 1;
         step[k] = k < D ? (long long)code_s(code, k) * str[k] : 0;
-        const double t = k < D ? L.gtau[3 * g + k] : 0.0;
+        const double t = k < D ? ((gcp<double>)L.gtau)[3 * g + k] : 0.0;
 #pragma unroll
         for (int m = 0; m < 3; m++) la[k][m] = lagrange(w[k], m, t);
     }
@@ -82,18 +82,19 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, const T *__res
 // Residual of the INSIDE rows of a segment (two nodes per lane); returns the
 // lane's sum of r^2.
 template <int D, typename Tu, typename Tr>
-__device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane) {
+__device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
     double r2 = 0.0;
-    const Tu *__restrict__ u = (const Tu *)L.u;
-    const Tu *__restrict__ f = (const Tu *)L.rhs;
+    gcp<Tu> __restrict__ u = (gcp<Tu>)L.u;
+    gcp<Tu> __restrict__ f = (gcp<Tu>)L.rhs;
+    gcp<uint8_t> cls = (gcp<uint8_t>)L.cls;
+    gp<Tr> __restrict__ r = (gp<Tr>)L.r;
     const long long nn = L.nn;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        if (q >= s.len) continue;
-        const long long p = s.p0 + q;
-        const uint8_t c = L.cls[p];
+        const long long p = s.p0 + (q < s.len ? q : 0);
+        const int c = cls[p];
         const double up = (double)u[p], fp = (double)f[p];
         const double xm = (double)u[clampi(p - 1, nn)], xp = (double)u[clampi(p + 1, nn)];
         double ym = 0, yp = 0, zm = 0, zp = 0;
@@ -105,14 +106,17 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
             zm = (double)u[clampi(p - L.sz, nn)];
             zp = (double)u[clampi(p + L.sz, nn)];
         }
-        if (c != C_INSIDE) continue;
         double sum = xp + xm;
         if (D >= 2) sum += yp + ym;
         if (D >= 3) sum += zp + zm;
         const double lap = (2.0 * D * up - sum) / L.h2;
-        const double r = fp - lap;
-        ((Tr *)L.r)[p] = (Tr)r;
-        r2 += r * r;
+        const double rv = fp - lap;
+        pin(rv);
+        pin(c);
+        if (q < s.len && c == C_INSIDE && live) {
+            r[p] = (Tr)rv;
+            r2 += rv * rv;
+        }
     }
     return r2;
 }
@@ -123,9 +127,11 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
 // (or their plain mean).  Also zeroes the coarse unknown (initial guess of
 // the coarse correction).  Coarse GHOST nodes are done by restrict_ghost.
 template <int D, typename T>
-__device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2) {
+__device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
+                                              bool ok) {
     constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
-    const T *__restrict__ r = (const T *)F.r;
+    gcp<T> __restrict__ r = (gcp<T>)F.r;
+    gcp<uint8_t> fcls = (gcp<uint8_t>)F.cls;
     uint8_t fc[2 * R2 + 1][2 * R1 + 1][3];
     double rv[2 * R2 + 1][2 * R1 + 1][3];
     bool inb[2 * R2 + 1][2 * R1 + 1][3];
@@ -141,12 +147,10 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
                                 (D < 3 || (J2 >= 0 && J2 <= F.N));
                 const long long q = in ? pf + m0 + m1 * F.sy + m2 * F.sz : pf;
                 inb[m2 + R2][m1 + R1][m0 + 1] = in;
-                fc[m2 + R2][m1 + R1][m0 + 1] = F.cls[q];
+                fc[m2 + R2][m1 + R1][m0 + 1] = fcls[q];
                 rv[m2 + R2][m1 + R1][m0 + 1] = (double)r[q];
             }
-    const uint8_t cc = C.cls[pc];
-    if (cc != C_INSIDE) return;
-    ((T *)C.u)[pc] = (T)0;
+    const int cc = ((gcp<uint8_t>)C.cls)[pc];
     double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
     bool all_ok = true;
 #pragma unroll
@@ -181,31 +185,53 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
         out = mcnt > 0.0 ? msum / mcnt : 0.0;
     else
         out = selw > 0.0 ? sel / selw : 0.0;
-    ((T *)C.rhs)[pc] = (T)out;
+    pin(out);
+    pin(cc);
+    if (!ok || cc != C_INSIDE) return;
+    ((gp<T>)C.u)[pc] = (T)0;
+    ((gp<T>)C.rhs)[pc] = (T)out;
 }
 
 // Restriction to coarse ghost g: its precomputed row over the fine ghost
 // residuals (FW or renormalised FW of the extended fine residual, with the
 // extension folded in); zeroes the coarse unknown.
 template <typename T>
-__device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g) {
-    const T *__restrict__ r = (const T *)F.r;
-    const int beg = C.rptr[g], end = C.rptr[g + 1];
+__device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g, bool live) {
+    gcp<T> __restrict__ r = (gcp<T>)F.r;
+    gcp<int> rptr = (gcp<int>)C.rptr, ridx = (gcp<int>)C.ridx;
+    gcp<double> rcoef = (gcp<double>)C.rcoef;
+    const int beg = rptr[g], end = rptr[g + 1];
+    const long long pc = ((gcp<int>)C.gidx)[g];
+    // eight independent loads in flight per step; the sum keeps the row order
     double acc = 0.0;
-    for (int j = beg; j < end; j++) acc += C.rcoef[j] * (double)r[C.ridx[j]];
-    const long long pc = C.gidx[g];
-    ((T *)C.rhs)[pc] = (T)acc;
-    ((T *)C.u)[pc] = (T)0;
+    int j = beg;
+    for (; j + 8 <= end; j += 8) {
+        int ix[8];
+        double cf[8], rv[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            ix[k] = ridx[j + k];
+            cf[k] = rcoef[j + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) rv[k] = (double)r[ix[k]];
+#pragma unroll
+        for (int k = 0; k < 8; k++) acc += cf[k] * rv[k];
+    }
+    for (; j < end; j++) acc += rcoef[j] * (double)r[ridx[j]];
+    if (!live) return;
+    ((gp<T>)C.rhs)[pc] = (T)acc;
+    ((gp<T>)C.u)[pc] = (T)0;
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane) {
+__device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        if (q >= s.len) continue;
-        restrict_node<D, T>(C, F, s.p0 + q, 2 * (s.x0 + q), 2 * s.yj, 2 * s.zk);
+        const int qq = q < s.len ? q : 0;
+        restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, live && q < s.len);
     }
 }
 
@@ -213,10 +239,11 @@ __device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const
 // coarse error to INSIDE and GHOST nodes, u += e (Sec. 2.1 interpolation,
 // Sec. 3.2 bilinear interpolation, Sec. 3.3).
 template <int D, typename T>
-__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2) {
+__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2,
+                                             bool ok) {
     const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
     const int B0 = (I0 - h0) / 2, B1 = (I1 - h1) / 2, B2 = (I2 - h2) / 2;
-    const T *__restrict__ ec = (const T *)C.u;
+    gcp<T> __restrict__ ec = (gcp<T>)C.u;
     constexpr int M1 = D >= 2 ? 2 : 1, M2 = D >= 3 ? 2 : 1;
     double ev[M2][M1][2];
     const long long b = B0 + B1 * C.sy + B2 * C.sz;
@@ -229,10 +256,9 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
                 const bool in = m0 <= h0 && m1 <= h1 && m2 <= h2;
                 ev[m2][m1][m0] = (double)ec[in ? b + m0 + m1 * C.sy + m2 * C.sz : b];
             }
-    T *u = (T *)F.u;
-    const uint8_t fc = F.cls[p];
+    gp<T> u = (gp<T>)F.u;
+    const int fc = ((gcp<uint8_t>)F.cls)[p];
     const double up = (double)u[p];
-    if (fc != C_INSIDE && fc != C_GHOST) return;
     double e = 0.0;
 #pragma unroll
     for (int m2 = 0; m2 < M2; m2++)
@@ -247,43 +273,57 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
                 if (h2) wgt *= 0.5;
                 e += wgt * ev[m2][m1][m0];
             }
-    u[p] = (T)(up + e);
+    const T v = (T)(up + e);
+    pin(v);
+    pin(fc);
+    if (!ok || (fc != C_INSIDE && fc != C_GHOST)) return;
+    u[p] = v;
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane) {
+__device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        if (q >= s.len) continue;
-        prolong_node<D, T>(F, C, s.p0 + q, s.x0 + q, s.yj, s.zk);
+        const int qq = q < s.len ? q : 0;
+        prolong_node<D, T>(F, C, s.p0 + qq, s.x0 + qq, s.yj, s.zk, live && q < s.len);
     }
 }
 
 // Ghost relaxation (eq. rel with P_GG = I/dtau: new interior values, old ghost
 // values): increment, then u_G += increment in a second pass.
 template <int D, typename T>
-__device__ __forceinline__ void ghost_delta(const Desc &L, int g) {
-    const T *u = (const T *)L.u;
-    const T *rhs = (const T *)L.rhs;
-    const long long p = L.gidx[g];
+__device__ __forceinline__ void ghost_delta(const Desc &L, int g, bool live) {
+    gcp<T> u = (gcp<T>)L.u;
+    gcp<T> rhs = (gcp<T>)L.rhs;
+    const long long p = ((gcp<int>)L.gidx)[g];
     const double rg = (double)rhs[p];
+    const double up = (double)u[p];
     const double row = ghost_row<D, T>(L, g, u);
-    L.gnew[g] = (double)(T)((double)u[p] + L.gdtau[g] * (rg - row));
+    const double v = (double)(T)(up + ((gcp<double>)L.gdtau)[g] * (rg - row));
+    pin(v);
+    if (!live) return;
+    ((gp<double>)L.gnew)[g] = v;
 }
 
 template <typename T>
-__device__ __forceinline__ void ghost_apply(const Desc &L, int g) {
-    ((T *)L.u)[L.gidx[g]] = (T)L.gnew[g];
+__device__ __forceinline__ void ghost_apply(const Desc &L, int g, bool live) {
+    const long long p = ((gcp<int>)L.gidx)[g];
+    const T v = (T)((gcp<double>)L.gnew)[g];
+    pin(v);
+    if (!live) return;
+    ((gp<T>)L.u)[p] = v;
 }
 
 template <int D, typename Tu, typename Tr>
-__device__ __forceinline__ double ghost_residual(const Desc &L, int g) {
-    const long long pg = L.gidx[g];
-    const double rg = (double)((const Tu *)L.rhs)[pg];
-    const double r = rg - ghost_row<D, Tu>(L, g, (const Tu *)L.u);
-    ((Tr *)L.r)[pg] = (Tr)r;
+__device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live) {
+    const long long pg = ((gcp<int>)L.gidx)[g];
+    const double rg = (double)((gcp<Tu>)L.rhs)[pg];
+    const double r = rg - ghost_row<D, Tu>(L, g, (gcp<Tu>)L.u);
+    pin(r);
+    if (!live) return 0.0;
+    ((gp<Tr>)L.r)[pg] = (Tr)r;
     return r * r;
 }
 
@@ -292,15 +332,19 @@ __device__ __forceinline__ double ghost_residual(const Desc &L, int g) {
 // values; gsrc gives the ghost values in list order (the new values of a
 // ghost step), or null to read them from the field.
 template <typename T>
-__device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *gsrc) {
-    T *field = (T *)L.u;
-    const int beg = L.eptr[b], end = L.eptr[b + 1];
+__device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *gsrc, bool live) {
+    gp<T> field = (gp<T>)L.u;
+    gcp<int> eidx = (gcp<int>)L.eidx, gidx = (gcp<int>)L.gidx;
+    gcp<double> ecoef = (gcp<double>)L.ecoef, src = (gcp<double>)gsrc;
+    const int beg = ((gcp<int>)L.eptr)[b], end = ((gcp<int>)L.eptr)[b + 1];
+    const long long p = ((gcp<int>)L.bidx)[b];
     double v = 0.0;
     for (int j = beg; j < end; j++) {
-        const int g = L.eidx[j];
-        v += L.ecoef[j] * (gsrc ? gsrc[g] : (double)field[L.gidx[g]]);
+        const int g = eidx[j];
+        v += ecoef[j] * (src ? src[g] : (double)field[gidx[g]]);
     }
-    field[L.bidx[b]] = (T)v;
+    if (!live) return;
+    field[p] = (T)v;
 }
 
 // Coarsest level: x = A^{-1} b over INSIDE then GHOST unknowns, in FP64, by
@@ -321,10 +365,11 @@ __device__ void coarse_solve_block(const Desc &L, double *b) {
 }
 
 // ----------------------------------------------------------------- kernels
-#define CHUNK_ITEM                                                \
-    const Item it = items[blockIdx.x];                            \
+#define CHUNK_ITEM CHUNK_ITEM_AT(xcd_block())
+#define CHUNK_ITEM_AT(lblock)                                     \
+    const Item it = items[lblock];                                \
     const Desc &L = descs[it.x];                                  \
-    if (!st[L.slot].active) return;                               \
+    const bool live = st[L.slot].active != 0;                     \
     if ((int)threadIdx.x >= it.z) return;                         \
     const int e = it.y + threadIdx.x;
 
@@ -333,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__
                                                         const Item *__restrict__ items,
                                                         const SlotState *__restrict__ st) {
     CHUNK_ITEM
-    ghost_delta<D, T>(L, e);
+    ghost_delta<D, T>(L, e, live);
 }
 
 // Ghost step, second half: the new ghost values into u (chunk blocks), and,
@@ -344,16 +389,17 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__
                                                         const Item *__restrict__ items, int ngch,
                                                         const Item *__restrict__ bch,
                                                         const SlotState *__restrict__ st) {
-    if ((int)blockIdx.x < ngch) {
-        CHUNK_ITEM
-        ghost_apply<T>(L, e);
+    const int lb = xcd_block(ngch);
+    if (lb < ngch) {
+        CHUNK_ITEM_AT(lb)
+        ghost_apply<T>(L, e, live);
         return;
     }
-    const Item it = bch[blockIdx.x - ngch];
+    const Item it = bch[lb - ngch];
     const Desc &L = descs[it.x];
-    if (!st[L.slot].active) return;
+    const bool live = st[L.slot].active != 0;
     if ((int)threadIdx.x >= it.z) return;
-    ext_gather<T>(L, it.y + threadIdx.x, L.gnew);
+    ext_gather<T>(L, it.y + threadIdx.x, L.gnew, live);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -369,21 +415,22 @@ template <int D, typename Tu, typename Tr, bool NORM>
 __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st, double *__restrict__ partials) {
-    if ((int)blockIdx.x < nseg_blocks) {
-        SEG_ITEM
-        double r2 = seg_residual<D, Tu, Tr>(L, it, lane);
+    const int lb = xcd_block(nseg_blocks);
+    if (lb < nseg_blocks) {
+        SEG_ITEM_AT(lb)
+        double r2 = seg_residual<D, Tu, Tr>(L, it, lane, live);
         if (NORM) {
             r2 = wave_sum(r2);
             if (lane == 0) partials[sidx] = r2;
         }
         return;
     }
-    const int cb = blockIdx.x - nseg_blocks;
+    const int cb = lb - nseg_blocks;
     const Item it = gch[cb];
     const Desc &L = descs[it.x];
-    if (!st[L.slot].active) return;
+    const bool live = st[L.slot].active != 0;
     double r2 = 0.0;
-    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr>(L, it.y + threadIdx.x);
+    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr>(L, it.y + threadIdx.x, live);
     if (NORM) {
         __shared__ double ws[kWavesPerBlock];
         r2 = wave_sum(r2);
@@ -397,8 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     }
 }
 
-// Per-slot sum of the partials in a fixed order (each thread a contiguous
-// run, then a tree), then the convergence test.  mode 0: ||r^0|| of slots
+// Per-slot sum of the partials in a fixed order (thread t adds entries t,
+// t + 1024, ..., then a tree), then the convergence test.  mode 0: ||r^0|| of slots
 // waiting for it; mode 1: after a cycle; mode 2: only store the norm.
 constexpr int kNormThreads = 1024;
 __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
@@ -413,10 +460,9 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
     if (mode == 0 && st[s].active != 2) return;
     const NormRange R = ranges[s];
     const int nA = R.seg_end - R.seg_beg, nB = R.gch_end - R.gch_beg, n = nA + nB;
-    const int per = (n + kNormThreads - 1) / kNormThreads;
-    const int beg = threadIdx.x * per, end = min(n, beg + per);
     double acc = 0.0;
-    for (int i = beg; i < end; i++) acc += i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
+    for (int i = threadIdx.x; i < n; i += kNormThreads)
+        acc += i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
     __shared__ double red[kNormThreads];
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -463,7 +509,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ext_gather(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                        const SlotState *__restrict__ st) {
     CHUNK_ITEM
-    ext_gather<T>(L, e, nullptr);
+    ext_gather<T>(L, e, nullptr, live);
 }
 
 // Restriction: coarse INSIDE rows by segment blocks, then coarse GHOST rows by
@@ -472,23 +518,24 @@ template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st) {
-    if ((int)blockIdx.x < nseg_blocks) {
-        SEG_ITEM
-        seg_restrict<D, T>(L, descs[it.x - 1], it, lane);
+    const int lb = xcd_block(nseg_blocks);
+    if (lb < nseg_blocks) {
+        SEG_ITEM_AT(lb)
+        seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live);
         return;
     }
-    const Item it = gch[blockIdx.x - nseg_blocks];
+    const Item it = gch[lb - nseg_blocks];
     const Desc &C = descs[it.x];
-    if (!st[C.slot].active) return;
+    const bool live = st[C.slot].active != 0;
     if ((int)threadIdx.x >= it.z) return;
-    restrict_ghost<T>(C, descs[it.x - 1], it.y + threadIdx.x);
+    restrict_ghost<T>(C, descs[it.x - 1], it.y + threadIdx.x, live);
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                     int nseg, const SlotState *__restrict__ st) {
     SEG_ITEM
-    seg_prolong<D, T>(L, descs[it.x + 1], it, lane);
+    seg_prolong<D, T>(L, descs[it.x + 1], it, lane, live);
 }
 
 template <typename T>
@@ -507,16 +554,18 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(const Desc *__restrict__ d
                                                       float *const *__restrict__ eptr) {
     SEG_ITEM
     const Seg s = seg_of(it);
-    float *ev = eptr[it.x];
-    double *u = (double *)L.u;
+    gp<float> ev = (gp<float>)eptr[it.x];
+    gp<double> u = (gp<double>)L.u;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        if (q >= s.len) continue;
-        const long long p = s.p0 + q;
-        const uint8_t c = L.cls[p];
-        if (c != C_INSIDE && c != C_GHOST) continue;
-        u[p] += (double)ev[p];
+        const long long p = s.p0 + (q < s.len ? q : 0);
+        const int c = ((gcp<uint8_t>)L.cls)[p];
+        const double v = u[p] + (double)ev[p];
+        pin(v);
+        pin(c);
+        if (q >= s.len || !live || (c != C_INSIDE && c != C_GHOST)) continue;
+        u[p] = v;
         ev[p] = 0.0f;
     }
 }
@@ -537,19 +586,19 @@ __device__ void blk_smooth(const Desc *descs, const Item *items, const CoarseLev
     for (int colour = 0; colour < 2; colour++) {
         for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
             const Item it = items[lv.seg + s];
-            seg_rb<D, T>(descs[it.x], it, lane, colour);
+            seg_rb<D, T>(descs[it.x], it, lane, colour, true);
         }
         __syncthreads();
     }
     const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
     for (int c = grp; c < lv.ngch; c += ngrp) {
         const Item it = items[lv.gch + c];
-        if (t < it.z) ghost_delta<D, T>(descs[it.x], it.y + t);
+        if (t < it.z) ghost_delta<D, T>(descs[it.x], it.y + t, true);
     }
     __syncthreads();
     for (int c = grp; c < lv.ngch; c += ngrp) {
         const Item it = items[lv.gch + c];
-        if (t < it.z) ghost_apply<T>(descs[it.x], it.y + t);
+        if (t < it.z) ghost_apply<T>(descs[it.x], it.y + t, true);
     }
     __syncthreads();
 }
@@ -560,7 +609,7 @@ __device__ void blk_extend(const Desc *descs, const Item *items, const CoarseLev
     const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
     for (int c = grp; c < lv.nbch; c += ngrp) {
         const Item it = items[lv.bch + c];
-        if (t < it.z) ext_gather<T>(descs[it.x], it.y + t, nullptr);
+        if (t < it.z) ext_gather<T>(descs[it.x], it.y + t, nullptr, true);
     }
     __syncthreads();
 }
@@ -581,21 +630,21 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
         for (int i = 0; i < nu1; i++) blk_smooth<D, T>(descs, items, lv);
         for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
             const Item it = items[lv.seg + s];
-            seg_residual<D, T, T>(descs[it.x], it, lane);
+            seg_residual<D, T, T>(descs[it.x], it, lane, true);
         }
         for (int c = grp; c < lv.ngch; c += ngrp) {
             const Item it = items[lv.gch + c];
-            if (t < it.z) ghost_residual<D, T, T>(descs[it.x], it.y + t);
+            if (t < it.z) ghost_residual<D, T, T>(descs[it.x], it.y + t, true);
         }
         __syncthreads();
         const CoarseLevel &cv = P.lev[a - 1];
         for (int s = wave; s < cv.nseg; s += kCoarseWaves) {
             const Item it = items[cv.seg + s];
-            seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane);
+            seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane, true);
         }
         for (int c = grp; c < cv.ngch; c += ngrp) {
             const Item it = items[cv.gch + c];
-            if (t < it.z) restrict_ghost<T>(descs[it.x], descs[it.x - 1], it.y + t);
+            if (t < it.z) restrict_ghost<T>(descs[it.x], descs[it.x - 1], it.y + t, true);
         }
         __syncthreads();
     }
@@ -613,7 +662,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
         blk_extend<T>(descs, items, P.lev[a - 1]);
         for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
             const Item it = items[lv.seg + s];
-            seg_prolong<D, T>(descs[it.x], descs[it.x + 1], it, lane);
+            seg_prolong<D, T>(descs[it.x], descs[it.x + 1], it, lane, true);
         }
         __syncthreads();
         for (int i = 0; i < nu2; i++) blk_smooth<D, T>(descs, items, lv);

@@ -6,6 +6,15 @@
 
 namespace bcmg {
 
+// Pointers into global memory.  Pointers kept in descriptors are generic;
+// casting them to the global address space makes the compiler emit global
+// (not flat) loads, which a wavefront can wait for without also waiting for
+// its outstanding scalar loads.
+template <typename T>
+using gp = __attribute__((address_space(1))) T *;
+template <typename T>
+using gcp = const __attribute__((address_space(1))) T *;
+
 struct Seg {
     long long p0;  // first node
     int len, x0, yj, zk;
@@ -23,14 +32,46 @@ __device__ __forceinline__ Seg seg_of(const Item &it) {
 
 __device__ __forceinline__ long long clampi(long long q, long long nn) { return q < 0 ? 0 : (q >= nn ? nn - 1 : q); }
 
-// One wavefront per segment item; returns early for padding waves and for
-// problems whose slot is no longer active.
-#define SEG_ITEM                                                  \
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   \
-    const int sidx = blockIdx.x * kWavesPerBlock + wave;          \
-    if (sidx >= nseg) return;                                     \
-    const Item it = items[sidx];                                  \
-    const Desc &L = descs[it.x];                                  \
-    if (!st[L.slot].active) return;
+// Workgroups are handed to the chip's 8 XCDs round-robin (workgroup b to
+// XCD b mod 8), and each XCD has its own L2.  The logical workgroup index
+// gives every XCD one contiguous range of the work list, so that the rows a
+// stencil shares (y and z neighbours) are fetched into the same L2.
+// A grid may hold two lists, nfirst blocks of one (row segments) followed
+// by blocks of another (chunks); each XCD then gets one contiguous range of
+// each list, in even shares.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int nfirst) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b % kXcds, i = b / kXcds;
+    const int qa = nfirst / kXcds, ra = nfirst % kXcds;       // first list: blocks per XCD
+    const int qt = nb / kXcds, rt = nb % kXcds;               // whole grid: blocks per XCD
+    const int na = qa + (x < ra ? 1 : 0);
+    const int abeg = x * qa + min(x, ra);
+    if (i < na) return abeg + i;
+    const int tbeg = x * qt + min(x, rt);
+    return nfirst + (tbeg - abeg) + (i - na);
+}
+__device__ __forceinline__ int xcd_block() { return xcd_block(gridDim.x); }
+
+// Keeps the computation of v, and the loads it needs, ahead of the branches
+// that follow: a wavefront then issues all of its loads before it first
+// waits, instead of waiting once per test (the compiler would otherwise sink
+// loads whose results are only used under a condition).
+template <typename V>
+__device__ __forceinline__ void pin(const V &v) {
+    asm volatile("" ::"v"(v));
+}
+
+// One wavefront per segment item; returns early for padding waves.  live
+// tells whether the item's problem still iterates; node updates test it
+// just before their stores, so its load overlaps the data loads.
+#define SEG_ITEM SEG_ITEM_AT(xcd_block())
+#define SEG_ITEM_AT(lblock)                                                              \
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;                          \
+    const int sidx = __builtin_amdgcn_readfirstlane((lblock) * kWavesPerBlock + wave);   \
+    if (sidx >= nseg) return;                                                            \
+    const Item it = items[sidx];                                                         \
+    const Desc L = descs[it.x];                                                          \
+    const bool live = st[L.slot].active != 0;
 
 }  // namespace bcmg
