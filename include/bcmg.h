@@ -250,6 +250,7 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
 
 /* Batch tuning parameters (take effect at the next step). */
 #define BCMG_PARAM_COARSE_NODES 1 /* levels with at most this many nodes run in one workgroup per problem (default 1200) */
+#define BCMG_PARAM_LDS_BYTES 2    /* LDS bytes that workgroup may hold its levels in (default and maximum 61440; 0 keeps them in HBM) */
 
 bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value);
 

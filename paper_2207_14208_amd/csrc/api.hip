@@ -57,6 +57,7 @@ struct LevelH {
     int *gidx = nullptr, *gcode = nullptr, *gfb = nullptr;
     double *gtau = nullptr, *gdtau = nullptr, *geta = nullptr, *gn = nullptr, *gq = nullptr;
     int *bidx = nullptr;
+    long long ne = 0, nr = 0;              // entries of the extension / restriction rows
     int *eptr = nullptr, *eidx = nullptr;  // extension rows (CSR over ghost-list indices)
     double *ecoef = nullptr;
     int *rptr = nullptr, *ridx = nullptr;  // restriction rows of this level's ghosts (levels >= 1)
@@ -144,6 +145,9 @@ struct bcmg_batch {
     long long coarse_nodes = kCoarseNodes;
     CoarseProg *d_progs = nullptr;
     int nprog = 0;
+    LdsProg *d_lprogs = nullptr;   // the same programs with their levels staged in LDS
+    size_t lds_bytes = 0;          // dynamic LDS per workgroup of k_coarse_lds (0: LDS path off)
+    size_t lds_budget = 0;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -270,6 +274,7 @@ bcmg_status build_ext_rows(bcmg_problem *P, LevelH &V, const int *bref, const do
         int *oidx = nullptr;
         double *ocf = nullptr;
         if (j == K) {
+            V.ne = *h_total;
             if ((st = dalloc_t(P, &V.eidx, tot)) || (st = dalloc_t(P, &V.ecoef, tot))) return st;
             oidx = V.eidx;
             ocf = V.ecoef;
@@ -313,6 +318,7 @@ bcmg_status build_restrict_rows(bcmg_problem *P, int l, int *h_total) {
     HIPCHK(hipMemcpyAsync(h_total, C.rptr + ng, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const size_t tot = (size_t)std::max(*h_total, 1);
+    C.nr = *h_total;
     if ((st = dalloc_t(P, &C.ridx, tot)) || (st = dalloc_t(P, &C.rcoef, tot))) return st;
     launch_rrow(P->d, C.N, C.gidx, ng, F.N, F.cls, F.gidx, (int)F.ng, F.bidx, (int)F.nb, F.eptr, F.eidx, F.ecoef,
                 P->opt.restrict_mode, C.rptr, counts, C.ridx, C.rcoef, s);
@@ -855,6 +861,7 @@ bcmg_status bcmg_batch_create(int32_t capacity, void *stream, bcmg_batch **out) 
         return fail(BCMG_ERR_OOM, "batch allocation: %s", hipGetErrorString(e));
     }
     memset(b->h_state, 0, sizeof(SlotState) * capacity);
+    b->lds_budget = kLdsBudget;
     *out = b;
     return BCMG_OK;
 }
@@ -887,6 +894,7 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
     hipFree(b->d_items);
     hipFree(b->d_coarse);
     hipFree(b->d_progs);
+    hipFree(b->d_lprogs);
     hipFree(b->d_partials);
     if (b->join) hipEventDestroy(b->join);
     if (b->stream) hipStreamDestroy(b->stream);
@@ -1040,6 +1048,46 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         }
         progs.push_back(cp);
     }
+    // the same programs with their levels staged in LDS, when they all fit
+    std::vector<LdsProg> lprogs;
+    size_t lds_max = 0;
+    for (const CoarseProg &cp : progs) {
+        const bcmg_problem *P = b->prob[cp.slot];
+        LdsProg lp;
+        memset(&lp, 0, sizeof lp);
+        lp.slot = cp.slot;
+        lp.top = cp.top;
+        lp.ext_top = cp.ext_top;
+        lp.finest = cp.top == P->L - 1 ? 1 : 0;
+        const size_t esz = P->fp32 ? 4 : 8;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 15) & ~size_t(15);
+            return (int)o;
+        };
+        for (int a2 = 0; a2 <= cp.top; a2++) {
+            const int l = P->L - 1 - a2;
+            const LevelH &V = P->lev[l];
+            LdsLevel &q = lp.lev[a2];
+            q.desc = cp.lev[a2].desc;
+            q.nn = (int)V.nn;
+            q.ng = (int)V.ng;
+            q.nb = (int)V.nb;
+            q.cls = take(V.nn);
+            q.u = take(V.nn * esz);
+            q.rhs = take(V.nn * esz);
+            q.r = take(V.nn * esz);
+            q.gidx = take(4 * V.ng);
+            q.gcode = take(4 * V.ng);
+            q.gtau = take(24 * V.ng);
+            q.gdtau = take(8 * V.ng);
+            q.gnew = take(8 * V.ng);
+        }
+        lds_max = std::max(lds_max, off);
+        lprogs.push_back(lp);
+    }
+    b->lds_bytes = !lprogs.empty() && lds_max <= b->lds_budget ? std::max<size_t>(lds_max, 16) : 0;
     // upload
     hipStream_t st = b->stream;
     if (descs.size() > b->desc_cap) {
@@ -1056,6 +1104,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipMalloc((void **)&b->d_coarse, sizeof(int) * (coarse.size() + 1)));
     hipFree(b->d_progs);
     HIPCHK(hipMalloc((void **)&b->d_progs, sizeof(CoarseProg) * (progs.size() + 1)));
+    hipFree(b->d_lprogs);
+    HIPCHK(hipMalloc((void **)&b->d_lprogs, sizeof(LdsProg) * (lprogs.size() + 1)));
     const size_t np = (size_t)nfseg + nfgch + 1;
     if (np > b->partials_cap) {
         hipFree(b->d_partials);
@@ -1074,6 +1124,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), sizeof(NormRange) * b->cap, hipMemcpyHostToDevice, cs));
     if (!progs.empty())
         HIPCHK(hipMemcpyAsync(b->d_progs, progs.data(), sizeof(CoarseProg) * progs.size(), hipMemcpyHostToDevice, cs));
+    if (!lprogs.empty())
+        HIPCHK(hipMemcpyAsync(b->d_lprogs, lprogs.data(), sizeof(LdsProg) * lprogs.size(), hipMemcpyHostToDevice, cs));
     HIPCHK(hipStreamSynchronize(cs));
     b->lv.assign(A, Lists());
     for (int a = 0; a < A; a++) {
@@ -1142,7 +1194,10 @@ static void launch_vcycle(bcmg_batch *b) {
         launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s);
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s);
     }
-    launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s);
+    if (b->lds_bytes)
+        launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s);
+    else
+        launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s);
     for (int a = b->Ac + 1; a < b->A; a++) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
@@ -1258,6 +1313,14 @@ bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value) {
         if (value < 0 || value > 100000000) return fail(BCMG_ERR_INVALID, "coarse_nodes out of range");
         HIPCHK(hipStreamSynchronize(b->stream));
         b->coarse_nodes = value;
+        b->dirty = true;
+        return BCMG_OK;
+    }
+    if (param == BCMG_PARAM_LDS_BYTES) {
+        if (value < 0 || value > (int64_t)kLdsBudget)
+            return fail(BCMG_ERR_INVALID, "lds budget out of range [0, %zu]", kLdsBudget);
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->lds_budget = (size_t)value;
         b->dirty = true;
         return BCMG_OK;
     }

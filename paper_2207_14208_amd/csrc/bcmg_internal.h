@@ -32,6 +32,8 @@ constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
 constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
 // levels with at most this many nodes are cycled by one workgroup per problem
 constexpr long long kCoarseNodes = 1200;
+// dynamic LDS a coarse workgroup may use to hold its levels (else they stay in HBM)
+constexpr size_t kLdsBudget = 60 * 1024;
 
 // Work item over a row segment: desc, first node, x0 | len << 16, j | k << 16.
 // Ghost / band chunk: desc, first entry, count, unused.
@@ -89,6 +91,24 @@ struct alignas(16) CoarseProg {
     int ext_top;  // 1 if the problem has a finer level above top: extend top's error for its prolongation
     int pad;
     CoarseLevel lev[kMaxLevels];
+};
+
+// A level of the per-problem coarse workgroup held in LDS: sizes, and the
+// byte offsets of its node arrays and ghost records in the workgroup's
+// dynamic LDS block (its extension and restriction rows, read once per
+// cycle, stay in HBM).
+struct LdsLevel {
+    int desc;                              // global descriptor of the level
+    int nn, ng, nb;                        // nodes, ghosts, band nodes
+    int cls, u, rhs, r;                    // node arrays
+    int gidx, gcode, gtau, gdtau, gnew;    // ghost records
+};
+
+// The aligned levels 0..top of one problem cycled in LDS by k_coarse_lds.
+struct alignas(16) LdsProg {
+    int slot, top, ext_top;
+    int finest;  // 1 if top is the problem's finest level (u is the caller's: only unknowns are written back)
+    LdsLevel lev[kMaxLevels];
 };
 
 // Per-slot ranges of the partial sums written by a finest-level residual.

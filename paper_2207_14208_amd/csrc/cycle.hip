@@ -33,19 +33,22 @@ __device__ __forceinline__ double lagrange(int w, int m, double t) {
 // Lagrange weights of widths w_k at the local coordinates tau_k of Q.  The
 // 3^d candidate nodes are loaded first (nodes outside the stencil read G
 // itself), then accumulated in lexicographic order of m.
-template <int D, typename T>
-__device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restrict__ u) {
-    const long long p = ((gcp<int>)L.gidx)[g];
-    const int code = ((gcp<int>)L.gcode)[g];
+// Left side of ghost row g, sum_m w_m u(G - m o s) (eq. BCh), from the
+// ghost's code (widths, signs) and local coordinates tau; PI/PD/PU are
+// pointers into global memory or LDS.
+template <int D, typename PI, typename PD, typename PU>
+__device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, long long sy, long long sz, int g, PU u) {
+    const long long p = gidx[g];
+    const int code = gcode[g];
     int w[3];
     long long step[3];
     double la[3][3];
-    const long long str[3] = {1, L.sy, L.sz};
+    const long long str[3] = {1, sy, sz};
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         w[k] = k < D ? code_w(code, k) : 1;
         step[k] = k < D ? (long long)code_s(code, k) * str[k] : 0;
-        const double t = k < D ? ((gcp<double>)L.gtau)[3 * g + k] : 0.0;
+        const double t = k < D ? gtau[3 * g + k] : 0.0;
 #pragma unroll
         for (int m = 0; m < 3; m++) la[k][m] = lagrange(w[k], m, t);
     }
@@ -76,6 +79,11 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restr
                 acc += wgt * val[m2][m1][m0];
             }
     return acc;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restrict__ u) {
+    return ghost_row_at<D>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, L.sy, L.sz, g, u);
 }
 
 // ------------------------------------------------------------ node updates
@@ -126,16 +134,17 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
 // all of it is INSIDE, else the FW weights of its INSIDE nodes renormalised
 // (or their plain mean).  Also zeroes the coarse unknown (initial guess of
 // the coarse correction).  Coarse GHOST nodes are done by restrict_ghost.
-template <int D, typename T>
-__device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
-                                              bool ok) {
+// FW of the fine residual r over the 3^d box around fine node X for a
+// coarse INSIDE row: all of the box INSIDE and in the grid, else the FW
+// weights of its INSIDE nodes renormalised (or their plain mean).
+template <int D, typename PR, typename PC>
+__device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long long fsy, long long fsz, int X0,
+                                                     int X1, int X2, int mode) {
     constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
-    gcp<T> __restrict__ r = (gcp<T>)F.r;
-    gcp<uint8_t> fcls = (gcp<uint8_t>)F.cls;
     uint8_t fc[2 * R2 + 1][2 * R1 + 1][3];
     double rv[2 * R2 + 1][2 * R1 + 1][3];
     bool inb[2 * R2 + 1][2 * R1 + 1][3];
-    const long long pf = X0 + X1 * F.sy + X2 * F.sz;
+    const long long pf = X0 + X1 * fsy + X2 * fsz;
 #pragma unroll
     for (int m2 = -R2; m2 <= R2; m2++)
 #pragma unroll
@@ -143,14 +152,13 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
 #pragma unroll
             for (int m0 = -1; m0 <= 1; m0++) {
                 const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
-                const bool in = J0 >= 0 && J0 <= F.N && (D < 2 || (J1 >= 0 && J1 <= F.N)) &&
-                                (D < 3 || (J2 >= 0 && J2 <= F.N));
-                const long long q = in ? pf + m0 + m1 * F.sy + m2 * F.sz : pf;
+                const bool in = J0 >= 0 && J0 <= FN && (D < 2 || (J1 >= 0 && J1 <= FN)) &&
+                                (D < 3 || (J2 >= 0 && J2 <= FN));
+                const long long q = in ? pf + m0 + m1 * fsy + m2 * fsz : pf;
                 inb[m2 + R2][m1 + R1][m0 + 1] = in;
                 fc[m2 + R2][m1 + R1][m0 + 1] = fcls[q];
                 rv[m2 + R2][m1 + R1][m0 + 1] = (double)r[q];
             }
-    const int cc = ((gcp<uint8_t>)C.cls)[pc];
     double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
     bool all_ok = true;
 #pragma unroll
@@ -178,13 +186,21 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
                     mcnt += 1.0;
                 }
             }
-    double out;
-    if (all_ok)
-        out = full;
-    else if (C.restrict_mode == BCMG_RESTRICT_PLAIN_MEAN)
-        out = mcnt > 0.0 ? msum / mcnt : 0.0;
-    else
-        out = selw > 0.0 ? sel / selw : 0.0;
+    if (all_ok) return full;
+    if (mode == BCMG_RESTRICT_PLAIN_MEAN) return mcnt > 0.0 ? msum / mcnt : 0.0;
+    return selw > 0.0 ? sel / selw : 0.0;
+}
+
+// Restriction (fine level F, coarse level C; eq. coarseFW, Sec. 3.2 FW,
+// Sec. 3.3) to a coarse INSIDE node; also zeroes the coarse unknown (initial
+// guess of the coarse correction).  Coarse GHOST nodes are done by
+// restrict_ghost.
+template <int D, typename T>
+__device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
+                                              bool ok) {
+    const double out = restrict_inside_at<D>((gcp<T>)F.r, (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
+                                             C.restrict_mode);
+    const int cc = ((gcp<uint8_t>)C.cls)[pc];
     pin(out);
     pin(cc);
     if (!ok || cc != C_INSIDE) return;
@@ -238,15 +254,15 @@ __device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const
 // Prolongation and correction: multilinear interpolation of the (extended)
 // coarse error to INSIDE and GHOST nodes, u += e (Sec. 2.1 interpolation,
 // Sec. 3.2 bilinear interpolation, Sec. 3.3).
-template <int D, typename T>
-__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2,
-                                             bool ok) {
+// Multilinear interpolation at fine node I of the coarse error ec (its
+// coarse cell corners; Sec. 2.1 interpolation, Sec. 3.2).
+template <int D, typename PE>
+__device__ __forceinline__ double prolong_at(PE ec, long long csy, long long csz, int I0, int I1, int I2) {
     const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
     const int B0 = (I0 - h0) / 2, B1 = (I1 - h1) / 2, B2 = (I2 - h2) / 2;
-    gcp<T> __restrict__ ec = (gcp<T>)C.u;
     constexpr int M1 = D >= 2 ? 2 : 1, M2 = D >= 3 ? 2 : 1;
     double ev[M2][M1][2];
-    const long long b = B0 + B1 * C.sy + B2 * C.sz;
+    const long long b = B0 + B1 * csy + B2 * csz;
 #pragma unroll
     for (int m2 = 0; m2 < M2; m2++)
 #pragma unroll
@@ -254,11 +270,8 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
 #pragma unroll
             for (int m0 = 0; m0 < 2; m0++) {
                 const bool in = m0 <= h0 && m1 <= h1 && m2 <= h2;
-                ev[m2][m1][m0] = (double)ec[in ? b + m0 + m1 * C.sy + m2 * C.sz : b];
+                ev[m2][m1][m0] = (double)ec[in ? b + m0 + m1 * csy + m2 * csz : b];
             }
-    gp<T> u = (gp<T>)F.u;
-    const int fc = ((gcp<uint8_t>)F.cls)[p];
-    const double up = (double)u[p];
     double e = 0.0;
 #pragma unroll
     for (int m2 = 0; m2 < M2; m2++)
@@ -273,7 +286,18 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
                 if (h2) wgt *= 0.5;
                 e += wgt * ev[m2][m1][m0];
             }
-    const T v = (T)(up + e);
+    return e;
+}
+
+// Prolongation and correction at fine INSIDE / GHOST node p: u += P e
+// (Sec. 3.3: the coarse error was extended into its band first).
+template <int D, typename T>
+__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2,
+                                             bool ok) {
+    const double e = prolong_at<D>((gcp<T>)C.u, C.sy, C.sz, I0, I1, I2);
+    gp<T> u = (gp<T>)F.u;
+    const int fc = ((gcp<uint8_t>)F.cls)[p];
+    const T v = (T)((double)u[p] + e);
     pin(v);
     pin(fc);
     if (!ok || (fc != C_INSIDE && fc != C_GHOST)) return;
@@ -671,6 +695,246 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
     if (P.ext_top) blk_extend<T>(descs, items, P.lev[P.top]);
 }
 
+// ------------------------------------------- coarse levels, one block, in LDS
+// The same sub-V-cycle as k_coarse_cycle, with every array of the levels
+// 0..top (node arrays, ghost records, extension and restriction rows) copied
+// into the workgroup's LDS first: each step then loops densely over the
+// level's nodes and waits on LDS only.  The top level's u is written back at
+// the end (only its unknowns when it is the caller's array).
+template <typename V>
+using lp = __attribute__((address_space(3))) V *;
+
+template <typename T>
+struct LdsView {
+    int n, nn, ng, nb;
+    long long sy, sz;
+    double h2;
+    int N;
+    lp<uint8_t> cls;
+    lp<T> u, rhs, r;
+    lp<int> gidx, gcode;
+    lp<double> gtau, gdtau, gnew;
+    gcp<int> eptr, eidx, bidx, rptr, ridx;  // rows in HBM
+    gcp<double> ecoef, rcoef;
+};
+
+template <typename V>
+__device__ __forceinline__ lp<V> lds_ptr(unsigned char *base, int off) {
+    return (lp<V>)(base + off);
+}
+
+template <typename V>
+__device__ __forceinline__ void lds_copy(lp<V> dst, const V *src, int n) {
+    gcp<V> g = (gcp<V>)src;
+    for (int i = threadIdx.x; i < n; i += kCoarseThreads) dst[i] = g[i];
+}
+
+template <typename V>
+__device__ __forceinline__ void lds_zero(lp<V> dst, int n) {
+    for (int i = threadIdx.x; i < n; i += kCoarseThreads) dst[i] = V(0);
+}
+
+template <int D>
+__device__ __forceinline__ void node_coords(int p, int n, int &i, int &j, int &k) {
+    i = p % n;
+    j = D >= 2 ? (p / n) % n : 0;
+    k = D >= 3 ? p / (n * n) : 0;
+}
+
+template <int D, typename T>
+__device__ void lds_smooth(const LdsView<T> &L) {
+    for (int colour = 0; colour < 2; colour++) {
+        for (int p = threadIdx.x; p < L.nn; p += kCoarseThreads) {
+            int i, j, k;
+            node_coords<D>(p, L.n, i, j, k);
+            if (((i + j + k) & 1) != colour || L.cls[p] != C_INSIDE) continue;
+            T sum = L.u[p + 1] + L.u[p - 1];
+            if (D >= 2) sum += L.u[p + L.sy] + L.u[p - L.sy];
+            if (D >= 3) sum += L.u[p + L.sz] + L.u[p - L.sz];
+            L.u[p] = ((T)L.h2 * L.rhs[p] + sum) / (T)(2 * D);
+        }
+        __syncthreads();
+    }
+    for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) {
+        const int p = L.gidx[g];
+        const double row = ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u);
+        L.gnew[g] = (double)(T)((double)L.u[p] + L.gdtau[g] * ((double)L.rhs[p] - row));
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) L.u[L.gidx[g]] = (T)L.gnew[g];
+    __syncthreads();
+}
+
+template <int D, typename T>
+__device__ void lds_residual(const LdsView<T> &L) {
+    for (int p = threadIdx.x; p < L.nn; p += kCoarseThreads) {
+        if (L.cls[p] != C_INSIDE) continue;
+        double sum = (double)L.u[p + 1] + (double)L.u[p - 1];
+        if (D >= 2) sum += (double)L.u[p + L.sy] + (double)L.u[p - L.sy];
+        if (D >= 3) sum += (double)L.u[p + L.sz] + (double)L.u[p - L.sz];
+        const double lap = (2.0 * D * (double)L.u[p] - sum) / L.h2;
+        L.r[p] = (T)((double)L.rhs[p] - lap);
+    }
+    for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) {
+        const int p = L.gidx[g];
+        L.r[p] = (T)((double)L.rhs[p] - ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u));
+    }
+    __syncthreads();
+}
+
+// coarse level C from the residual of the finer level F
+template <int D, typename T>
+__device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode) {
+    for (int p = threadIdx.x; p < C.nn; p += kCoarseThreads) {
+        if (C.cls[p] != C_INSIDE) continue;
+        int i, j, k;
+        node_coords<D>(p, C.n, i, j, k);
+        C.rhs[p] = (T)restrict_inside_at<D>(F.r, F.cls, F.N, F.sy, F.sz, 2 * i, 2 * j, 2 * k, mode);
+        C.u[p] = (T)0;
+    }
+    for (int g = threadIdx.x; g < C.ng; g += kCoarseThreads) {
+        const int beg = C.rptr[g], end = C.rptr[g + 1];
+        double acc = 0.0;
+        int e = beg;
+        for (; e + 8 <= end; e += 8) {
+            int ix[8];
+            double cf[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                ix[k] = C.ridx[e + k];
+                cf[k] = C.rcoef[e + k];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) acc += cf[k] * (double)F.r[ix[k]];
+        }
+        for (; e < end; e++) acc += C.rcoef[e] * (double)F.r[C.ridx[e]];
+        const int p = C.gidx[g];
+        C.rhs[p] = (T)acc;
+        C.u[p] = (T)0;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_extend(const LdsView<T> &L) {
+    for (int b = threadIdx.x; b < L.nb; b += kCoarseThreads) {
+        double v = 0.0;
+        for (int e = L.eptr[b]; e < L.eptr[b + 1]; e++) v += L.ecoef[e] * (double)L.u[L.gidx[L.eidx[e]]];
+        L.u[L.bidx[b]] = (T)v;
+    }
+    __syncthreads();
+}
+
+template <int D, typename T>
+__device__ void lds_prolong(const LdsView<T> &F, const LdsView<T> &C) {
+    for (int p = threadIdx.x; p < F.nn; p += kCoarseThreads) {
+        const int c = F.cls[p];
+        if (c != C_INSIDE && c != C_GHOST) continue;
+        int i, j, k;
+        node_coords<D>(p, F.n, i, j, k);
+        F.u[p] = (T)((double)F.u[p] + prolong_at<D>(C.u, C.sy, C.sz, i, j, k));
+    }
+    __syncthreads();
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__restrict__ descs,
+                                                               const LdsProg *__restrict__ progs,
+                                                               const SlotState *__restrict__ st, int nu1, int nu2) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ double bsh[kCoarseMax];
+    const LdsProg &P = progs[blockIdx.x];
+    if (!st[P.slot].active) return;
+    __shared__ LdsView<T> V[kMaxLevels];
+    if (threadIdx.x == 0) {
+        for (int a = 0; a <= P.top; a++) {
+            const LdsLevel &Q = P.lev[a];
+            const Desc &G = descs[Q.desc];
+            LdsView<T> &W = V[a];
+            W.n = G.n;
+            W.N = G.N;
+            W.nn = Q.nn;
+            W.ng = Q.ng;
+            W.nb = Q.nb;
+            W.sy = G.sy;
+            W.sz = G.sz;
+            W.h2 = G.h2;
+            W.cls = lds_ptr<uint8_t>(lds, Q.cls);
+            W.u = lds_ptr<T>(lds, Q.u);
+            W.rhs = lds_ptr<T>(lds, Q.rhs);
+            W.r = lds_ptr<T>(lds, Q.r);
+            W.gidx = lds_ptr<int>(lds, Q.gidx);
+            W.gcode = lds_ptr<int>(lds, Q.gcode);
+            W.gtau = lds_ptr<double>(lds, Q.gtau);
+            W.gdtau = lds_ptr<double>(lds, Q.gdtau);
+            W.gnew = lds_ptr<double>(lds, Q.gnew);
+            W.eptr = (gcp<int>)G.eptr;
+            W.eidx = (gcp<int>)G.eidx;
+            W.ecoef = (gcp<double>)G.ecoef;
+            W.bidx = (gcp<int>)G.bidx;
+            W.rptr = (gcp<int>)G.rptr;
+            W.ridx = (gcp<int>)G.ridx;
+            W.rcoef = (gcp<double>)G.rcoef;
+        }
+    }
+    __syncthreads();
+    for (int a = 0; a <= P.top; a++) {
+        const LdsLevel &Q = P.lev[a];
+        const Desc &G = descs[Q.desc];
+        const LdsView<T> &W = V[a];
+        lds_copy(W.cls, G.cls, Q.nn);
+        lds_copy(W.gidx, G.gidx, Q.ng);
+        lds_copy(W.gcode, G.gcode, Q.ng);
+        lds_copy(W.gtau, G.gtau, 3 * Q.ng);
+        lds_copy(W.gdtau, G.gdtau, Q.ng);
+        if (a == P.top) {
+            lds_copy(W.u, (const T *)G.u, Q.nn);
+            lds_copy(W.rhs, (const T *)G.rhs, Q.nn);
+        } else {
+            lds_zero(W.u, Q.nn);
+            lds_zero(W.rhs, Q.nn);
+        }
+        lds_zero(W.r, Q.nn);
+    }
+    __syncthreads();
+    const int mode = descs[P.lev[0].desc].restrict_mode;
+    for (int a = P.top; a >= 1; a--) {
+        for (int i = 0; i < nu1; i++) lds_smooth<D, T>(V[a]);
+        lds_residual<D, T>(V[a]);
+        lds_restrict<D, T>(V[a - 1], V[a], mode);
+    }
+    {
+        const Desc &G = descs[P.lev[0].desc];
+        if (G.nc > 0 && !G.singular) {
+            gcp<int> cmap = (gcp<int>)G.cmap;
+            gcp<double> ainv = (gcp<double>)G.ainv;
+            for (int t = threadIdx.x; t < G.nc; t += kCoarseThreads) bsh[t] = (double)V[0].rhs[cmap[t]];
+            __syncthreads();
+            for (int t = threadIdx.x; t < G.nc; t += kCoarseThreads) {
+                double x = 0.0;
+                for (int j = 0; j < G.nc; j++) x += ainv[(long long)t * G.nc + j] * bsh[j];
+                V[0].u[cmap[t]] = (T)x;
+            }
+            __syncthreads();
+        } else if (G.nc > 0) {
+            for (int i = 0; i < 50; i++) lds_smooth<D, T>(V[0]);
+        }
+    }
+    for (int a = 1; a <= P.top; a++) {
+        lds_extend<T>(V[a - 1]);
+        lds_prolong<D, T>(V[a], V[a - 1]);
+        for (int i = 0; i < nu2; i++) lds_smooth<D, T>(V[a]);
+    }
+    if (P.ext_top) lds_extend<T>(V[P.top]);
+    const LdsView<T> &W = V[P.top];
+    gp<T> ug = (gp<T>)descs[P.lev[P.top].desc].u;
+    for (int p = threadIdx.x; p < W.nn; p += kCoarseThreads) {
+        const int c = W.cls[p];
+        if (P.finest && c != C_INSIDE && c != C_GHOST) continue;
+        ug[p] = W.u[p];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline int blocks_for_segs(int nseg) { return (nseg + kWavesPerBlock - 1) / kWavesPerBlock; }
 
@@ -784,6 +1048,16 @@ void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, 
         DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2);
     else
         DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2);
+}
+
+void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,
+                       const SlotState *st, int nu1, int nu2, hipStream_t s) {
+    if (nprog <= 0) return;
+    dim3 g(nprog), b(kCoarseThreads);
+    if (fp32)
+        DISPATCH_D(d, k_coarse_lds, float, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
+    else
+        DISPATCH_D(d, k_coarse_lds, double, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
 }
 
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,

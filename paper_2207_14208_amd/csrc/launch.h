@@ -28,6 +28,9 @@ void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const Sl
 // one workgroup per program: the V-cycle on the program's coarse levels
 void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
                          const SlotState *st, int nu1, int nu2, hipStream_t s);
+// the same on the levels staged in LDS (lds_bytes of dynamic LDS per workgroup)
+void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,
+                       const SlotState *st, int nu1, int nu2, hipStream_t s);
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
                       hipStream_t s);
 

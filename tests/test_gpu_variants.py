@@ -95,3 +95,32 @@ def test_batch_same_alone_and_in_mix():
         uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
         O.solve(uo, 0.0, st_a.cycles)
         assert np.abs(uo - u_a).max() <= 1e-12 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("name,coarse_nodes", [("circle65", 1200), ("flower3d65", 1200), ("star257", 300),
+                                               ("star257", 5000), ("ellipsoid33", 1200)])
+def test_coarse_levels_in_lds_same_as_in_hbm(name, coarse_nodes):
+    """The per-problem coarse workgroup gives the same bits with its levels
+    staged in LDS and kept in HBM."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Batch
+    c = {"circle65": W.circle_65, "flower3d65": lambda: W.flower3d(64), "ellipsoid33": lambda: W.ellipsoid(32),
+         "star257": lambda: W.star_case(0, 257, 0.45, 0.08, 5)}[name]()
+    out = []
+    for lds in (N.__dict__.get("LDS_DEFAULT", 61440), 0):
+        G = gpu_problem(c)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        B = Batch(2)
+        B.set_param(N.PARAM_COARSE_NODES, coarse_nodes)
+        B.set_param(N.PARAM_LDS_BYTES, lds)
+        s = B.add(G, u, 1e-10)
+        B.run(1, 300)
+        st, h = B.stats(s)
+        out.append((st.status, st.cycles, h, u.cpu().numpy()))
+        B.close()
+        G.close()
+    (s1, c1, h1, u1), (s2, c2, h2, u2) = out
+    assert (s1, c1) == (s2, c2) and s1 == 0
+    assert np.array_equal(h1, h2)
+    assert np.array_equal(u1, u2)
