@@ -249,8 +249,10 @@ bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stat
 bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64_t *bytes);
 
 /* Batch tuning parameters (take effect at the next step). */
-#define BCMG_PARAM_COARSE_NODES 1 /* levels with at most this many nodes run in one workgroup per problem (default 1200) */
-#define BCMG_PARAM_LDS_BYTES 2    /* LDS bytes that workgroup may hold its levels in (default and maximum 61440; 0 keeps them in HBM) */
+#define BCMG_PARAM_COARSE_NODES 1 /* levels with at most this many nodes run in one workgroup per problem (default 5000;
+                                     lowered as needed so that they fit the LDS budget) */
+#define BCMG_PARAM_LDS_BYTES 2    /* LDS bytes that workgroup may hold its levels in (default and maximum 153600;
+                                     0 keeps them in HBM) */
 
 bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value);
 

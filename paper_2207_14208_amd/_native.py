@@ -20,6 +20,7 @@ DTAU_OPT_EXP, DTAU_OPT_POLY, DTAU_CONST = 0, 1, 2
 RESTRICT_RENORM_FW, RESTRICT_PLAIN_MEAN = 0, 1
 PARAM_COARSE_NODES = 1
 PARAM_LDS_BYTES = 2
+LDS_DEFAULT = 150 * 1024
 
 
 class bcmg_options(C.Structure):

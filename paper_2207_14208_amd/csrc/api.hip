@@ -58,6 +58,10 @@ struct LevelH {
     double *gtau = nullptr, *gdtau = nullptr, *geta = nullptr, *gn = nullptr, *gq = nullptr;
     int *bidx = nullptr;
     long long ne = 0, nr = 0;              // entries of the extension / restriction rows
+    int *bneed = nullptr;                  // band entries read by the prolongation (levels >= 1)
+    long long nbn = 0;
+    int *ilist = nullptr;                  // INSIDE nodes, even i+j+k first (levels up to kListNodes nodes)
+    int nred = 0;
     int *eptr = nullptr, *eidx = nullptr;  // extension rows (CSR over ghost-list indices)
     double *ecoef = nullptr;
     int *rptr = nullptr, *ridx = nullptr;  // restriction rows of this level's ghosts (levels >= 1)
@@ -229,12 +233,17 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
     D.gtau = V.gtau;
     D.gdtau = V.gdtau;
     D.bidx = V.bidx;
+    D.bneed = V.bneed;
+    D.nbn = (int)V.nbn;
     D.eptr = V.eptr;
     D.eidx = V.eidx;
     D.ecoef = V.ecoef;
     D.rptr = V.rptr;
     D.ridx = V.ridx;
     D.rcoef = V.rcoef;
+    D.ilist = V.ilist;
+    D.ni = (int)V.ni;
+    D.nred = V.nred;
     D.u = u;
     D.rhs = rhs;
     D.r = r;
@@ -295,6 +304,31 @@ bcmg_status build_ext_rows(bcmg_problem *P, LevelH &V, const int *bref, const do
     }
     HIPCHK(hipFreeAsync(counts, s));
     HIPCHK(hipStreamSynchronize(s));
+    return BCMG_OK;
+}
+
+// Band entries of level l >= 1 whose extended values the prolongation to
+// level l-1 reads (see k_need_mark).
+bcmg_status build_needed_band(bcmg_problem *P, int l, int *counts, int *offsets, int *total_dev, int *h_total) {
+    hipStream_t s = P->stream;
+    LevelH &C = P->lev[l];
+    const LevelH &F = P->lev[l - 1];
+    bcmg_status st;
+    const size_t nb = (size_t)std::max<long long>(C.nb, 1);
+    if ((st = dalloc_t(P, &C.bneed, nb))) return st;
+    if (C.nb == 0) return BCMG_OK;
+    uint8_t *mark = nullptr, *flag = nullptr;
+    HIPCHK(hipMallocAsync((void **)&mark, (size_t)C.nn, s));
+    HIPCHK(hipMallocAsync((void **)&flag, nb, s));
+    HIPCHK(hipMemsetAsync(mark, 0, (size_t)C.nn, s));
+    launch_need_mark(P->d, F.N, F.cls, C.cls, mark, F.nn, s);
+    launch_need_flags(C.bidx, (int)C.nb, mark, flag, s);
+    launch_compact(flag, (long long)C.nb, 1, counts, offsets, C.bneed, total_dev, s);
+    HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipFreeAsync(mark, s));
+    HIPCHK(hipFreeAsync(flag, s));
+    HIPCHK(hipStreamSynchronize(s));
+    C.nbn = *h_total;
     return BCMG_OK;
 }
 
@@ -402,6 +436,29 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
                 V.segs.push_back(seg_item(0, r * V.n + x, x, len, j, k));
             }
         }
+    }
+    // colour-sorted INSIDE list of a small level (the LDS coarse cycle walks it)
+    if (V.nn <= kListNodes) {
+        std::vector<uint8_t> hc((size_t)V.nn);
+        HIPCHK(hipMemcpyAsync(hc.data(), V.cls, (size_t)V.nn, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int> red, black;
+        for (long long p = 0; p < V.nn; p++) {
+            if (hc[p] != C_INSIDE) continue;
+            long long q = p;
+            int par = 0;
+            for (int k = 0; k < d; k++) {
+                par += (int)(q % V.n);
+                q /= V.n;
+            }
+            ((par & 1) ? black : red).push_back((int)p);
+        }
+        V.nred = (int)red.size();
+        red.insert(red.end(), black.begin(), black.end());
+        if ((st = dalloc_t(P, &V.ilist, std::max<size_t>(red.size(), 1)))) return st;
+        if (!red.empty())
+            HIPCHK(hipMemcpyAsync(V.ilist, red.data(), sizeof(int) * red.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
     // level arrays (cycle precision); the finest FP64 level uses caller memory for u
     const size_t esz = P->fp32 ? 4 : 8;
@@ -611,7 +668,8 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
         }
     }
     for (int l = 1; l < L; l++) {
-        if ((st = build_restrict_rows(P, l, h_total))) {
+        if ((st = build_restrict_rows(P, l, h_total)) ||
+            (st = build_needed_band(P, l, counts, offsets, flag, h_total))) {
             hipHostFree(h_total);
             return bail(st);
         }
@@ -771,7 +829,7 @@ bcmg_status bcmg_level_extend(bcmg_problem *P, int32_t l, double *v) {
     if (!v) return fail(BCMG_ERR_INVALID, "null argument");
     void *pu[1] = {v}, *pr[1] = {P->lev[l].rhs}, *px[1] = {P->lev[l].r};
     if ((st = upload_step_descs(P, l, 1, pu, pr, px))) return st;
-    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l], P->n_bch[l], P->d_stepst, P->stream);
+    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l], P->n_bch[l], 0, P->d_stepst, P->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
     return BCMG_OK;
@@ -797,7 +855,7 @@ bcmg_status bcmg_level_prolong(bcmg_problem *P, int32_t l, double *ec, double *u
     if (l + 1 >= P->L || !ec || !uf) return fail(BCMG_ERR_INVALID, "bad argument");
     void *pu[2] = {uf, ec}, *pr[2] = {P->lev[l].rhs, P->lev[l + 1].rhs}, *px[2] = {P->lev[l].r, P->lev[l + 1].r};
     if ((st = upload_step_descs(P, l, 2, pu, pr, px))) return st;
-    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l + 1], P->n_bch[l + 1], P->d_stepst, P->stream);
+    launch_ext_gather(0, P->d_step, P->d_stepitems + P->off_bch[l + 1], P->n_bch[l + 1], 0, P->d_stepst, P->stream);
     launch_prolong(P->d, 0, P->d_step, P->d_stepitems + P->off_seg[l], P->n_seg[l], P->d_stepst, P->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
@@ -910,6 +968,43 @@ static bcmg_status batch_join(bcmg_batch *b) {
 }
 
 // Rebuild descriptor tables and work lists for the current slots.
+// LDS layout of a problem's coarse levels 0..top (aligned, 0 = coarsest) for
+// k_coarse_lds; returns the bytes needed.  The top level's residual stays in
+// HBM (it is written and read once per cycle).
+static size_t lds_plan(const bcmg_problem *P, int top, LdsProg *lp) {
+    const size_t esz = P->fp32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 15) & ~size_t(15);
+        return (int)o;
+    };
+    for (int a2 = 0; a2 <= top; a2++) {
+        const LevelH &V = P->lev[P->L - 1 - a2];
+        LdsLevel q;
+        memset(&q, 0, sizeof q);
+        q.nn = (int)V.nn;
+        q.ng = (int)V.ng;
+        q.nb = (int)V.nb;
+        q.ni = (int)V.ni;
+        q.nred = V.nred;
+        q.cls = take(V.nn);
+        q.u = take(V.nn * esz);
+        q.rhs = take(V.nn * esz);
+        q.r = a2 < top ? take(V.nn * esz) : -1;
+        q.gidx = take(4 * V.ng);
+        q.gcode = take(4 * V.ng);
+        q.gtau = take(24 * V.ng);
+        q.gdtau = take(8 * V.ng);
+        q.gnew = take(8 * V.ng);
+        q.ilist = take(4 * V.ni);
+        q.nbn = (int)V.nbn;
+        q.bneed = take(4 * V.nbn);
+        if (lp) lp->lev[a2] = q;
+    }
+    return off;
+}
+
 static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipStreamSynchronize(b->stream));  // tables may be in use by queued work
     drop_graph(b);
@@ -976,7 +1071,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         for (int s = 0; s < b->cap; s++)
             if (b->prob[s] && b->prob[s]->L > a && a >= 1) {
                 const int l = b->prob[s]->L - 1 - a;
-                append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].nb);
+                append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].nbn);
             }
         o.ncbch = (int)(items.size() - o.cbch);
         o.cgch = items.size();
@@ -1021,6 +1116,23 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         if (nn > b->coarse_nodes) break;
         Ac = a2;
     }
+    // with LDS enabled, lower the threshold until every problem's coarse
+    // levels fit in the budget
+    if (b->lds_budget > 0) {
+        while (Ac > 0) {
+            size_t need = 0;
+            bool lists = true;
+            for (int s = 0; s < b->cap; s++) {
+                const bcmg_problem *Q = b->prob[s];
+                if (!Q) continue;
+                const int top = std::min(Ac, Q->L - 1);
+                need = std::max(need, lds_plan(Q, top, nullptr));
+                lists = lists && Q->lev[Q->L - 1 - top].ilist != nullptr;
+            }
+            if (need <= b->lds_budget && lists) break;
+            Ac--;
+        }
+    }
     b->Ac = Ac;
     std::vector<CoarseProg> progs;
     for (int s = 0; s < b->cap; s++) {
@@ -1059,32 +1171,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         lp.top = cp.top;
         lp.ext_top = cp.ext_top;
         lp.finest = cp.top == P->L - 1 ? 1 : 0;
-        const size_t esz = P->fp32 ? 4 : 8;
-        size_t off = 0;
-        auto take = [&](size_t bytes) {
-            const size_t o = off;
-            off += (bytes + 15) & ~size_t(15);
-            return (int)o;
-        };
-        for (int a2 = 0; a2 <= cp.top; a2++) {
-            const int l = P->L - 1 - a2;
-            const LevelH &V = P->lev[l];
-            LdsLevel &q = lp.lev[a2];
-            q.desc = cp.lev[a2].desc;
-            q.nn = (int)V.nn;
-            q.ng = (int)V.ng;
-            q.nb = (int)V.nb;
-            q.cls = take(V.nn);
-            q.u = take(V.nn * esz);
-            q.rhs = take(V.nn * esz);
-            q.r = take(V.nn * esz);
-            q.gidx = take(4 * V.ng);
-            q.gcode = take(4 * V.ng);
-            q.gtau = take(24 * V.ng);
-            q.gdtau = take(8 * V.ng);
-            q.gnew = take(8 * V.ng);
-        }
-        lds_max = std::max(lds_max, off);
+        lds_max = std::max(lds_max, lds_plan(P, cp.top, &lp));
+        for (int a2 = 0; a2 <= cp.top; a2++) lp.lev[a2].desc = cp.lev[a2].desc;
         lprogs.push_back(lp);
     }
     b->lds_bytes = !lprogs.empty() && lds_max <= b->lds_budget ? std::max<size_t>(lds_max, 16) : 0;
@@ -1207,7 +1295,7 @@ static void launch_vcycle(bcmg_batch *b) {
             const bool last = i == b->nu2 - 1;
             smooth(b, a, last && U ? U->cbch : nullptr, last && U ? U->ncbch : 0);
         }
-        if (b->nu2 == 0 && U) launch_ext_gather(f, b->d_desc, U->cbch, U->ncbch, b->d_state, s);
+        if (b->nu2 == 0 && U) launch_ext_gather(f, b->d_desc, U->cbch, U->ncbch, 1, b->d_state, s);
     }
 }
 

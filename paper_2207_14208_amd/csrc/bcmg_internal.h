@@ -31,9 +31,13 @@ constexpr int kRefZero = INT32_MIN;       // band reference to a node whose valu
 constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
 constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
 // levels with at most this many nodes are cycled by one workgroup per problem
-constexpr long long kCoarseNodes = 1200;
-// dynamic LDS a coarse workgroup may use to hold its levels (else they stay in HBM)
-constexpr size_t kLdsBudget = 60 * 1024;
+constexpr long long kCoarseNodes = 5000;
+// levels with at most this many nodes keep a colour-sorted list of their
+// INSIDE nodes (used when they are cycled in LDS)
+constexpr long long kListNodes = 1 << 15;
+// dynamic LDS a coarse workgroup may use to hold its levels (else they stay
+// in HBM); gfx950 gives a workgroup up to 160 KiB
+constexpr size_t kLdsBudget = 150 * 1024;
 
 // Work item over a row segment: desc, first node, x0 | len << 16, j | k << 16.
 // Ghost / band chunk: desc, first entry, count, unused.
@@ -51,12 +55,16 @@ struct alignas(16) Desc {
     const double *gtau;       // [3*ng]
     const double *gdtau;      // [ng]
     const int *bidx;          // band node indices, ascending
+    const int *bneed;         // band entries the prolongation reads (levels >= 1), ascending
+    int nbn;                  //   their count
     const int *eptr;          // [nb+1] extension rows: v(band b) = sum ecoef * u(ghost eidx)
     const int *eidx;          //   ghost-list indices, ascending within a row
     const double *ecoef;
     const int *rptr;          // [ng+1] restricted value of this level's ghost g (levels >= 1):
     const int *ridx;          //   sum rcoef * r_fine(ridx), ridx = fine node indices
     const double *rcoef;
+    const int *ilist;         // INSIDE nodes, even i+j+k first (small levels only, else null)
+    int ni, nred;             //   their count and the count of the first colour
     void *u, *rhs, *r;        // level arrays, element type = cycle precision
     double *gnew;             // [ng] new ghost values of a Jacobi ghost step
     // coarsest level: dense inverse over INSIDE then GHOST unknowns
@@ -99,8 +107,10 @@ struct alignas(16) CoarseProg {
 // cycle, stay in HBM).
 struct LdsLevel {
     int desc;                              // global descriptor of the level
-    int nn, ng, nb;                        // nodes, ghosts, band nodes
-    int cls, u, rhs, r;                    // node arrays
+    int nn, ng, nb, ni, nred, nbn;         // nodes, ghosts, band nodes, INSIDE nodes (first colour), needed band
+    int cls, u, rhs, r;                    // node arrays (r < 0: the residual stays in HBM)
+    int ilist;                             // INSIDE nodes by colour
+    int bneed;                             // needed band entries
     int gidx, gcode, gtau, gdtau, gnew;    // ghost records
 };
 

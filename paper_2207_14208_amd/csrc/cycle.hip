@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__
     const Desc &L = descs[it.x];
     const bool live = st[L.slot].active != 0;
     if ((int)threadIdx.x >= it.z) return;
-    ext_gather<T>(L, it.y + threadIdx.x, L.gnew, live);
+    ext_gather<T>(L, ((gcp<int>)L.bneed)[it.y + threadIdx.x], L.gnew, live);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -531,9 +531,9 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
 // Extension of u into the band chunks (ghost values read from u).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ext_gather(const Desc *__restrict__ descs, const Item *__restrict__ items,
-                                                       const SlotState *__restrict__ st) {
+                                                       int via_need, const SlotState *__restrict__ st) {
     CHUNK_ITEM
-    ext_gather<T>(L, e, nullptr, live);
+    ext_gather<T>(L, via_need ? ((gcp<int>)L.bneed)[e] : e, nullptr, live);
 }
 
 // Restriction: coarse INSIDE rows by segment blocks, then coarse GHOST rows by
@@ -706,13 +706,15 @@ using lp = __attribute__((address_space(3))) V *;
 
 template <typename T>
 struct LdsView {
-    int n, nn, ng, nb;
+    int n, nn, ng, nb, ni, nred;
     long long sy, sz;
     double h2;
     int N;
     lp<uint8_t> cls;
     lp<T> u, rhs, r;
-    lp<int> gidx, gcode;
+    gp<T> rg;  // the residual in HBM instead of r (null when r is in LDS)
+    lp<int> gidx, gcode, ilist, bneed;
+    int nbn;
     lp<double> gtau, gdtau, gnew;
     gcp<int> eptr, eidx, bidx, rptr, ridx;  // rows in HBM
     gcp<double> ecoef, rcoef;
@@ -721,12 +723,6 @@ struct LdsView {
 template <typename V>
 __device__ __forceinline__ lp<V> lds_ptr(unsigned char *base, int off) {
     return (lp<V>)(base + off);
-}
-
-template <typename V>
-__device__ __forceinline__ void lds_copy(lp<V> dst, const V *src, int n) {
-    gcp<V> g = (gcp<V>)src;
-    for (int i = threadIdx.x; i < n; i += kCoarseThreads) dst[i] = g[i];
 }
 
 template <typename V>
@@ -744,10 +740,9 @@ __device__ __forceinline__ void node_coords(int p, int n, int &i, int &j, int &k
 template <int D, typename T>
 __device__ void lds_smooth(const LdsView<T> &L) {
     for (int colour = 0; colour < 2; colour++) {
-        for (int p = threadIdx.x; p < L.nn; p += kCoarseThreads) {
-            int i, j, k;
-            node_coords<D>(p, L.n, i, j, k);
-            if (((i + j + k) & 1) != colour || L.cls[p] != C_INSIDE) continue;
+        const int beg = colour ? L.nred : 0, end = colour ? L.ni : L.nred;
+        for (int t = beg + (int)threadIdx.x; t < end; t += kCoarseThreads) {
+            const int p = L.ilist[t];
             T sum = L.u[p + 1] + L.u[p - 1];
             if (D >= 2) sum += L.u[p + L.sy] + L.u[p - L.sy];
             if (D >= 3) sum += L.u[p + L.sz] + L.u[p - L.sz];
@@ -767,29 +762,39 @@ __device__ void lds_smooth(const LdsView<T> &L) {
 
 template <int D, typename T>
 __device__ void lds_residual(const LdsView<T> &L) {
-    for (int p = threadIdx.x; p < L.nn; p += kCoarseThreads) {
-        if (L.cls[p] != C_INSIDE) continue;
+    for (int t = threadIdx.x; t < L.ni; t += kCoarseThreads) {
+        const int p = L.ilist[t];
         double sum = (double)L.u[p + 1] + (double)L.u[p - 1];
         if (D >= 2) sum += (double)L.u[p + L.sy] + (double)L.u[p - L.sy];
         if (D >= 3) sum += (double)L.u[p + L.sz] + (double)L.u[p - L.sz];
         const double lap = (2.0 * D * (double)L.u[p] - sum) / L.h2;
-        L.r[p] = (T)((double)L.rhs[p] - lap);
+        const T v = (T)((double)L.rhs[p] - lap);
+        if (L.rg)
+            L.rg[p] = v;
+        else
+            L.r[p] = v;
     }
     for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) {
         const int p = L.gidx[g];
-        L.r[p] = (T)((double)L.rhs[p] - ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u));
+        const T v = (T)((double)L.rhs[p] - ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u));
+        if (L.rg)
+            L.rg[p] = v;
+        else
+            L.r[p] = v;
     }
+    __threadfence_block();
     __syncthreads();
 }
 
 // coarse level C from the residual of the finer level F
 template <int D, typename T>
 __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode) {
-    for (int p = threadIdx.x; p < C.nn; p += kCoarseThreads) {
-        if (C.cls[p] != C_INSIDE) continue;
+    for (int t = threadIdx.x; t < C.ni; t += kCoarseThreads) {
+        const int p = C.ilist[t];
         int i, j, k;
         node_coords<D>(p, C.n, i, j, k);
-        C.rhs[p] = (T)restrict_inside_at<D>(F.r, F.cls, F.N, F.sy, F.sz, 2 * i, 2 * j, 2 * k, mode);
+        C.rhs[p] = (T)(F.rg ? restrict_inside_at<D>((gcp<T>)F.rg, F.cls, F.N, F.sy, F.sz, 2 * i, 2 * j, 2 * k, mode)
+                            : restrict_inside_at<D>(F.r, F.cls, F.N, F.sy, F.sz, 2 * i, 2 * j, 2 * k, mode));
         C.u[p] = (T)0;
     }
     for (int g = threadIdx.x; g < C.ng; g += kCoarseThreads) {
@@ -804,10 +809,13 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
                 ix[k] = C.ridx[e + k];
                 cf[k] = C.rcoef[e + k];
             }
+            double rv[8];
 #pragma unroll
-            for (int k = 0; k < 8; k++) acc += cf[k] * (double)F.r[ix[k]];
+            for (int k = 0; k < 8; k++) rv[k] = (double)(F.rg ? ((gcp<T>)F.rg)[ix[k]] : F.r[ix[k]]);
+#pragma unroll
+            for (int k = 0; k < 8; k++) acc += cf[k] * rv[k];
         }
-        for (; e < end; e++) acc += C.rcoef[e] * (double)F.r[C.ridx[e]];
+        for (; e < end; e++) acc += C.rcoef[e] * (double)(F.rg ? ((gcp<T>)F.rg)[C.ridx[e]] : F.r[C.ridx[e]]);
         const int p = C.gidx[g];
         C.rhs[p] = (T)acc;
         C.u[p] = (T)0;
@@ -817,7 +825,8 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
 
 template <typename T>
 __device__ void lds_extend(const LdsView<T> &L) {
-    for (int b = threadIdx.x; b < L.nb; b += kCoarseThreads) {
+    for (int t = threadIdx.x; t < L.nbn; t += kCoarseThreads) {
+        const int b = L.bneed[t];
         double v = 0.0;
         for (int e = L.eptr[b]; e < L.eptr[b + 1]; e++) v += L.ecoef[e] * (double)L.u[L.gidx[L.eidx[e]]];
         L.u[L.bidx[b]] = (T)v;
@@ -827,9 +836,8 @@ __device__ void lds_extend(const LdsView<T> &L) {
 
 template <int D, typename T>
 __device__ void lds_prolong(const LdsView<T> &F, const LdsView<T> &C) {
-    for (int p = threadIdx.x; p < F.nn; p += kCoarseThreads) {
-        const int c = F.cls[p];
-        if (c != C_INSIDE && c != C_GHOST) continue;
+    for (int t = threadIdx.x; t < F.ni + F.ng; t += kCoarseThreads) {
+        const int p = t < F.ni ? F.ilist[t] : F.gidx[t - F.ni];
         int i, j, k;
         node_coords<D>(p, F.n, i, j, k);
         F.u[p] = (T)((double)F.u[p] + prolong_at<D>(C.u, C.sy, C.sz, i, j, k));
@@ -856,13 +864,19 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
             W.nn = Q.nn;
             W.ng = Q.ng;
             W.nb = Q.nb;
+            W.ni = Q.ni;
+            W.nred = Q.nred;
+            W.ilist = lds_ptr<int>(lds, Q.ilist);
+            W.nbn = Q.nbn;
+            W.bneed = lds_ptr<int>(lds, Q.bneed);
             W.sy = G.sy;
             W.sz = G.sz;
             W.h2 = G.h2;
             W.cls = lds_ptr<uint8_t>(lds, Q.cls);
             W.u = lds_ptr<T>(lds, Q.u);
             W.rhs = lds_ptr<T>(lds, Q.rhs);
-            W.r = lds_ptr<T>(lds, Q.r);
+            W.r = lds_ptr<T>(lds, Q.r < 0 ? 0 : Q.r);
+            W.rg = Q.r < 0 ? (gp<T>)G.r : nullptr;
             W.gidx = lds_ptr<int>(lds, Q.gidx);
             W.gcode = lds_ptr<int>(lds, Q.gcode);
             W.gtau = lds_ptr<double>(lds, Q.gtau);
@@ -878,23 +892,77 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
         }
     }
     __syncthreads();
+    // staging: one flat list of copies (4-byte words; every staged array is
+    // a whole number of words, class arrays are padded allocations), walked
+    // by all threads with sixteen loads in flight each
+    __shared__ const uint32_t *csrc[kMaxLevels * 8];
+    __shared__ int cdst[kMaxLevels * 8], cbeg[kMaxLevels * 8 + 1];
+    __shared__ int ncopy;
+    if (threadIdx.x == 0) {
+        int n = 0, w = 0;
+        auto add = [&](const void *src, int lds_off, long long bytes) {
+            if (bytes <= 0) return;
+            csrc[n] = (const uint32_t *)src;
+            cdst[n] = lds_off / 4;
+            cbeg[n] = w;
+            w += (int)((bytes + 3) / 4);
+            n++;
+        };
+        for (int a = 0; a <= P.top; a++) {
+            const LdsLevel &Q = P.lev[a];
+            const Desc &G = descs[Q.desc];
+            add(G.cls, Q.cls, Q.nn);
+            add(G.gidx, Q.gidx, 4LL * Q.ng);
+            add(G.gcode, Q.gcode, 4LL * Q.ng);
+            add(G.gtau, Q.gtau, 24LL * Q.ng);
+            add(G.gdtau, Q.gdtau, 8LL * Q.ng);
+            add(G.ilist, Q.ilist, 4LL * Q.ni);
+            add(G.bneed, Q.bneed, 4LL * Q.nbn);
+            if (a == P.top) {
+                add(G.u, Q.u, (long long)sizeof(T) * Q.nn);
+                add(G.rhs, Q.rhs, (long long)sizeof(T) * Q.nn);
+            }
+        }
+        cbeg[n] = w;
+        ncopy = n;
+    }
+    __syncthreads();
+    {
+        const int n = ncopy, total = cbeg[n];
+        lp<uint32_t> words = (lp<uint32_t>)lds;
+        constexpr int U = 16;
+        for (int w0 = threadIdx.x; w0 < total; w0 += U * kCoarseThreads) {
+            uint32_t v[U];
+            int dst[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const int w = w0 + k * kCoarseThreads;
+                dst[k] = -1;
+                if (w >= total) continue;
+                int lo = 0, hi = n - 1;  // segment holding word w
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (cbeg[mid] <= w)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                v[k] = ((gcp<uint32_t>)csrc[lo])[w - cbeg[lo]];
+                dst[k] = cdst[lo] + (w - cbeg[lo]);
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++)
+                if (dst[k] >= 0) words[dst[k]] = v[k];
+        }
+    }
     for (int a = 0; a <= P.top; a++) {
         const LdsLevel &Q = P.lev[a];
-        const Desc &G = descs[Q.desc];
         const LdsView<T> &W = V[a];
-        lds_copy(W.cls, G.cls, Q.nn);
-        lds_copy(W.gidx, G.gidx, Q.ng);
-        lds_copy(W.gcode, G.gcode, Q.ng);
-        lds_copy(W.gtau, G.gtau, 3 * Q.ng);
-        lds_copy(W.gdtau, G.gdtau, Q.ng);
-        if (a == P.top) {
-            lds_copy(W.u, (const T *)G.u, Q.nn);
-            lds_copy(W.rhs, (const T *)G.rhs, Q.nn);
-        } else {
+        if (a != P.top) {
             lds_zero(W.u, Q.nn);
             lds_zero(W.rhs, Q.nn);
         }
-        lds_zero(W.r, Q.nn);
+        if (Q.r >= 0) lds_zero(W.r, Q.nn);
     }
     __syncthreads();
     const int mode = descs[P.lev[0].desc].restrict_mode;
@@ -911,8 +979,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
             for (int t = threadIdx.x; t < G.nc; t += kCoarseThreads) bsh[t] = (double)V[0].rhs[cmap[t]];
             __syncthreads();
             for (int t = threadIdx.x; t < G.nc; t += kCoarseThreads) {
+                gcp<double> row = ainv + (long long)t * G.nc;
                 double x = 0.0;
-                for (int j = 0; j < G.nc; j++) x += ainv[(long long)t * G.nc + j] * bsh[j];
+                int j = 0;
+                for (; j + 8 <= G.nc; j += 8) {  // eight loads in flight, sum in row order
+                    double a[8];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) a[k] = row[j + k];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) x += a[k] * bsh[j + k];
+                }
+                for (; j < G.nc; j++) x += row[j] * bsh[j];
                 V[0].u[cmap[t]] = (T)x;
             }
             __syncthreads();
@@ -1003,12 +1080,13 @@ void launch_norm_finish(const NormRange *ranges, int nslots, const double *parti
                        st, rtol2, hist, hist_stride, mode, out);
 }
 
-void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, const SlotState *st, hipStream_t s) {
+void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,
+                       hipStream_t s) {
     if (nbch <= 0) return;
     if (fp32)
-        hipLaunchKernelGGL((k_ext_gather<float>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, st);
+        hipLaunchKernelGGL((k_ext_gather<float>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, via_need, st);
     else
-        hipLaunchKernelGGL((k_ext_gather<double>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, st);
+        hipLaunchKernelGGL((k_ext_gather<double>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, via_need, st);
 }
 
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,

@@ -18,7 +18,9 @@ void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, con
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s);
 // extension of u into the band chunks bch (ghost values read from u)
-void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, const SlotState *st, hipStream_t s);
+// via_need: the chunks run over the needed band entries (bneed) instead of all of them
+void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,
+                       hipStream_t s);
 // restriction into the coarse segments csegs (INSIDE rows) and coarse ghost chunks cgch
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
                      const SlotState *st, hipStream_t s);
@@ -58,6 +60,9 @@ void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_
                  const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
                  int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf, hipStream_t s);
 void launch_scan(const int *counts, int n, int *ptr, hipStream_t s);
+void launch_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c, uint8_t *mark_c, long long nnf,
+                      hipStream_t s);
+void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag, hipStream_t s);
 void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s);
 void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
                          const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s);

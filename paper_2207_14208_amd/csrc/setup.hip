@@ -709,6 +709,50 @@ void launch_scan(const int *counts, int n, int *ptr, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, counts, n, ptr, ptr + n);
 }
 
+// Coarse OUTSIDE nodes that the prolongation reads: the corners of the
+// coarse cells holding fine INSIDE / GHOST nodes.  Only these band nodes
+// need the extended coarse error during a cycle.
+__global__ void k_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c, uint8_t *mark_c,
+                            long long nnf) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnf) return;
+    const uint8_t c = cls_f[p];
+    if (c != C_INSIDE && c != C_GHOST) return;
+    const int nf = Nf + 1, nc = Nf / 2 + 1;
+    int I[3];
+    coords(p, nf, d, I);
+    int B[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    for (int k = 0; k < d; k++) {
+        h[k] = I[k] & 1;
+        B[k] = (I[k] - h[k]) / 2;
+    }
+    for (int m2 = 0; m2 <= h[2]; m2++)
+        for (int m1 = 0; m1 <= h[1]; m1++)
+            for (int m0 = 0; m0 <= h[0]; m0++) {
+                const int J[3] = {B[0] + m0, B[1] + m1, B[2] + m2};
+                const long long q = index_of(J, nc, d);
+                if (cls_c[q] == C_OUTSIDE) mark_c[q] = 1;
+            }
+}
+
+// flag[b] = mark[bidx[b]] over the band entries
+__global__ void k_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) flag[b] = mark[bidx[b]];
+}
+
+void launch_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c, uint8_t *mark_c, long long nnf,
+                      hipStream_t s) {
+    if (nnf <= 0) return;
+    hipLaunchKernelGGL(k_need_mark, dim3((unsigned)((nnf + 255) / 256)), dim3(256), 0, s, d, Nf, cls_f, cls_c,
+                       mark_c, nnf);
+}
+
+void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_need_flags, dim3((nb + 255) / 256), dim3(256), 0, s, bidx, nb, mark, flag);
+}
+
 // x-extent of the INSIDE/GHOST nodes of each grid row (-1 if none).
 __global__ void k_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, long long rows) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;

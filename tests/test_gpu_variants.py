@@ -108,7 +108,7 @@ def test_coarse_levels_in_lds_same_as_in_hbm(name, coarse_nodes):
     c = {"circle65": W.circle_65, "flower3d65": lambda: W.flower3d(64), "ellipsoid33": lambda: W.ellipsoid(32),
          "star257": lambda: W.star_case(0, 257, 0.45, 0.08, 5)}[name]()
     out = []
-    for lds in (N.__dict__.get("LDS_DEFAULT", 61440), 0):
+    for lds in (N.LDS_DEFAULT, 0):
         G = gpu_problem(c)
         u = G.initial_guess(torch.from_numpy(c.gB).cuda())
         B = Batch(2)
