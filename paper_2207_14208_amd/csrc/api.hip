@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "bcmg_internal.h"
@@ -165,10 +166,12 @@ bcmg_status dalloc(bcmg_problem *P, void **out, size_t bytes) {
     *out = nullptr;
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~size_t(255);
-    hipError_t e = hipMalloc(out, bytes);
+    // stream-ordered allocation from the device pool: cheap, and the memory
+    // is ready when the setup's final synchronisation returns
+    hipError_t e = hipMallocAsync(out, bytes, P->stream);
     if (e != hipSuccess) {
         *out = nullptr;
-        return fail(BCMG_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return fail(BCMG_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
     e = hipMemsetAsync(*out, 0, bytes, P->stream);
     if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -186,7 +189,8 @@ bcmg_status dalloc_t(bcmg_problem *P, T **out, size_t count) {
 }
 
 void free_problem_memory(bcmg_problem *P) {
-    for (void *p : P->allocs) hipFree(p);
+    for (void *p : P->allocs) hipFreeAsync(p, P->stream);
+    hipStreamSynchronize(P->stream);
     P->allocs.clear();
     if (P->h_stage) hipHostFree(P->h_stage);
     P->h_stage = nullptr;
@@ -604,6 +608,23 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
     return BCMG_OK;
 }
 
+// Keep freed problem memory in the device pool instead of returning it to
+// the driver at every synchronisation (problems come and go when serving).
+static void keep_pool_memory() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    static std::mutex mu;
+    static bool done[64] = {false};
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done[dev] = true;
+}
+
 bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg_options *opt, void *stream,
                        bcmg_problem **out) {
     if (!out) return fail(BCMG_ERR_INVALID, "null output handle");
@@ -621,6 +642,7 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
     P->N = N;
     P->opt = o;
     P->stream = (hipStream_t)stream;
+    keep_pool_memory();
     P->fp32 = o.precision == BCMG_MIXED;
     int L = 0;
     for (int NN = N; NN >= o.coarsest_N; NN /= 2) L++;

@@ -161,11 +161,51 @@ __global__ void k_compact_scatter(const uint8_t *cls, long long nn, uint8_t valu
     }
 }
 
+// Exclusive prefix sum of n counts of any size: blocks of kTile counts are
+// reduced to block sums, those are scanned (recursively), and every block
+// rescans its counts from its offset.
+__global__ void k_scan_reduce(const int *in, int n, int *bsum) {
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kPer;
+    int c = 0;
+    for (int i = 0; i < kPer; i++)
+        if (base + i < n) c += in[base + i];
+    int tot;
+    block_exclusive_scan(c, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_apply(const int *in, int n, const int *boff, int *out) {
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kPer;
+    int c = 0;
+    for (int i = 0; i < kPer; i++)
+        if (base + i < n) c += in[base + i];
+    int off = boff[blockIdx.x] + block_exclusive_scan(c, nullptr);
+    for (int i = 0; i < kPer; i++)
+        if (base + i < n) {
+            out[base + i] = off;
+            off += in[base + i];
+        }
+}
+
+void scan_exclusive(const int *in, int n, int *out, int *total, hipStream_t s) {
+    const int nb = (n + kTile - 1) / kTile;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, in, n, out, total);
+        return;
+    }
+    int *tmp = nullptr;
+    if (hipMallocAsync((void **)&tmp, sizeof(int) * 2 * (size_t)nb, s) != hipSuccess) return;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, tmp);
+    scan_exclusive(tmp, nb, tmp + nb, total, s);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, n, tmp + nb, out);
+    hipFreeAsync(tmp, s);
+}
+
 void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
                     int *total_dev, hipStream_t s) {
     const int nb = compact_blocks(nn);
     hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, counts);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, counts, nb, offsets, total_dev);
+    scan_exclusive(counts, nb, offsets, total_dev, s);
     if (out) hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, offsets, out);
 }
 
@@ -192,21 +232,19 @@ __device__ __forceinline__ double lag(int w, int m, double t) {
     return t * (t - 1.0) / 2.0;
 }
 
-// tensor-product quadratic interpolant of phi on {I - m o s : m_k < 3}
-__device__ double phi_tilde(const double *phi, int n, int d, const int I[3], const int s[3], const double t[3]) {
+// tensor-product quadratic interpolant of phi on {I - m o s : m_k < 3}, from
+// the node values pv[m2][m1][m0] = phi(I - m o s), loaded once
+__device__ double phi_tilde_vals(const double pv[3][3][3], int d, const double t[3]) {
     double val = 0.0;
     const int mmax0 = 3, mmax1 = d >= 2 ? 3 : 1, mmax2 = d >= 3 ? 3 : 1;
     for (int m2 = 0; m2 < mmax2; m2++)
         for (int m1 = 0; m1 < mmax1; m1++)
             for (int m0 = 0; m0 < mmax0; m0++) {
                 const int m[3] = {m0, m1, m2};
-                int J[3];
                 double wgt = 1.0;
-                for (int k = 0; k < 3; k++) {
-                    J[k] = I[k] - m[k] * s[k];
+                for (int k = 0; k < 3; k++)
                     if (k < d) wgt *= lag(3, m[k], t[k]);
-                }
-                val += wgt * phi[index_of(J, n, d)];
+                val += wgt * pv[m2][m1][m0];
             }
     return val;
 }
@@ -323,6 +361,13 @@ __global__ void k_ghost_geometry(int d, int N, int level, double h, const double
         if (far < 0 || far > N) sp[k] = -s[k];
     }
     const double phiG = phi[p];
+    double pv[3][3][3];
+    for (int m2 = 0; m2 < (d >= 3 ? 3 : 1); m2++)
+        for (int m1 = 0; m1 < (d >= 2 ? 3 : 1); m1++)
+            for (int m0 = 0; m0 < 3; m0++) {
+                const int J[3] = {I[0] - m0 * sp[0], I[1] - m1 * sp[1], I[2] - m2 * sp[2]};
+                pv[m2][m1][m0] = phi[index_of(J, n, d)];
+            }
     double eta;
     int fb = 0;
     if (phiG == 0.0) {
@@ -332,7 +377,7 @@ __global__ void k_ghost_geometry(int d, int N, int level, double h, const double
         {
             double t[3] = {0.0, 0.0, 0.0};
             for (int k = 0; k < d; k++) t[k] = nv[k] * sp[k];
-            if (phi_tilde(phi, n, d, I, sp, t) < 0.0) hi = 1.0;
+            if (phi_tilde_vals(pv, d, t) < 0.0) hi = 1.0;
         }
         if (hi > 0.0) {
             double lo = 0.0;
@@ -340,7 +385,7 @@ __global__ void k_ghost_geometry(int d, int N, int level, double h, const double
                 const double mid = 0.5 * (lo + hi);
                 double t[3] = {0.0, 0.0, 0.0};
                 for (int k = 0; k < d; k++) t[k] = mid * nv[k] * sp[k];
-                if (phi_tilde(phi, n, d, I, sp, t) < 0.0)
+                if (phi_tilde_vals(pv, d, t) < 0.0)
                     hi = mid;
                 else
                     lo = mid;
@@ -705,9 +750,7 @@ void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_
 }
 
 // Exclusive prefix sum of n counts into ptr[0..n-1], total into ptr[n].
-void launch_scan(const int *counts, int n, int *ptr, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, counts, n, ptr, ptr + n);
-}
+void launch_scan(const int *counts, int n, int *ptr, hipStream_t s) { scan_exclusive(counts, n, ptr, ptr + n, s); }
 
 // Coarse OUTSIDE nodes that the prolongation reads: the corners of the
 // coarse cells holding fine INSIDE / GHOST nodes.  Only these band nodes
