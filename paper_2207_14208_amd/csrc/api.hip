@@ -2,9 +2,11 @@
 // hierarchy, work lists, the cycle launch sequence, hipGraph capture and
 // replay, batches and the single-step entry points.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <mutex>
@@ -85,6 +87,8 @@ struct bcmg_problem {
     double *rhs64 = nullptr;  // finest FP64 right-hand side (f on INSIDE, g(Q) on GHOST)
     double *r64 = nullptr;    // finest FP64 residual scratch
     std::vector<void *> allocs;
+    char *arena = nullptr;       // current zeroed chunk that small arrays are carved from
+    size_t arena_used = 0, arena_size = 0;
     long long bytes = 0;
     // single-step entry points
     Desc *d_step = nullptr;   // [L]
@@ -162,12 +166,40 @@ struct bcmg_batch {
 
 namespace {
 
-bcmg_status dalloc(bcmg_problem *P, void **out, size_t bytes) {
-    *out = nullptr;
-    if (bytes == 0) bytes = 16;
-    bytes = (bytes + 255) & ~size_t(255);
-    // stream-ordered allocation from the device pool: cheap, and the memory
-    // is ready when the setup's final synchronisation returns
+// Setup phase timer: with BCMG_SETUP_TIMING=1 in the environment, setup
+// prints the wall time of its phases (after a stream synchronisation) to
+// stderr.
+struct PhaseTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::chrono::steady_clock::time_point t;
+    explicit PhaseTimer(hipStream_t st) : s(st) {
+        const char *e = getenv("BCMG_SETUP_TIMING");
+        on = e && e[0] == '1';
+        t = std::chrono::steady_clock::now();
+    }
+    void mark(const char *what, int level = -1) {
+        if (!on) return;
+        hipStreamSynchronize(s);
+        const auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "bcmg setup %-14s level %2d %8.3f ms\n", what, level,
+                std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
+thread_local PhaseTimer *t_phase = nullptr;
+#define PHASE(what, level) \
+    do {                   \
+        if (t_phase) t_phase->mark(what, level); \
+    } while (0)
+
+// Zeroed device memory owned by the problem.  Small arrays are carved from
+// zeroed 4 MiB chunks (a problem has ~25 arrays per level: one allocation,
+// one fill and one free per chunk instead of per array); large arrays get
+// their own allocation.  All come from the device's stream-ordered pool.
+constexpr size_t kArenaChunk = 4u << 20;
+
+static bcmg_status dalloc_raw(bcmg_problem *P, void **out, size_t bytes) {
     hipError_t e = hipMallocAsync(out, bytes, P->stream);
     if (e != hipSuccess) {
         *out = nullptr;
@@ -177,6 +209,24 @@ bcmg_status dalloc(bcmg_problem *P, void **out, size_t bytes) {
     if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
     P->allocs.push_back(*out);
     P->bytes += (long long)bytes;
+    return BCMG_OK;
+}
+
+bcmg_status dalloc(bcmg_problem *P, void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes > kArenaChunk / 4) return dalloc_raw(P, out, bytes);
+    if (!P->arena || P->arena_used + bytes > P->arena_size) {
+        void *chunk = nullptr;
+        bcmg_status st = dalloc_raw(P, &chunk, kArenaChunk);
+        if (st) return st;
+        P->arena = (char *)chunk;
+        P->arena_used = 0;
+        P->arena_size = kArenaChunk;
+    }
+    *out = P->arena + P->arena_used;
+    P->arena_used += bytes;
     return BCMG_OK;
 }
 
@@ -190,7 +240,6 @@ bcmg_status dalloc_t(bcmg_problem *P, T **out, size_t count) {
 
 void free_problem_memory(bcmg_problem *P) {
     for (void *p : P->allocs) hipFreeAsync(p, P->stream);
-    hipStreamSynchronize(P->stream);
     P->allocs.clear();
     if (P->h_stage) hipHostFree(P->h_stage);
     P->h_stage = nullptr;
@@ -372,6 +421,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     hipStream_t s = P->stream;
     bcmg_status st;
     launch_classify(d, V.n, V.phi, V.cls, s);
+    PHASE("classify", l);
     // counts of INSIDE and GHOST nodes, ghost list
     launch_compact(V.cls, V.nn, C_INSIDE, scratch_counts, scratch_offsets, nullptr, total_dev, s);
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -387,8 +437,10 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gnew, ng)))
         return st;
     launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
+    PHASE("ghost list", l);
     launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
                           V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, s);
+    PHASE("geometry", l);
     // extension band (only levels that restrict or receive a prolongation need it)
     {
         uint8_t *mark = nullptr;
@@ -413,7 +465,9 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, V.bidx, total_dev, s);
         launch_band_records(d, V.N, V.h, V.phi, V.cls, V.bidx, (int)V.nb, bref, bw, s);
         HIPCHK(hipFreeAsync(tmp, s));
+        PHASE("band", l);
         st = build_ext_rows(P, V, bref, bw, h_total);
+        PHASE("ext rows", l);
         HIPCHK(hipFreeAsync(bref, s));
         HIPCHK(hipFreeAsync(bw, s));
         if (st) return st;
@@ -441,6 +495,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
             }
         }
     }
+    PHASE("segments", l);
     // colour-sorted INSIDE list of a small level (the LDS coarse cycle walks it)
     if (V.nn <= kListNodes) {
         std::vector<uint8_t> hc((size_t)V.nn);
@@ -536,7 +591,6 @@ bcmg_status setup_step_tables(bcmg_problem *P) {
     P->partials_cap = np;
     NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};
     HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
-    HIPCHK(hipHostMalloc((void **)&P->h_stage, sizeof(Desc) * kMaxLevels));
     HIPCHK(hipStreamSynchronize(P->stream));
     return BCMG_OK;
 }
@@ -545,6 +599,7 @@ bool valid_level(const bcmg_problem *P, int l) { return P && l >= 0 && l < P->L;
 
 // upload step descriptors for levels [l0, l0+cnt) with the given pointers
 bcmg_status upload_step_descs(bcmg_problem *P, int l0, int cnt, void *const *u, void *const *rhs, void *const *r) {
+    if (!P->h_stage) HIPCHK(hipHostMalloc((void **)&P->h_stage, sizeof(Desc) * kMaxLevels));
     for (int i = 0; i < cnt; i++) P->h_stage[i] = make_desc(P, l0 + i, u[i], rhs[i], r[i], 0);
     HIPCHK(hipMemcpyAsync(P->d_step + l0, P->h_stage, sizeof(Desc) * cnt, hipMemcpyHostToDevice, P->stream));
     return BCMG_OK;
@@ -643,6 +698,11 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
     P->opt = o;
     P->stream = (hipStream_t)stream;
     keep_pool_memory();
+    PhaseTimer timer(P->stream);
+    t_phase = &timer;
+    struct ClearPhase {
+        ~ClearPhase() { t_phase = nullptr; }
+    } clear_phase;
     P->fp32 = o.precision == BCMG_MIXED;
     int L = 0;
     for (int NN = N; NN >= o.coarsest_N; NN /= 2) L++;
@@ -689,6 +749,7 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
             return bail(st);
         }
     }
+    PHASE("levels", -1);
     for (int l = 1; l < L; l++) {
         if ((st = build_restrict_rows(P, l, h_total)) ||
             (st = build_needed_band(P, l, counts, offsets, flag, h_total))) {
@@ -697,7 +758,9 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
         }
     }
     hipHostFree(h_total);
+    PHASE("rows", -1);
     if ((st = setup_coarse(P))) return bail(st);
+    PHASE("coarse", -1);
     if ((st = dalloc_t(P, &P->rhs64, P->lev[0].nn))) return bail(st);
     if (P->fp32) {
         if ((st = dalloc_t(P, &P->r64, P->lev[0].nn))) return bail(st);
@@ -706,6 +769,7 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
         P->lev[0].rhs = P->rhs64;  // the FP64 cycle reads the finest rhs directly
     }
     if ((st = setup_step_tables(P))) return bail(st);
+    PHASE("tables", -1);
     hipError_t e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) return bail(fail(BCMG_ERR_DEVICE, "setup: %s", hipGetErrorString(e)));
     *out = P;
@@ -717,7 +781,9 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b);
 bcmg_status bcmg_destroy(bcmg_problem *P) {
     if (!P) return BCMG_OK;
     if (P->solo) bcmg_batch_destroy(P->solo);
-    hipStreamSynchronize(P->stream);
+    // the frees are ordered after the work queued on the problem's stream;
+    // the host does not wait (a serving loop retires problems while other
+    // problems are being set up on that stream)
     free_problem_memory(P);
     delete P;
     return BCMG_OK;
@@ -1604,8 +1670,7 @@ bcmg_status bcmg_residual_norm(bcmg_problem *P, const double *u, double *norm_ho
     if (!P || !u || !norm_host) return fail(BCMG_ERR_INVALID, "null argument");
     void *pu[1] = {(void *)u}, *pr[1] = {P->rhs64}, *px[1] = {P->r64};
     bcmg_status st;
-    for (int i = 0; i < 1; i++) P->h_stage[i] = make_desc(P, 0, pu[i], pr[i], px[i], 0);
-    HIPCHK(hipMemcpyAsync(P->d_step, P->h_stage, sizeof(Desc), hipMemcpyHostToDevice, P->stream));
+    if ((st = upload_step_descs(P, 0, 1, pu, pr, px))) return st;
     launch_residual(P->d, 0, 0, 1, P->d_step, P->d_stepitems + P->off_seg[0], P->n_seg[0],
                     P->d_stepitems + P->off_gch[0], P->n_gch[0], P->d_stepst, P->d_partials, P->stream);
     NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};

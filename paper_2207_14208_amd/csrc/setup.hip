@@ -311,7 +311,7 @@ __device__ double dtau_of(int d, double theta, int mode, double cnst) {
 // the finest level, 1 on coarse levels), Q, tau and dtau(theta~ = eta)
 // bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 3.3 eqs. BCh, rel,
 // DtauOptTheta, Remark exptheta2D.
-__global__ void k_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls,
+__global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls,
                                  const int *gidx, int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau,
                                  double *gdtau, double *geta, double *gn, double *gq, int *gfb) {
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,24 +562,55 @@ __device__ int find_sorted(const int *a, int n, int q) {
     return -1;
 }
 
-// Merge of ns sorted sparse rows with weights w: returns the number of
-// distinct indices; writes them (mapped through map when given) and their
-// coefficients sum_s w_s c_s when oidx is not null.
-__device__ int merge_rows(const int *const *idx, const double *const *cf, const int *len, const double *w, int ns,
-                          const int *map, int *oidx, double *ocf) {
-    int pos[kMaxSrc];
-    for (int t = 0; t < ns; t++) pos[t] = 0;
+// Sources of a merged row, one fixed slot each (slots of a 3^d box, or
+// the upwind references), so that every loop over them unrolls into
+// registers: a sorted row (ip, cp, len) or a single entry `one` with
+// coefficient 1; each with weight w.
+template <int NS>
+struct Srcs {
+    const int *ip[NS];
+    const double *cp[NS];
+    int len[NS];
+    int one[NS];
+    double w[NS];
+};
+
+template <int NS>
+__device__ __forceinline__ void srcs_clear(Srcs<NS> &S) {
+#pragma unroll
+    for (int t = 0; t < NS; t++) {
+        S.ip[t] = nullptr;
+        S.cp[t] = nullptr;
+        S.len[t] = 0;
+        S.one[t] = -1;
+        S.w[t] = 0.0;
+    }
+}
+
+// Merge of the sorted source rows: returns the number of distinct indices;
+// writes them (mapped through map when given) and their coefficients
+// sum_t w_t c_t (in slot order) when oidx is not null.
+template <int NS>
+__device__ int merge_srcs(const Srcs<NS> &S, const int *map, int *oidx, double *ocf) {
+    int pos[NS], head[NS];
+#pragma unroll
+    for (int t = 0; t < NS; t++) {
+        pos[t] = 0;
+        head[t] = S.len[t] > 0 ? (S.one[t] >= 0 ? S.one[t] : S.ip[t][0]) : INT32_MAX;
+    }
     int n = 0;
     while (true) {
         int m = INT32_MAX;
-        for (int t = 0; t < ns; t++)
-            if (pos[t] < len[t] && idx[t][pos[t]] < m) m = idx[t][pos[t]];
+#pragma unroll
+        for (int t = 0; t < NS; t++) m = head[t] < m ? head[t] : m;
         if (m == INT32_MAX) break;
         double c = 0.0;
-        for (int t = 0; t < ns; t++)
-            if (pos[t] < len[t] && idx[t][pos[t]] == m) {
-                c += w[t] * cf[t][pos[t]];
+#pragma unroll
+        for (int t = 0; t < NS; t++)
+            if (head[t] == m) {
+                c += S.w[t] * (S.one[t] >= 0 ? 1.0 : S.cp[t][pos[t]]);
                 pos[t]++;
+                head[t] = (S.one[t] < 0 && pos[t] < S.len[t]) ? S.ip[t][pos[t]] : INT32_MAX;
             }
         if (oidx) {
             oidx[n] = map ? map[m] : m;
@@ -592,63 +623,65 @@ __device__ int merge_rows(const int *const *idx, const double *const *cf, const 
 
 // Sweep j (1..K) of the extension rows of every band node b.  Count mode
 // when optr is null (counts[b] = row length), else write mode.
-__global__ void k_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb,
+__global__ __launch_bounds__(128) void k_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb,
                        const int *bref, const double *bw, int j, const int *pptr, const int *pidx,
                        const double *pcf, const int *optr, int *counts, int *oidx, double *ocf) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
-    const int *idx[kMaxSrc];
-    const double *cf[kMaxSrc];
-    int len[kMaxSrc], one[kMaxSrc];
-    double w[kMaxSrc];
-    const double unit = 1.0;
-    int ns = 0;
+    int n;
+    int *oi = optr ? oidx + optr[b] : nullptr;
+    double *oc = optr ? ocf + optr[b] : nullptr;
     if (bref[3 * b] == kRefFallback) {
-        const int n = N + 1;
+        // the mean of the GHOST nodes of the 3^d box, one slot per box position
+        Srcs<27> S;
+        srcs_clear(S);
+        const int nn1 = N + 1;
         int I[3];
-        coords(bidx[b], n, d, I);
-        const int r2 = d >= 3 ? 1 : 0, r1 = d >= 2 ? 1 : 0;
-        for (int m2 = -r2; m2 <= r2; m2++)
-            for (int m1 = -r1; m1 <= r1; m1++)
+        coords(bidx[b], nn1, d, I);
+        int cnt = 0;
+#pragma unroll
+        for (int m2 = -1; m2 <= 1; m2++)
+#pragma unroll
+            for (int m1 = -1; m1 <= 1; m1++)
+#pragma unroll
                 for (int m0 = -1; m0 <= 1; m0++) {
+                    const int t = (m2 + 1) * 9 + (m1 + 1) * 3 + (m0 + 1);
+                    if ((d < 3 && m2 != 0) || (d < 2 && m1 != 0)) continue;
                     const int J[3] = {I[0] + m0, I[1] + m1, I[2] + m2};
                     if (!in_box(J, N, d)) continue;
-                    const long long q = index_of(J, n, d);
+                    const long long q = index_of(J, nn1, d);
                     if (cls[q] != C_GHOST) continue;
-                    one[ns] = find_sorted(gidx, ng, (int)q);
-                    idx[ns] = &one[ns];
-                    cf[ns] = &unit;
-                    len[ns] = 1;
-                    ns++;
+                    S.one[t] = find_sorted(gidx, ng, (int)q);
+                    S.len[t] = 1;
+                    cnt++;
                 }
-        for (int t = 0; t < ns; t++) w[t] = 1.0 / ns;
+#pragma unroll
+        for (int t = 0; t < 27; t++) S.w[t] = S.len[t] ? 1.0 / cnt : 0.0;
+        n = merge_srcs(S, nullptr, oi, oc);
     } else {
+        Srcs<3> S;
+        srcs_clear(S);
         double den = 0.0;
         for (int k = 0; k < d; k++) den += bw[3 * b + k];
-        for (int k = 0; k < d; k++) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            if (k >= d) continue;
             const int ref = bref[3 * b + k];
-            const double wk = bw[3 * b + k] / den;
             if (ref == kRefZero) continue;
             if (ref >= 0) {
                 if (j < 2) continue;  // v^0 = 0 on the band
-                idx[ns] = pidx + pptr[ref];
-                cf[ns] = pcf + pptr[ref];
-                len[ns] = pptr[ref + 1] - pptr[ref];
+                S.ip[k] = pidx + pptr[ref];
+                S.cp[k] = pcf + pptr[ref];
+                S.len[k] = pptr[ref + 1] - pptr[ref];
             } else {
-                one[ns] = find_sorted(gidx, ng, -1 - ref);
-                idx[ns] = &one[ns];
-                cf[ns] = &unit;
-                len[ns] = 1;
+                S.one[k] = find_sorted(gidx, ng, -1 - ref);
+                S.len[k] = 1;
             }
-            w[ns] = wk;
-            ns++;
+            S.w[k] = bw[3 * b + k] / den;
         }
+        n = merge_srcs(S, nullptr, oi, oc);
     }
-    if (!optr) {
-        counts[b] = merge_rows(idx, cf, len, w, ns, nullptr, nullptr, nullptr);
-        return;
-    }
-    merge_rows(idx, cf, len, w, ns, nullptr, oidx + optr[b], ocf + optr[b]);
+    if (!optr) counts[b] = n;
 }
 
 // Restriction rows of the ghosts of a coarse level (Sec. 3.3: full weighting
@@ -656,7 +689,7 @@ __global__ void k_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng
 // renormalised unless the fine 3^d box is complete and has no INSIDE node;
 // or the plain mean).  Fine OUTSIDE nodes contribute through their extension
 // rows; the result is a row over fine ghost nodes (node indices, ascending).
-__global__ void k_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f,
+__global__ __launch_bounds__(128) void k_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f,
                        int ngf, const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
                        int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -664,18 +697,19 @@ __global__ void k_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const 
     const int nc = Nc + 1, nf = Nf + 1;
     int P[3];
     coords(gidx_c[g], nc, d, P);
-    const int *idx[kMaxSrc];
-    const double *cf[kMaxSrc];
-    int len[kMaxSrc], one[kMaxSrc];
-    double w[kMaxSrc];
-    const double unit = 1.0;
-    int ns = 0;
+    Srcs<27> S;
+    srcs_clear(S);
     bool all_ok = true;
     double selw = 0.0;
-    const int r2 = d >= 3 ? 1 : 0, r1 = d >= 2 ? 1 : 0;
-    for (int m2 = -r2; m2 <= r2; m2++)
-        for (int m1 = -r1; m1 <= r1; m1++)
+    int cnt = 0;  // admissible nodes of the box (beyond-band OUTSIDE nodes included)
+#pragma unroll
+    for (int m2 = -1; m2 <= 1; m2++)
+#pragma unroll
+        for (int m1 = -1; m1 <= 1; m1++)
+#pragma unroll
             for (int m0 = -1; m0 <= 1; m0++) {
+                const int t = (m2 + 1) * 9 + (m1 + 1) * 3 + (m0 + 1);
+                if ((d < 3 && m2 != 0) || (d < 2 && m1 != 0)) continue;
                 const int J[3] = {2 * P[0] + m0, 2 * P[1] + m1, 2 * P[2] + m2};
                 if (!in_box(J, Nf, d)) {
                     all_ok = false;
@@ -692,45 +726,33 @@ __global__ void k_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const 
                 }
                 if (c == C_BOXDIR) continue;
                 selw += wgt;
+                cnt++;
                 if (c == C_GHOST) {
-                    one[ns] = find_sorted(gidx_f, ngf, (int)q);
-                    idx[ns] = &one[ns];
-                    cf[ns] = &unit;
-                    len[ns] = 1;
+                    S.one[t] = find_sorted(gidx_f, ngf, (int)q);
+                    S.len[t] = 1;
                 } else {
                     const int bb = find_sorted(bidx_f, nbf, (int)q);
                     if (bb < 0) continue;  // beyond the band: extended value 0
-                    idx[ns] = eidx_f + eptr_f[bb];
-                    cf[ns] = ecf_f + eptr_f[bb];
-                    len[ns] = eptr_f[bb + 1] - eptr_f[bb];
+                    S.ip[t] = eidx_f + eptr_f[bb];
+                    S.cp[t] = ecf_f + eptr_f[bb];
+                    S.len[t] = eptr_f[bb + 1] - eptr_f[bb];
                 }
-                w[ns] = wgt;
-                ns++;
-            }
-    // the number of admissible nodes of the box (for the plain mean) counts
-    // beyond-band OUTSIDE nodes too
-    int cnt = 0;
-    for (int m2 = -r2; m2 <= r2; m2++)
-        for (int m1 = -r1; m1 <= r1; m1++)
-            for (int m0 = -1; m0 <= 1; m0++) {
-                const int J[3] = {2 * P[0] + m0, 2 * P[1] + m1, 2 * P[2] + m2};
-                if (!in_box(J, Nf, d)) continue;
-                const uint8_t c = cls_f[index_of(J, nf, d)];
-                if (c != C_INSIDE && c != C_BOXDIR) cnt++;
+                S.w[t] = wgt;
             }
     if (!all_ok) {
-        for (int t = 0; t < ns; t++) {
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
             if (restrict_mode == BCMG_RESTRICT_PLAIN_MEAN)
-                w[t] = 1.0 / cnt;
+                S.w[t] = S.len[t] ? 1.0 / cnt : 0.0;
             else
-                w[t] = w[t] / selw;
+                S.w[t] = S.w[t] / selw;
         }
     }
     if (!optr) {
-        counts[g] = merge_rows(idx, cf, len, w, ns, gidx_f, nullptr, nullptr);
+        counts[g] = merge_srcs(S, gidx_f, nullptr, nullptr);
         return;
     }
-    merge_rows(idx, cf, len, w, ns, gidx_f, oidx + optr[g], ocf + optr[g]);
+    merge_srcs(S, gidx_f, oidx + optr[g], ocf + optr[g]);
 }
 
 void launch_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, const int *bidx, int nb, const int *bref,

@@ -52,6 +52,12 @@ class ServerStats:
     retried: int = 0
     peak_slots: int = 0
     peak_bytes: int = 0
+    # wall time spent (seconds): batch steps, joining prepared problems,
+    # retiring finished ones (main thread), preparing requests (worker)
+    t_step: float = 0.0
+    t_join: float = 0.0
+    t_retire: float = 0.0
+    t_prepare: float = 0.0
 
     def percentile_ms(self, q: float) -> float:
         lat = [r.latency for r in self.completed if r.latency is not None]
@@ -61,7 +67,7 @@ class ServerStats:
 class Server:
     """Admission by slots and memory budget, continuous batching, retirement."""
 
-    def __init__(self, backend, slots: int, budget_bytes: int, cycles_per_step: int = 2):
+    def __init__(self, backend, slots: int, budget_bytes: int, cycles_per_step: int = 2, workers: int = 2):
         self.backend = backend
         self.slots = slots
         self.budget = budget_bytes
@@ -74,8 +80,10 @@ class Server:
         self.stats = ServerStats()
         self.requeue: list[Request] = []   # failed solves to start again with the fallback options
         self._work: "queue.Queue" = queue.Queue()
-        self._worker = threading.Thread(target=self._prepare_loop, daemon=True)
-        self._worker.start()
+        self._lock = threading.Lock()
+        self._workers = [threading.Thread(target=self._prepare_loop, daemon=True) for _ in range(workers)]
+        for w in self._workers:
+            w.start()
 
     # worker thread: device setup of admitted requests (overlaps with the batch steps)
     def _prepare_loop(self):
@@ -84,15 +92,20 @@ class Server:
             if item is None:
                 return
             req = item
+            t0 = time.perf_counter()
             try:
                 handle = self.backend.prepare(req)
+                with self._lock:
+                    self.stats.t_prepare += time.perf_counter() - t0
                 self.ready.put((req, handle, None))
             except Exception as e:  # setup failure: reject, keep serving
                 self.ready.put((req, None, str(e)))
 
     def close(self):
-        self._work.put(None)
-        self._worker.join(timeout=5)
+        for _ in self._workers:
+            self._work.put(None)
+        for w in self._workers:
+            w.join(timeout=5)
 
     def try_admit(self, req: Request, now: float) -> bool:
         """Admit if a slot is free (counting requests being prepared) and the
@@ -134,12 +147,17 @@ class Server:
             self.stats.peak_slots = max(self.stats.peak_slots, len(self.resident))
 
     def step(self, now_fn) -> None:
+        t0 = time.perf_counter()
         self._join_ready()
+        t1 = time.perf_counter()
+        self.stats.t_join += t1 - t0
         if not self.resident:
             return
         active = self.backend.step(self.cycles_per_step)
         self.stats.steps += 1
         t = now_fn()
+        t2 = time.perf_counter()
+        self.stats.t_step += t2 - t1
         for slot in list(self.resident):
             if active[slot]:
                 continue
@@ -155,6 +173,7 @@ class Server:
             req.status = status
             req.done = t
             self.stats.completed.append(req)
+        self.stats.t_retire += time.perf_counter() - t2
 
     def busy(self) -> bool:
         return bool(self.resident or self.preparing or self.requeue)
@@ -225,7 +244,7 @@ class GPUBackend:
         self.batch = Batch(capacity)
         if coarse_nodes is not None:
             self.batch.set_param(N.PARAM_COARSE_NODES, coarse_nodes)
-        self.side = torch.cuda.Stream()
+        self._local = threading.local()  # one side stream per preparing thread
         self.held: dict[int, tuple] = {}
         self.keep = keep_results
         self.results: dict[int, "torch.Tensor"] = {}   # rid -> final u (keep_results only)
@@ -238,15 +257,18 @@ class GPUBackend:
         from . import workloads as W
         from .solver import Problem
         torch = self.torch
-        with torch.cuda.stream(self.side):
+        side = getattr(self._local, "stream", None)
+        if side is None:
+            side = self._local.stream = torch.cuda.Stream()
+        with torch.cuda.stream(side):
             phi, f = W.sample_sphere_request_torch(req.params)
             opts = self.opts if req.attempts <= 1 else self.fallback
-            G = Problem(3, req.params["side"] - 1, phi, stream=self.side, **opts)
+            G = Problem(3, req.params["side"] - 1, phi, stream=side, **opts)
             ng = G.level_info(0)["n_ghost"]
             G.set_data(f, torch.zeros(ng, dtype=torch.float64, device="cuda"))
             u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
             G.fill_boundary(None, u)
-            self.side.synchronize()
+            side.synchronize()
         info = G.level_info(0)
         return (req.rid, G, u, info["n_inside"] + info["n_ghost"])
 
@@ -328,6 +350,8 @@ def bench(args) -> dict:
         "converged": len(ok), "failed": len(meas) - len(ok), "rejected": len(st.rejected),
         "retried_with_const_dtau": sum(1 for r in meas if r.attempts > 1),
         "peak_slots": st.peak_slots, "peak_bytes": st.peak_bytes,
+        "wall_s": {"span": span, "steps": st.t_step, "join": st.t_join, "retire": st.t_retire,
+                   "prepare_worker": st.t_prepare, "batch_steps": st.steps},
     }
     be.close()
     return res
