@@ -77,6 +77,7 @@ PROTOTYPES = {
     "bcmg_problem_bytes": (i32, [vp, P(i64)]),
     "bcmg_timing_enable": (i32, [i32]),
     "bcmg_timing_read": (i32, [P(i64), P(dbl), P(i64)]),
+    "bcmg_timing_sweeps": (i32, [vp, vp, i32, P(dbl)]),
 }
 
 

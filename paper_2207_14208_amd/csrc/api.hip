@@ -1700,4 +1700,33 @@ bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *nodes
     return BCMG_OK;
 }
 
+bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, double *ms) {
+    bcmg_status st = check_fp64_step(P, 0);
+    if (st) return st;
+    if (!u || !ms || reps < 1) return fail(BCMG_ERR_INVALID, "bad argument");
+    const LevelH &V = P->lev[0];
+    double *scratch = (double *)V.r;  // residual scratch of the finest level
+    HIPCHK(hipMemcpyAsync(scratch, u, sizeof(double) * V.nn, hipMemcpyDeviceToDevice, P->stream));
+    void *pu[1] = {scratch}, *pr[1] = {P->rhs64}, *px[1] = {V.r};
+    if ((st = upload_step_descs(P, 0, 1, pu, pr, px))) return st;
+    const Item *segs = P->d_stepitems + P->off_seg[0];
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);  // warm
+    HIPCHK(hipEventRecord(e0, P->stream));
+    for (int i = 0; i < reps; i++) {
+        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);
+        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 1, P->d_stepst, P->stream);
+    }
+    HIPCHK(hipEventRecord(e1, P->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = t;
+    return BCMG_OK;
+}
+
 }  // extern "C"

@@ -156,6 +156,12 @@ class Problem:
     def coarse_solve(self, u, rhs):
         check(lib().bcmg_coarse_solve(self.h, _ptr(u), _ptr(rhs)))
 
+    def timing_sweeps(self, u: torch.Tensor, reps: int) -> float:
+        """ms for `reps` back-to-back red + black finest-level sweeps on a copy of u."""
+        v = C.c_double()
+        check(lib().bcmg_timing_sweeps(self.h, _ptr(u), int(reps), C.byref(v)))
+        return v.value
+
     def device_bytes(self) -> int:
         b = C.c_int64()
         check(lib().bcmg_problem_bytes(self.h, C.byref(b)))
