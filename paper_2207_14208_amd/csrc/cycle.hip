@@ -211,6 +211,31 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
 // Restriction to coarse ghost g: its precomputed row over the fine ghost
 // residuals (FW or renormalised FW of the extended fine residual, with the
 // extension folded in); zeroes the coarse unknown.
+// sum over j in [beg, end) of coef[j] * value(idx[j]), accumulated in j
+// order; the row's index and coefficient loads, then the value loads, go
+// out eight at a time (a row walked one entry per wait costs a memory
+// latency per entry)
+template <typename F>
+__device__ __forceinline__ double row_dot(gcp<int> idx, gcp<double> coef, int beg, int end, F value) {
+    double v = 0.0;
+    for (int j = beg; j < end; j += 8) {
+        int ix[8];
+        double cf[8], x[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int jj = min(j + k, end - 1);
+            ix[k] = idx[jj];
+            cf[k] = coef[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) x[k] = value(ix[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (j + k < end) v += cf[k] * x[k];
+    }
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g, bool live) {
     gcp<T> __restrict__ r = (gcp<T>)F.r;
@@ -218,23 +243,7 @@ __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int
     gcp<double> rcoef = (gcp<double>)C.rcoef;
     const int beg = rptr[g], end = rptr[g + 1];
     const long long pc = ((gcp<int>)C.gidx)[g];
-    // eight independent loads in flight per step; the sum keeps the row order
-    double acc = 0.0;
-    int j = beg;
-    for (; j + 8 <= end; j += 8) {
-        int ix[8];
-        double cf[8], rv[8];
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            ix[k] = ridx[j + k];
-            cf[k] = rcoef[j + k];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; k++) rv[k] = (double)r[ix[k]];
-#pragma unroll
-        for (int k = 0; k < 8; k++) acc += cf[k] * rv[k];
-    }
-    for (; j < end; j++) acc += rcoef[j] * (double)r[ridx[j]];
+    const double acc = row_dot(ridx, rcoef, beg, end, [&](int q) { return (double)r[q]; });
     if (!live) return;
     ((gp<T>)C.rhs)[pc] = (T)acc;
     ((gp<T>)C.u)[pc] = (T)0;
@@ -358,15 +367,13 @@ __device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live
 template <typename T>
 __device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *gsrc, bool live) {
     gp<T> field = (gp<T>)L.u;
-    gcp<int> eidx = (gcp<int>)L.eidx, gidx = (gcp<int>)L.gidx;
-    gcp<double> ecoef = (gcp<double>)L.ecoef, src = (gcp<double>)gsrc;
+    gcp<int> gidx = (gcp<int>)L.gidx;
+    gcp<double> src = (gcp<double>)gsrc;
     const int beg = ((gcp<int>)L.eptr)[b], end = ((gcp<int>)L.eptr)[b + 1];
     const long long p = ((gcp<int>)L.bidx)[b];
-    double v = 0.0;
-    for (int j = beg; j < end; j++) {
-        const int g = eidx[j];
-        v += ecoef[j] * (src ? src[g] : (double)field[gidx[g]]);
-    }
+    const double v =
+        src ? row_dot((gcp<int>)L.eidx, (gcp<double>)L.ecoef, beg, end, [&](int g) { return src[g]; })
+            : row_dot((gcp<int>)L.eidx, (gcp<double>)L.ecoef, beg, end, [&](int g) { return (double)field[gidx[g]]; });
     if (!live) return;
     field[p] = (T)v;
 }
@@ -799,23 +806,9 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
     }
     for (int g = threadIdx.x; g < C.ng; g += kCoarseThreads) {
         const int beg = C.rptr[g], end = C.rptr[g + 1];
-        double acc = 0.0;
-        int e = beg;
-        for (; e + 8 <= end; e += 8) {
-            int ix[8];
-            double cf[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                ix[k] = C.ridx[e + k];
-                cf[k] = C.rcoef[e + k];
-            }
-            double rv[8];
-#pragma unroll
-            for (int k = 0; k < 8; k++) rv[k] = (double)(F.rg ? ((gcp<T>)F.rg)[ix[k]] : F.r[ix[k]]);
-#pragma unroll
-            for (int k = 0; k < 8; k++) acc += cf[k] * rv[k];
-        }
-        for (; e < end; e++) acc += C.rcoef[e] * (double)(F.rg ? ((gcp<T>)F.rg)[C.ridx[e]] : F.r[C.ridx[e]]);
+        const double acc =
+            F.rg ? row_dot(C.ridx, C.rcoef, beg, end, [&](int q) { return (double)((gcp<T>)F.rg)[q]; })
+                 : row_dot(C.ridx, C.rcoef, beg, end, [&](int q) { return (double)F.r[q]; });
         const int p = C.gidx[g];
         C.rhs[p] = (T)acc;
         C.u[p] = (T)0;
@@ -827,8 +820,7 @@ template <typename T>
 __device__ void lds_extend(const LdsView<T> &L) {
     for (int t = threadIdx.x; t < L.nbn; t += kCoarseThreads) {
         const int b = L.bneed[t];
-        double v = 0.0;
-        for (int e = L.eptr[b]; e < L.eptr[b + 1]; e++) v += L.ecoef[e] * (double)L.u[L.gidx[L.eidx[e]]];
+        const double v = row_dot(L.eidx, L.ecoef, L.eptr[b], L.eptr[b + 1], [&](int g) { return (double)L.u[L.gidx[g]]; });
         L.u[L.bidx[b]] = (T)v;
     }
     __syncthreads();
