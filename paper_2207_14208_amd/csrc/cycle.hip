@@ -846,119 +846,133 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
     const LdsProg &P = progs[blockIdx.x];
     if (!st[P.slot].active) return;
     __shared__ LdsView<T> V[kMaxLevels];
-    if (threadIdx.x == 0) {
-        for (int a = 0; a <= P.top; a++) {
-            const LdsLevel &Q = P.lev[a];
-            const Desc &G = descs[Q.desc];
-            LdsView<T> &W = V[a];
-            W.n = G.n;
-            W.N = G.N;
-            W.nn = Q.nn;
-            W.ng = Q.ng;
-            W.nb = Q.nb;
-            W.ni = Q.ni;
-            W.nred = Q.nred;
-            W.ilist = lds_ptr<int>(lds, Q.ilist);
-            W.nbn = Q.nbn;
-            W.bneed = lds_ptr<int>(lds, Q.bneed);
-            W.sy = G.sy;
-            W.sz = G.sz;
-            W.h2 = G.h2;
-            W.cls = lds_ptr<uint8_t>(lds, Q.cls);
-            W.u = lds_ptr<T>(lds, Q.u);
-            W.rhs = lds_ptr<T>(lds, Q.rhs);
-            W.r = lds_ptr<T>(lds, Q.r < 0 ? 0 : Q.r);
-            W.rg = Q.r < 0 ? (gp<T>)G.r : nullptr;
-            W.gidx = lds_ptr<int>(lds, Q.gidx);
-            W.gcode = lds_ptr<int>(lds, Q.gcode);
-            W.gtau = lds_ptr<double>(lds, Q.gtau);
-            W.gdtau = lds_ptr<double>(lds, Q.gdtau);
-            W.gnew = lds_ptr<double>(lds, Q.gnew);
-            W.eptr = (gcp<int>)G.eptr;
-            W.eidx = (gcp<int>)G.eidx;
-            W.ecoef = (gcp<double>)G.ecoef;
-            W.bidx = (gcp<int>)G.bidx;
-            W.rptr = (gcp<int>)G.rptr;
-            W.ridx = (gcp<int>)G.ridx;
-            W.rcoef = (gcp<double>)G.rcoef;
-        }
+    // staging: one flat list of copies (4-byte words; every staged array is
+    // a whole number of words, class arrays are padded allocations).  Thread
+    // a sets up level a: its view and its kStage copy entries (word counts
+    // at first, turned into offsets by the scan below; an empty entry is
+    // never the segment of a word).  The top level's u is staged only when
+    // it is the caller's array: else its unknowns are zero after the
+    // restriction, and its other nodes are not read before the extension
+    // writes them, so it is zero-filled like the levels below.
+    constexpr int kStage = 9;
+    __shared__ const uint32_t *csrc[kMaxLevels * kStage];
+    __shared__ int cdst[kMaxLevels * kStage], cbeg[kMaxLevels * kStage + 1];
+    const int top = P.top;
+    const bool finest = P.finest != 0;
+    if ((int)threadIdx.x <= top) {
+        const int a = threadIdx.x;
+        const LdsLevel &Q = P.lev[a];
+        const Desc &G = descs[Q.desc];
+        LdsView<T> &W = V[a];
+        W.n = G.n;
+        W.N = G.N;
+        W.nn = Q.nn;
+        W.ng = Q.ng;
+        W.nb = Q.nb;
+        W.ni = Q.ni;
+        W.nred = Q.nred;
+        W.ilist = lds_ptr<int>(lds, Q.ilist);
+        W.nbn = Q.nbn;
+        W.bneed = lds_ptr<int>(lds, Q.bneed);
+        W.sy = G.sy;
+        W.sz = G.sz;
+        W.h2 = G.h2;
+        W.cls = lds_ptr<uint8_t>(lds, Q.cls);
+        W.u = lds_ptr<T>(lds, Q.u);
+        W.rhs = lds_ptr<T>(lds, Q.rhs);
+        W.r = lds_ptr<T>(lds, Q.r < 0 ? 0 : Q.r);
+        W.rg = Q.r < 0 ? (gp<T>)G.r : nullptr;
+        W.gidx = lds_ptr<int>(lds, Q.gidx);
+        W.gcode = lds_ptr<int>(lds, Q.gcode);
+        W.gtau = lds_ptr<double>(lds, Q.gtau);
+        W.gdtau = lds_ptr<double>(lds, Q.gdtau);
+        W.gnew = lds_ptr<double>(lds, Q.gnew);
+        W.eptr = (gcp<int>)G.eptr;
+        W.eidx = (gcp<int>)G.eidx;
+        W.ecoef = (gcp<double>)G.ecoef;
+        W.bidx = (gcp<int>)G.bidx;
+        W.rptr = (gcp<int>)G.rptr;
+        W.ridx = (gcp<int>)G.ridx;
+        W.rcoef = (gcp<double>)G.rcoef;
+        int e = a * kStage;
+        auto add = [&](const void *src, int lds_off, long long bytes) {
+            csrc[e] = (const uint32_t *)src;
+            cdst[e] = lds_off / 4;
+            cbeg[e] = (int)((bytes + 3) / 4);
+            e++;
+        };
+        add(G.cls, Q.cls, Q.nn);
+        add(G.gidx, Q.gidx, 4LL * Q.ng);
+        add(G.gcode, Q.gcode, 4LL * Q.ng);
+        add(G.gtau, Q.gtau, 24LL * Q.ng);
+        add(G.gdtau, Q.gdtau, 8LL * Q.ng);
+        add(G.ilist, Q.ilist, 4LL * Q.ni);
+        add(G.bneed, Q.bneed, 4LL * Q.nbn);
+        add(G.rhs, Q.rhs, a == top ? (long long)sizeof(T) * Q.nn : 0);
+        add(G.u, Q.u, a == top && finest ? (long long)sizeof(T) * Q.nn : 0);
     }
     __syncthreads();
-    // staging: one flat list of copies (4-byte words; every staged array is
-    // a whole number of words, class arrays are padded allocations), walked
-    // by all threads with sixteen loads in flight each
-    __shared__ const uint32_t *csrc[kMaxLevels * 8];
-    __shared__ int cdst[kMaxLevels * 8], cbeg[kMaxLevels * 8 + 1];
-    __shared__ int ncopy;
+    const int n = (top + 1) * kStage;
     if (threadIdx.x == 0) {
-        int n = 0, w = 0;
-        auto add = [&](const void *src, int lds_off, long long bytes) {
-            if (bytes <= 0) return;
-            csrc[n] = (const uint32_t *)src;
-            cdst[n] = lds_off / 4;
-            cbeg[n] = w;
-            w += (int)((bytes + 3) / 4);
-            n++;
-        };
-        for (int a = 0; a <= P.top; a++) {
-            const LdsLevel &Q = P.lev[a];
-            const Desc &G = descs[Q.desc];
-            add(G.cls, Q.cls, Q.nn);
-            add(G.gidx, Q.gidx, 4LL * Q.ng);
-            add(G.gcode, Q.gcode, 4LL * Q.ng);
-            add(G.gtau, Q.gtau, 24LL * Q.ng);
-            add(G.gdtau, Q.gdtau, 8LL * Q.ng);
-            add(G.ilist, Q.ilist, 4LL * Q.ni);
-            add(G.bneed, Q.bneed, 4LL * Q.nbn);
-            if (a == P.top) {
-                add(G.u, Q.u, (long long)sizeof(T) * Q.nn);
-                add(G.rhs, Q.rhs, (long long)sizeof(T) * Q.nn);
-            }
+        int w = 0;
+        for (int e = 0; e < n; e++) {
+            const int c = cbeg[e];
+            cbeg[e] = w;
+            w += c;
         }
         cbeg[n] = w;
-        ncopy = n;
     }
     __syncthreads();
     {
-        const int n = ncopy, total = cbeg[n];
+        // U words per thread per round: the segment searches first, then
+        // every load, then the LDS stores, so that the loads of a round are
+        // in flight together
+        const int total = cbeg[n];
         lp<uint32_t> words = (lp<uint32_t>)lds;
         constexpr int U = 16;
         for (int w0 = threadIdx.x; w0 < total; w0 += U * kCoarseThreads) {
-            uint32_t v[U];
+            // segment of each word: the last entry starting at or before it,
+            // by a fixed-step search run for the U words side by side
+            int w[U], lo[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                w[k] = min(w0 + k * kCoarseThreads, total - 1);
+                lo[k] = 0;
+            }
+            // branch-free steps: each reads cbeg for all U words, then waits once
+            for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1) {
+                int cb[U];
+#pragma unroll
+                for (int k = 0; k < U; k++) cb[k] = cbeg[min(lo[k] + step, n)];
+#pragma unroll
+                for (int k = 0; k < U; k++) pin(cb[k]);
+#pragma unroll
+                for (int k = 0; k < U; k++) lo[k] = lo[k] + step < n && cb[k] <= w[k] ? lo[k] + step : lo[k];
+            }
+            const uint32_t *sp[U];
             int dst[U];
 #pragma unroll
             for (int k = 0; k < U; k++) {
-                const int w = w0 + k * kCoarseThreads;
-                dst[k] = -1;
-                if (w >= total) continue;
-                int lo = 0, hi = n - 1;  // segment holding word w
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (cbeg[mid] <= w)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                v[k] = ((gcp<uint32_t>)csrc[lo])[w - cbeg[lo]];
-                dst[k] = cdst[lo] + (w - cbeg[lo]);
+                sp[k] = csrc[lo[k]] + (w[k] - cbeg[lo[k]]);
+                dst[k] = cdst[lo[k]] + (w[k] - cbeg[lo[k]]);
             }
+            uint32_t v[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) v[k] = *(gcp<uint32_t>)sp[k];
 #pragma unroll
             for (int k = 0; k < U; k++)
-                if (dst[k] >= 0) words[dst[k]] = v[k];
+                if (w0 + k * kCoarseThreads < total) words[dst[k]] = v[k];
         }
     }
-    for (int a = 0; a <= P.top; a++) {
-        const LdsLevel &Q = P.lev[a];
+    for (int a = 0; a <= top; a++) {
         const LdsView<T> &W = V[a];
-        if (a != P.top) {
-            lds_zero(W.u, Q.nn);
-            lds_zero(W.rhs, Q.nn);
-        }
-        if (Q.r >= 0) lds_zero(W.r, Q.nn);
+        if (a != top || !finest) lds_zero(W.u, W.nn);
+        if (a != top) lds_zero(W.rhs, W.nn);
+        if (!W.rg) lds_zero(W.r, W.nn);
     }
     __syncthreads();
     const int mode = descs[P.lev[0].desc].restrict_mode;
-    for (int a = P.top; a >= 1; a--) {
+    for (int a = top; a >= 1; a--) {
         for (int i = 0; i < nu1; i++) lds_smooth<D, T>(V[a]);
         lds_residual<D, T>(V[a]);
         lds_restrict<D, T>(V[a - 1], V[a], mode);
@@ -973,15 +987,14 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
             for (int t = threadIdx.x; t < G.nc; t += kCoarseThreads) {
                 gcp<double> row = ainv + (long long)t * G.nc;
                 double x = 0.0;
-                int j = 0;
-                for (; j + 8 <= G.nc; j += 8) {  // eight loads in flight, sum in row order
+                for (int j = 0; j < G.nc; j += 8) {  // eight loads in flight, sum in row order
                     double a[8];
 #pragma unroll
-                    for (int k = 0; k < 8; k++) a[k] = row[j + k];
+                    for (int k = 0; k < 8; k++) a[k] = row[min(j + k, G.nc - 1)];
 #pragma unroll
-                    for (int k = 0; k < 8; k++) x += a[k] * bsh[j + k];
+                    for (int k = 0; k < 8; k++)
+                        if (j + k < G.nc) x += a[k] * bsh[j + k];
                 }
-                for (; j < G.nc; j++) x += row[j] * bsh[j];
                 V[0].u[cmap[t]] = (T)x;
             }
             __syncthreads();
@@ -989,17 +1002,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
             for (int i = 0; i < 50; i++) lds_smooth<D, T>(V[0]);
         }
     }
-    for (int a = 1; a <= P.top; a++) {
+    for (int a = 1; a <= top; a++) {
         lds_extend<T>(V[a - 1]);
         lds_prolong<D, T>(V[a], V[a - 1]);
         for (int i = 0; i < nu2; i++) lds_smooth<D, T>(V[a]);
     }
-    if (P.ext_top) lds_extend<T>(V[P.top]);
-    const LdsView<T> &W = V[P.top];
-    gp<T> ug = (gp<T>)descs[P.lev[P.top].desc].u;
+    if (P.ext_top) lds_extend<T>(V[top]);
+    const LdsView<T> &W = V[top];
+    gp<T> ug = (gp<T>)descs[P.lev[top].desc].u;
     for (int p = threadIdx.x; p < W.nn; p += kCoarseThreads) {
         const int c = W.cls[p];
-        if (P.finest && c != C_INSIDE && c != C_GHOST) continue;
+        if (finest && c != C_INSIDE && c != C_GHOST) continue;
         ug[p] = W.u[p];
     }
 }
