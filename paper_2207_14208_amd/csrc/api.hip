@@ -116,6 +116,11 @@ struct Lists {
     int ncbch = 0;
     Item *cgch = nullptr;  // ghost chunks of the next coarser level (restriction)
     int ncgch = 0;
+    // segments of the problems whose finest level this is: the first red
+    // half-sweep of the pre-smoothing runs on them only (on the others the
+    // restriction into the level has done it)
+    Item *rsegs = nullptr;
+    int nrseg = 0;
 };
 
 struct bcmg_batch {
@@ -1118,8 +1123,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     // work lists
     std::vector<Item> items;
     struct Off {
-        size_t seg, gch, bch, cseg, cbch, cgch;
-        int nseg, ngch, nbch, ncseg, ncbch, ncgch;
+        size_t seg, gch, bch, cseg, cbch, cgch, rseg;
+        int nseg, ngch, nbch, ncseg, ncbch, ncgch, nrseg;
     };
     std::vector<Off> off(A);
     auto add_segs = [&](int desc, const LevelH &V) {
@@ -1169,6 +1174,10 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
                 append_chunks(items, base[s] + l + 1, b->prob[s]->lev[l + 1].ng);
             }
         o.ncgch = (int)(items.size() - o.cgch);
+        o.rseg = items.size();
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L - 1 == a) add_segs(base[s], b->prob[s]->lev[0]);
+        o.nrseg = (int)(items.size() - o.rseg);
     }
     // finest lists over the outer descriptors, with per-slot norm ranges
     std::vector<NormRange> ranges(b->cap, NormRange{0, 0, 0, 0});
@@ -1319,6 +1328,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         L.ncbch = o.ncbch;
         L.cgch = b->d_items + o.cgch;
         L.ncgch = o.ncgch;
+        L.rsegs = b->d_items + o.rseg;
+        L.nrseg = o.nrseg;
     }
     b->fsegs = b->d_items + fseg0;
     b->nfseg = nfseg;
@@ -1330,7 +1341,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     return BCMG_OK;
 }
 
-static void timed_sweep(bcmg_batch *b, int a, int colour) {
+static void timed_sweep(bcmg_batch *b, int a, int colour, bool first = false) {
     const Lists &L = b->lv[a];
     const bool fine = g_timing.on && a == b->A - 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1339,7 +1350,8 @@ static void timed_sweep(bcmg_batch *b, int a, int colour) {
         hipEventCreate(&e1);
         hipEventRecord(e0, b->stream);
     }
-    launch_rb_sweep(b->d, b->fp32, b->d_desc, L.segs, L.nseg, colour, b->d_state, b->stream);
+    launch_rb_sweep(b->d, b->fp32, b->d_desc, first ? L.rsegs : L.segs, first ? L.nrseg : L.nseg, colour, b->d_state,
+                    b->stream);
     if (fine) {
         hipEventRecord(e1, b->stream);
         b->tev.push_back({e0, e1});
@@ -1348,8 +1360,10 @@ static void timed_sweep(bcmg_batch *b, int a, int colour) {
 
 // one smoothing step on aligned level a; ext: band chunks to extend into
 // after the ghost step (the level's error before its prolongation)
-static void smooth(bcmg_batch *b, int a, const Item *ext = nullptr, int next = 0) {
-    timed_sweep(b, a, 0);
+// first: the first step of the pre-smoothing (its red half-sweep covers the
+// problems whose finest level this is only)
+static void smooth(bcmg_batch *b, int a, const Item *ext = nullptr, int next = 0, bool first = false) {
+    timed_sweep(b, a, 0, first);
     timed_sweep(b, a, 1);
     const Lists &L = b->lv[a];
     launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream, ext, next);
@@ -1366,9 +1380,11 @@ static void launch_vcycle(bcmg_batch *b) {
     for (int a = b->A - 1; a > b->Ac; a--) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
-        for (int i = 0; i < b->nu1; i++) smooth(b, a);
+        for (int i = 0; i < b->nu1; i++) smooth(b, a, nullptr, 0, i == 0);
         launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s);
-        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s);
+        // a coarse level cycled by launches gets its first red half-sweep here
+        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
+                        b->nu1 > 0 && a - 1 > b->Ac);
     }
     if (b->lds_bytes)
         launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s);

@@ -195,22 +195,29 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
 // Sec. 3.3) to a coarse INSIDE node; also zeroes the coarse unknown (initial
 // guess of the coarse correction).  Coarse GHOST nodes are done by
 // restrict_ghost.
+// With red, the node also takes the first red half-sweep of the coarse
+// pre-smoothing: from the zero initial guess every neighbour of an INSIDE
+// node is zero, so the update of a red node (i+j+k even) is h^2 f / (2d),
+// computed as the sweep computes it (a zero neighbour sum added).
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
-                                              bool ok) {
+                                              bool ok, bool red) {
     const double out = restrict_inside_at<D>((gcp<T>)F.r, (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
                                              C.restrict_mode);
     const int cc = ((gcp<uint8_t>)C.cls)[pc];
     pin(out);
     pin(cc);
     if (!ok || cc != C_INSIDE) return;
-    ((gp<T>)C.u)[pc] = (T)0;
-    ((gp<T>)C.rhs)[pc] = (T)out;
+    const T fv = (T)out;
+    T uv = (T)0;
+    if (red && (((X0 + X1 + X2) >> 1) & 1) == 0) {
+        const T sum = (T)0;
+        uv = ((T)C.h2 * fv + sum) / (T)(2 * D);
+    }
+    ((gp<T>)C.u)[pc] = uv;
+    ((gp<T>)C.rhs)[pc] = fv;
 }
 
-// Restriction to coarse ghost g: its precomputed row over the fine ghost
-// residuals (FW or renormalised FW of the extended fine residual, with the
-// extension folded in); zeroes the coarse unknown.
 // sum over j in [beg, end) of coef[j] * value(idx[j]), accumulated in j
 // order; the row's index and coefficient loads, then the value loads, go
 // out eight at a time (a row walked one entry per wait costs a memory
@@ -236,6 +243,9 @@ __device__ __forceinline__ double row_dot(gcp<int> idx, gcp<double> coef, int be
     return v;
 }
 
+// Restriction to coarse ghost g: its precomputed row over the fine ghost
+// residuals (FW or renormalised FW of the extended fine residual, with the
+// extension folded in); zeroes the coarse unknown.
 template <typename T>
 __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g, bool live) {
     gcp<T> __restrict__ r = (gcp<T>)F.r;
@@ -250,13 +260,14 @@ __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane, bool live) {
+__device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane, bool live,
+                                             bool red) {
     const Seg s = seg_of(it);
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
         const int qq = q < s.len ? q : 0;
-        restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, live && q < s.len);
+        restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, live && q < s.len, red);
     }
 }
 
@@ -548,11 +559,11 @@ __global__ __launch_bounds__(kBlock) void k_ext_gather(const Desc *__restrict__ 
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
-                                                     const SlotState *__restrict__ st) {
+                                                     const SlotState *__restrict__ st, int red) {
     const int lb = xcd_block(nseg_blocks);
     if (lb < nseg_blocks) {
         SEG_ITEM_AT(lb)
-        seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live);
+        seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live, red != 0);
         return;
     }
     const Item it = gch[lb - nseg_blocks];
@@ -671,7 +682,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
         const CoarseLevel &cv = P.lev[a - 1];
         for (int s = wave; s < cv.nseg; s += kCoarseWaves) {
             const Item it = items[cv.seg + s];
-            seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane, true);
+            seg_restrict<D, T>(descs[it.x], descs[it.x - 1], it, lane, true, false);
         }
         for (int c = grp; c < cv.ngch; c += ngrp) {
             const Item it = items[cv.gch + c];
@@ -1095,14 +1106,14 @@ void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, i
 }
 
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
-                     const SlotState *st, hipStream_t s) {
+                     const SlotState *st, hipStream_t s, int red) {
     const int sb = blocks_for_segs(nseg);
     if (sb + ncgch <= 0) return;
     dim3 g(sb + ncgch), b(kBlock);
     if (fp32)
-        DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, cgch, sb, st);
+        DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, cgch, sb, st, red);
     else
-        DISPATCH_D(d, k_restrict, double, g, b, 0, s, descs, csegs, nseg, cgch, sb, st);
+        DISPATCH_D(d, k_restrict, double, g, b, 0, s, descs, csegs, nseg, cgch, sb, st, red);
 }
 
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,

@@ -21,9 +21,11 @@ void launch_norm_finish(const NormRange *ranges, int nslots, const double *parti
 // via_need: the chunks run over the needed band entries (bneed) instead of all of them
 void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,
                        hipStream_t s);
-// restriction into the coarse segments csegs (INSIDE rows) and coarse ghost chunks cgch
+// restriction into the coarse segments csegs (INSIDE rows) and coarse ghost chunks cgch;
+// red: the coarse INSIDE rows also take the first red half-sweep of their
+// pre-smoothing (from the zero initial guess)
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
-                     const SlotState *st, hipStream_t s);
+                     const SlotState *st, hipStream_t s, int red = 0);
 void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int nseg, const SlotState *st,
                     hipStream_t s);
 void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s);
