@@ -218,29 +218,65 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
     ((gp<T>)C.rhs)[pc] = fv;
 }
 
-// sum over j in [beg, end) of coef[j] * value(idx[j]), accumulated in j
-// order; the row's index and coefficient loads, then the value loads, go
-// out eight at a time (a row walked one entry per wait costs a memory
-// latency per entry)
+// Sparse row sums.  The sum over j in [beg, end) of coef[j] * value(idx[j])
+// is defined as eight strided partial sums, partial k over j = beg + k,
+// beg + k + 8, ... in increasing j, added as ((p0 + p1) + (p2 + p3)) +
+// ((p4 + p5) + (p6 + p7)).  row_dot computes it in one thread, row_dot_group
+// with eight lanes (one partial each, a shuffle tree), so that every path
+// gives the same bits.
+constexpr int kRowLanes = 8;
+
+__device__ __forceinline__ double row_tree(const double (&a)[kRowLanes]) {
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 template <typename F>
 __device__ __forceinline__ double row_dot(gcp<int> idx, gcp<double> coef, int beg, int end, F value) {
-    double v = 0.0;
-    for (int j = beg; j < end; j += 8) {
-        int ix[8];
-        double cf[8], x[8];
+    double a[kRowLanes] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = beg; j < end; j += kRowLanes) {  // eight entries' loads in flight per step
+        int ix[kRowLanes];
+        double cf[kRowLanes], x[kRowLanes];
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
+        for (int k = 0; k < kRowLanes; k++) {
             const int jj = min(j + k, end - 1);
             ix[k] = idx[jj];
             cf[k] = coef[jj];
         }
 #pragma unroll
-        for (int k = 0; k < 8; k++) x[k] = value(ix[k]);
+        for (int k = 0; k < kRowLanes; k++) x[k] = value(ix[k]);
 #pragma unroll
-        for (int k = 0; k < 8; k++)
-            if (j + k < end) v += cf[k] * x[k];
+        for (int k = 0; k < kRowLanes; k++)
+            if (j + k < end) a[k] += cf[k] * x[k];
     }
-    return v;
+    return row_tree(a);
+}
+
+// The same sum by the eight lanes sub = 0..7 of an aligned lane group (all
+// eight call it together; each gets the sum).  A lane keeps four of its
+// entries' loads in flight per step.
+template <typename F>
+__device__ __forceinline__ double row_dot_group(gcp<int> idx, gcp<double> coef, int beg, int end, int sub, F value) {
+    constexpr int M = 4;
+    double a = 0.0;
+    for (int j = beg + sub; j < end; j += M * kRowLanes) {
+        int ix[M];
+        double cf[M], x[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            const int jj = max(min(j + m * kRowLanes, end - 1), beg);
+            ix[m] = idx[jj];
+            cf[m] = coef[jj];
+        }
+#pragma unroll
+        for (int m = 0; m < M; m++) x[m] = value(ix[m]);
+#pragma unroll
+        for (int m = 0; m < M; m++)
+            if (j + m * kRowLanes < end) a += cf[m] * x[m];
+    }
+    a += __shfl_xor(a, 1);
+    a += __shfl_xor(a, 2);
+    a += __shfl_xor(a, 4);
+    return a;
 }
 
 // Restriction to coarse ghost g: its precomputed row over the fine ghost
@@ -255,6 +291,19 @@ __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int
     const long long pc = ((gcp<int>)C.gidx)[g];
     const double acc = row_dot(ridx, rcoef, beg, end, [&](int q) { return (double)r[q]; });
     if (!live) return;
+    ((gp<T>)C.rhs)[pc] = (T)acc;
+    ((gp<T>)C.u)[pc] = (T)0;
+}
+
+// restrict_ghost by the eight lanes sub of a group (one coarse ghost each group)
+template <typename T>
+__device__ __forceinline__ void restrict_ghost_group(const Desc &C, const Desc &F, int g, int sub, bool live) {
+    gcp<T> __restrict__ r = (gcp<T>)F.r;
+    const int beg = ((gcp<int>)C.rptr)[g], end = ((gcp<int>)C.rptr)[g + 1];
+    const long long pc = ((gcp<int>)C.gidx)[g];
+    const double acc =
+        row_dot_group((gcp<int>)C.ridx, (gcp<double>)C.rcoef, beg, end, sub, [&](int q) { return (double)r[q]; });
+    if (!live || sub != 0) return;
     ((gp<T>)C.rhs)[pc] = (T)acc;
     ((gp<T>)C.u)[pc] = (T)0;
 }
@@ -389,6 +438,27 @@ __device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *g
     field[p] = (T)v;
 }
 
+// ext_gather by the eight lanes sub of a group (one band entry each group)
+template <typename T>
+__device__ __forceinline__ void ext_gather_group(const Desc &L, int b, const double *gsrc, int sub, bool live) {
+    gp<T> field = (gp<T>)L.u;
+    gcp<int> gidx = (gcp<int>)L.gidx;
+    gcp<double> src = (gcp<double>)gsrc;
+    const int beg = ((gcp<int>)L.eptr)[b], end = ((gcp<int>)L.eptr)[b + 1];
+    const long long p = ((gcp<int>)L.bidx)[b];
+    gcp<int> eidx = (gcp<int>)L.eidx;
+    gcp<double> ecoef = (gcp<double>)L.ecoef;
+    const double v = src ? row_dot_group(eidx, ecoef, beg, end, sub, [&](int g) { return src[g]; })
+                         : row_dot_group(eidx, ecoef, beg, end, sub, [&](int g) { return (double)field[gidx[g]]; });
+    if (!live || sub != 0) return;
+    field[p] = (T)v;
+}
+
+// Row blocks: a chunk item of up to kChunk rows is served by kRowLanes
+// workgroups of kBlock / kRowLanes row groups of kRowLanes lanes.
+constexpr int kRowsPerBlock = kBlock / kRowLanes;
+static_assert(kRowsPerBlock * kRowLanes == kChunk, "a chunk spans kRowLanes row blocks");
+
 // Coarsest level: x = A^{-1} b over INSIDE then GHOST unknowns, in FP64, by
 // the threads of one workgroup (b staged in LDS).
 template <typename T>
@@ -437,11 +507,13 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__
         ghost_apply<T>(L, e, live);
         return;
     }
-    const Item it = bch[lb - ngch];
+    const int rb = lb - ngch;
+    const Item it = bch[rb / kRowLanes];
     const Desc &L = descs[it.x];
     const bool live = st[L.slot].active != 0;
-    if ((int)threadIdx.x >= it.z) return;
-    ext_gather<T>(L, ((gcp<int>)L.bneed)[it.y + threadIdx.x], L.gnew, live);
+    const int row = (rb % kRowLanes) * kRowsPerBlock + (int)threadIdx.x / kRowLanes;
+    if (row >= it.z) return;  // whole lane groups leave together
+    ext_gather_group<T>(L, ((gcp<int>)L.bneed)[it.y + row], L.gnew, threadIdx.x % kRowLanes, live);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -550,8 +622,14 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ext_gather(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                        int via_need, const SlotState *__restrict__ st) {
-    CHUNK_ITEM
-    ext_gather<T>(L, via_need ? ((gcp<int>)L.bneed)[e] : e, nullptr, live);
+    const int rb = xcd_block();
+    const Item it = items[rb / kRowLanes];
+    const Desc &L = descs[it.x];
+    const bool live = st[L.slot].active != 0;
+    const int row = (rb % kRowLanes) * kRowsPerBlock + (int)threadIdx.x / kRowLanes;
+    if (row >= it.z) return;
+    const int e = it.y + row;
+    ext_gather_group<T>(L, via_need ? ((gcp<int>)L.bneed)[e] : e, nullptr, threadIdx.x % kRowLanes, live);
 }
 
 // Restriction: coarse INSIDE rows by segment blocks, then coarse GHOST rows by
@@ -566,11 +644,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ de
         seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live, red != 0);
         return;
     }
-    const Item it = gch[lb - nseg_blocks];
+    const int rb = lb - nseg_blocks;
+    const Item it = gch[rb / kRowLanes];
     const Desc &C = descs[it.x];
     const bool live = st[C.slot].active != 0;
-    if ((int)threadIdx.x >= it.z) return;
-    restrict_ghost<T>(C, descs[it.x - 1], it.y + threadIdx.x, live);
+    const int row = (rb % kRowLanes) * kRowsPerBlock + (int)threadIdx.x / kRowLanes;
+    if (row >= it.z) return;
+    restrict_ghost_group<T>(C, descs[it.x - 1], it.y + row, threadIdx.x % kRowLanes, live);
 }
 
 template <int D, typename T>
@@ -815,11 +895,14 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
                             : restrict_inside_at<D>(F.r, F.cls, F.N, F.sy, F.sz, 2 * i, 2 * j, 2 * k, mode));
         C.u[p] = (T)0;
     }
-    for (int g = threadIdx.x; g < C.ng; g += kCoarseThreads) {
+    // coarse ghost rows by lane groups (the bound is a multiple of the group size)
+    for (int t = threadIdx.x; t < C.ng * kRowLanes; t += kCoarseThreads) {
+        const int g = t / kRowLanes, sub = t % kRowLanes;
         const int beg = C.rptr[g], end = C.rptr[g + 1];
         const double acc =
-            F.rg ? row_dot(C.ridx, C.rcoef, beg, end, [&](int q) { return (double)((gcp<T>)F.rg)[q]; })
-                 : row_dot(C.ridx, C.rcoef, beg, end, [&](int q) { return (double)F.r[q]; });
+            F.rg ? row_dot_group(C.ridx, C.rcoef, beg, end, sub, [&](int q) { return (double)((gcp<T>)F.rg)[q]; })
+                 : row_dot_group(C.ridx, C.rcoef, beg, end, sub, [&](int q) { return (double)F.r[q]; });
+        if (sub != 0) continue;
         const int p = C.gidx[g];
         C.rhs[p] = (T)acc;
         C.u[p] = (T)0;
@@ -829,10 +912,11 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
 
 template <typename T>
 __device__ void lds_extend(const LdsView<T> &L) {
-    for (int t = threadIdx.x; t < L.nbn; t += kCoarseThreads) {
-        const int b = L.bneed[t];
-        const double v = row_dot(L.eidx, L.ecoef, L.eptr[b], L.eptr[b + 1], [&](int g) { return (double)L.u[L.gidx[g]]; });
-        L.u[L.bidx[b]] = (T)v;
+    for (int t = threadIdx.x; t < L.nbn * kRowLanes; t += kCoarseThreads) {  // by lane groups
+        const int b = L.bneed[t / kRowLanes];
+        const double v = row_dot_group(L.eidx, L.ecoef, L.eptr[b], L.eptr[b + 1], t % kRowLanes,
+                                       [&](int g) { return (double)L.u[L.gidx[g]]; });
+        if (t % kRowLanes == 0) L.u[L.bidx[b]] = (T)v;
     }
     __syncthreads();
 }
@@ -1051,7 +1135,7 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
                         hipStream_t s, const Item *bch, int nbch) {
     if (ngch <= 0 && nbch <= 0) return;
-    dim3 g(ngch), ga(ngch + nbch), b(kBlock);
+    dim3 g(ngch), ga(ngch + nbch * kRowLanes), b(kBlock);
     if (fp32) {
         if (ngch > 0) DISPATCH_D(d, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
         hipLaunchKernelGGL((k_ghost_apply<float>), ga, b, 0, s, descs, gch, ngch, bch, st);
@@ -1100,16 +1184,17 @@ void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, i
                        hipStream_t s) {
     if (nbch <= 0) return;
     if (fp32)
-        hipLaunchKernelGGL((k_ext_gather<float>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, via_need, st);
+        hipLaunchKernelGGL((k_ext_gather<float>), dim3(nbch * kRowLanes), dim3(kBlock), 0, s, descs, bch, via_need, st);
     else
-        hipLaunchKernelGGL((k_ext_gather<double>), dim3(nbch), dim3(kBlock), 0, s, descs, bch, via_need, st);
+        hipLaunchKernelGGL((k_ext_gather<double>), dim3(nbch * kRowLanes), dim3(kBlock), 0, s, descs, bch, via_need,
+                           st);
 }
 
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
                      const SlotState *st, hipStream_t s, int red) {
     const int sb = blocks_for_segs(nseg);
     if (sb + ncgch <= 0) return;
-    dim3 g(sb + ncgch), b(kBlock);
+    dim3 g(sb + ncgch * kRowLanes), b(kBlock);
     if (fp32)
         DISPATCH_D(d, k_restrict, float, g, b, 0, s, descs, csegs, nseg, cgch, sb, st, red);
     else
