@@ -98,11 +98,17 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
     gcp<uint8_t> cls = (gcp<uint8_t>)L.cls;
     gp<Tr> __restrict__ r = (gp<Tr>)L.r;
     const long long nn = L.nn;
+    // both nodes of the lane are loaded and computed before either store,
+    // so that their loads are in flight together
+    double rv[2];
+    int cc[2];
+    long long pp[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
         const long long p = s.p0 + (q < s.len ? q : 0);
-        const int c = cls[p];
+        cc[h] = cls[p];
+        pp[h] = p;
         const double up = (double)u[p], fp = (double)f[p];
         const double xm = (double)u[clampi(p - 1, nn)], xp = (double)u[clampi(p + 1, nn)];
         double ym = 0, yp = 0, zm = 0, zp = 0;
@@ -118,12 +124,18 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
         if (D >= 2) sum += yp + ym;
         if (D >= 3) sum += zp + zm;
         const double lap = (2.0 * D * up - sum) / L.h2;
-        const double rv = fp - lap;
-        pin(rv);
-        pin(c);
-        if (q < s.len && c == C_INSIDE && live) {
-            r[p] = (Tr)rv;
-            r2 += rv * rv;
+        rv[h] = fp - lap;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(rv[h]);
+        pin(cc[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        if (lane + 64 * h < s.len && cc[h] == C_INSIDE && live) {
+            r[pp[h]] = (Tr)rv[h];
+            r2 += rv[h] * rv[h];
         }
     }
     return r2;
@@ -192,30 +204,25 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
 }
 
 // Restriction (fine level F, coarse level C; eq. coarseFW, Sec. 3.2 FW,
-// Sec. 3.3) to a coarse INSIDE node; also zeroes the coarse unknown (initial
-// guess of the coarse correction).  Coarse GHOST nodes are done by
-// restrict_ghost.
+// Sec. 3.3) to coarse node pc: its right-hand side fv, its class cc, and the
+// initial guess uv of the coarse correction, zero (seg_restrict stores them
+// at INSIDE nodes).  Coarse GHOST nodes are done by restrict_ghost.
 // With red, the node also takes the first red half-sweep of the coarse
 // pre-smoothing: from the zero initial guess every neighbour of an INSIDE
 // node is zero, so the update of a red node (i+j+k even) is h^2 f / (2d),
 // computed as the sweep computes it (a zero neighbour sum added).
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
-                                              bool ok, bool red) {
+                                              bool red, T &fv, T &uv, int &cc) {
     const double out = restrict_inside_at<D>((gcp<T>)F.r, (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
                                              C.restrict_mode);
-    const int cc = ((gcp<uint8_t>)C.cls)[pc];
-    pin(out);
-    pin(cc);
-    if (!ok || cc != C_INSIDE) return;
-    const T fv = (T)out;
-    T uv = (T)0;
+    cc = ((gcp<uint8_t>)C.cls)[pc];
+    fv = (T)out;
+    uv = (T)0;
     if (red && (((X0 + X1 + X2) >> 1) & 1) == 0) {
         const T sum = (T)0;
         uv = ((T)C.h2 * fv + sum) / (T)(2 * D);
     }
-    ((gp<T>)C.u)[pc] = uv;
-    ((gp<T>)C.rhs)[pc] = fv;
 }
 
 // Sparse row sums.  The sum over j in [beg, end) of coef[j] * value(idx[j])
@@ -312,11 +319,27 @@ template <int D, typename T>
 __device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const Item &it, int lane, bool live,
                                              bool red) {
     const Seg s = seg_of(it);
+    T fv[2], uv[2];
+    int cc[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {  // both nodes computed before either store
+        const int q = lane + 64 * h;
+        const int qq = q < s.len ? q : 0;
+        restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, red, fv[h], uv[h], cc[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(fv[h]);
+        pin(uv[h]);
+        pin(cc[h]);
+    }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        const int qq = q < s.len ? q : 0;
-        restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, live && q < s.len, red);
+        if (!live || q >= s.len || cc[h] != C_INSIDE) continue;
+        const long long pc = s.p0 + q;
+        ((gp<T>)C.u)[pc] = uv[h];
+        ((gp<T>)C.rhs)[pc] = fv[h];
     }
 }
 
@@ -358,29 +381,38 @@ __device__ __forceinline__ double prolong_at(PE ec, long long csy, long long csz
     return e;
 }
 
-// Prolongation and correction at fine INSIDE / GHOST node p: u += P e
-// (Sec. 3.3: the coarse error was extended into its band first).
+// Prolongation and correction at fine node p: v = u + P e and the class fc
+// (seg_prolong stores v at INSIDE and GHOST nodes; Sec. 3.3: the coarse
+// error was extended into its band first).
 template <int D, typename T>
-__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2,
-                                             bool ok) {
+__device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2, T &v,
+                                             int &fc) {
     const double e = prolong_at<D>((gcp<T>)C.u, C.sy, C.sz, I0, I1, I2);
-    gp<T> u = (gp<T>)F.u;
-    const int fc = ((gcp<uint8_t>)F.cls)[p];
-    const T v = (T)((double)u[p] + e);
-    pin(v);
-    pin(fc);
-    if (!ok || (fc != C_INSIDE && fc != C_GHOST)) return;
-    u[p] = v;
+    fc = ((gcp<uint8_t>)F.cls)[p];
+    v = (T)((double)((gcp<T>)F.u)[p] + e);
 }
 
 template <int D, typename T>
 __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
+    T v[2];
+    int fc[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {  // both nodes computed before either store
+        const int q = lane + 64 * h;
+        const int qq = q < s.len ? q : 0;
+        prolong_node<D, T>(F, C, s.p0 + qq, s.x0 + qq, s.yj, s.zk, v[h], fc[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(v[h]);
+        pin(fc[h]);
+    }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        const int qq = q < s.len ? q : 0;
-        prolong_node<D, T>(F, C, s.p0 + qq, s.x0 + qq, s.yj, s.zk, live && q < s.len);
+        if (!live || q >= s.len || (fc[h] != C_INSIDE && fc[h] != C_GHOST)) continue;
+        ((gp<T>)F.u)[s.p0 + q] = v[h];
     }
 }
 
@@ -678,17 +710,26 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(const Desc *__restrict__ d
     const Seg s = seg_of(it);
     gp<float> ev = (gp<float>)eptr[it.x];
     gp<double> u = (gp<double>)L.u;
+    double v[2];
+    int c[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {  // both nodes loaded before either store
+        const int q = lane + 64 * h;
+        const long long p = s.p0 + (q < s.len ? q : 0);
+        c[h] = ((gcp<uint8_t>)L.cls)[p];
+        v[h] = u[p] + (double)ev[p];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(v[h]);
+        pin(c[h]);
+    }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int q = lane + 64 * h;
-        const long long p = s.p0 + (q < s.len ? q : 0);
-        const int c = ((gcp<uint8_t>)L.cls)[p];
-        const double v = u[p] + (double)ev[p];
-        pin(v);
-        pin(c);
-        if (q >= s.len || !live || (c != C_INSIDE && c != C_GHOST)) continue;
-        u[p] = v;
-        ev[p] = 0.0f;
+        if (q >= s.len || !live || (c[h] != C_INSIDE && c[h] != C_GHOST)) continue;
+        u[s.p0 + q] = v[h];
+        ev[s.p0 + q] = 0.0f;
     }
 }
 
