@@ -160,6 +160,8 @@ struct bcmg_batch {
     CoarseProg *d_progs = nullptr;
     int nprog = 0;
     LdsProg *d_lprogs = nullptr;   // the same programs with their levels staged in LDS
+    uint32_t *d_limage = nullptr;  // their images (the LDS part fixed during a solve)
+    size_t limage_cap = 0;         //   capacity in words
     size_t lds_bytes = 0;          // dynamic LDS per workgroup of k_coarse_lds (0: LDS path off)
     size_t lds_budget = 0;
     bool dirty = true;
@@ -1046,6 +1048,7 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
     hipFree(b->d_coarse);
     hipFree(b->d_progs);
     hipFree(b->d_lprogs);
+    hipFree(b->d_limage);
     hipFree(b->d_partials);
     if (b->join) hipEventDestroy(b->join);
     if (b->stream) hipStreamDestroy(b->stream);
@@ -1072,28 +1075,36 @@ static size_t lds_plan(const bcmg_problem *P, int top, LdsProg *lp) {
         off += (bytes + 15) & ~size_t(15);
         return (int)o;
     };
+    LdsLevel q[kMaxLevels];
+    memset(q, 0, sizeof q);
+    // the arrays fixed during a solve first (the image), then the others
     for (int a2 = 0; a2 <= top; a2++) {
         const LevelH &V = P->lev[P->L - 1 - a2];
-        LdsLevel q;
-        memset(&q, 0, sizeof q);
-        q.nn = (int)V.nn;
-        q.ng = (int)V.ng;
-        q.nb = (int)V.nb;
-        q.ni = (int)V.ni;
-        q.nred = V.nred;
-        q.cls = take(V.nn);
-        q.u = take(V.nn * esz);
-        q.rhs = take(V.nn * esz);
-        q.r = a2 < top ? take(V.nn * esz) : -1;
-        q.gidx = take(4 * V.ng);
-        q.gcode = take(4 * V.ng);
-        q.gtau = take(24 * V.ng);
-        q.gdtau = take(8 * V.ng);
-        q.gnew = take(8 * V.ng);
-        q.ilist = take(4 * V.ni);
-        q.nbn = (int)V.nbn;
-        q.bneed = take(4 * V.nbn);
-        if (lp) lp->lev[a2] = q;
+        q[a2].nn = (int)V.nn;
+        q[a2].ng = (int)V.ng;
+        q[a2].nb = (int)V.nb;
+        q[a2].ni = (int)V.ni;
+        q[a2].nred = V.nred;
+        q[a2].nbn = (int)V.nbn;
+        q[a2].cls = take(V.nn);
+        q[a2].gidx = take(4 * V.ng);
+        q[a2].gcode = take(4 * V.ng);
+        q[a2].gtau = take(24 * V.ng);
+        q[a2].gdtau = take(8 * V.ng);
+        q[a2].ilist = take(4 * V.ni);
+        q[a2].bneed = take(4 * V.nbn);
+    }
+    const size_t static_bytes = off;
+    for (int a2 = 0; a2 <= top; a2++) {
+        const LevelH &V = P->lev[P->L - 1 - a2];
+        q[a2].u = take(V.nn * esz);
+        q[a2].rhs = take(V.nn * esz);
+        q[a2].r = a2 < top ? take(V.nn * esz) : -1;
+        q[a2].gnew = take(8 * V.ng);
+    }
+    if (lp) {
+        for (int a2 = 0; a2 <= top; a2++) lp->lev[a2] = q[a2];
+        lp->static_words = (int)(static_bytes / 4);
     }
     return off;
 }
@@ -1272,6 +1283,8 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         for (int a2 = 0; a2 <= cp.top; a2++) lp.lev[a2].desc = cp.lev[a2].desc;
         lprogs.push_back(lp);
     }
+    size_t image_words = 0;
+    for (const LdsProg &lp : lprogs) image_words += (size_t)lp.static_words;
     b->lds_bytes = !lprogs.empty() && lds_max <= b->lds_budget ? std::max<size_t>(lds_max, 16) : 0;
     // upload
     hipStream_t st = b->stream;
@@ -1291,6 +1304,18 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipMalloc((void **)&b->d_progs, sizeof(CoarseProg) * (progs.size() + 1)));
     hipFree(b->d_lprogs);
     HIPCHK(hipMalloc((void **)&b->d_lprogs, sizeof(LdsProg) * (lprogs.size() + 1)));
+    if (image_words + 1 > b->limage_cap) {
+        hipFree(b->d_limage);
+        b->limage_cap = std::max(image_words + 1, 2 * b->limage_cap);
+        HIPCHK(hipMalloc((void **)&b->d_limage, sizeof(uint32_t) * b->limage_cap));
+    }
+    {
+        size_t w = 0;
+        for (LdsProg &lp : lprogs) {
+            lp.image = b->d_limage + w;
+            w += (size_t)lp.static_words;
+        }
+    }
     const size_t np = (size_t)nfseg + nfgch + 1;
     if (np > b->partials_cap) {
         hipFree(b->d_partials);
@@ -1309,8 +1334,11 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), sizeof(NormRange) * b->cap, hipMemcpyHostToDevice, cs));
     if (!progs.empty())
         HIPCHK(hipMemcpyAsync(b->d_progs, progs.data(), sizeof(CoarseProg) * progs.size(), hipMemcpyHostToDevice, cs));
-    if (!lprogs.empty())
+    if (!lprogs.empty()) {
         HIPCHK(hipMemcpyAsync(b->d_lprogs, lprogs.data(), sizeof(LdsProg) * lprogs.size(), hipMemcpyHostToDevice, cs));
+        launch_lds_images(b->d_desc, b->d_lprogs, (int)lprogs.size(), cs);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(cs));
     b->lv.assign(A, Lists());
     for (int a = 0; a < A; a++) {

@@ -115,9 +115,15 @@ struct LdsLevel {
 };
 
 // The aligned levels 0..top of one problem cycled in LDS by k_coarse_lds.
+// The arrays that do not change during a solve (classes, ghost records,
+// INSIDE lists, needed band entries) of all its levels come first in the
+// LDS block, and image holds a copy of that part (static_words 4-byte
+// words), built when the batch's programs are built.
 struct alignas(16) LdsProg {
     int slot, top, ext_top;
     int finest;  // 1 if top is the problem's finest level (u is the caller's: only unknowns are written back)
+    int static_words, pad;
+    const uint32_t *image;
     LdsLevel lev[kMaxLevels];
 };
 

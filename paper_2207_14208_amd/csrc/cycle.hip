@@ -606,18 +606,33 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
     if (mode == 0 && st[s].active != 2) return;
     const NormRange R = ranges[s];
     const int nA = R.seg_end - R.seg_beg, nB = R.gch_end - R.gch_beg, n = nA + nB;
+    // a thread's entries are loaded eight at a time and added in order; the
+    // tree pairs t with t + w, through LDS while w spans wavefronts and by
+    // shuffles within the first wavefront after that (the same pairs)
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += kNormThreads)
-        acc += i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
+    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kNormThreads) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int i = min(i0 + k * kNormThreads, n - 1);
+            v[k] = i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (i0 + k * kNormThreads < n) acc += v[k];
+    }
     __shared__ double red[kNormThreads];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+    for (int w = kNormThreads / 2; w >= 64; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x >= 64) return;
+    double t = red[threadIdx.x];
+    for (int w = 32; w > 0; w >>= 1) t += __shfl_down(t, w);
     if (threadIdx.x != 0) return;
-    const double tot = red[0];
+    const double tot = t;
     if (out) out[s] = tot;
     SlotState &S = st[s];
     if (mode == 0) {
@@ -973,6 +988,45 @@ __device__ void lds_prolong(const LdsView<T> &F, const LdsView<T> &C) {
     __syncthreads();
 }
 
+// Copy n 4-byte words from HBM into LDS with every thread of the workgroup,
+// sixteen loads in flight per thread and round.
+__device__ __forceinline__ void lds_copy_words(lp<uint32_t> dst, gcp<uint32_t> src, int n) {
+    constexpr int U = 16;
+    for (int w0 = threadIdx.x; w0 < n; w0 += U * kCoarseThreads) {
+        uint32_t v[U];
+#pragma unroll
+        for (int k = 0; k < U; k++) v[k] = src[min(w0 + k * kCoarseThreads, n - 1)];
+#pragma unroll
+        for (int k = 0; k < U; k++)
+            if (w0 + k * kCoarseThreads < n) dst[w0 + k * kCoarseThreads] = v[k];
+    }
+}
+
+// A program's image: the arrays of its levels fixed during a solve, at their
+// LDS offsets (one workgroup per program; run when the programs are built).
+__global__ __launch_bounds__(kBlock) void k_lds_images(const Desc *__restrict__ descs,
+                                                        const LdsProg *__restrict__ progs) {
+    const LdsProg &P = progs[blockIdx.x];
+    gp<uint32_t> img = (gp<uint32_t>)P.image;
+    for (int a = 0; a <= P.top; a++) {
+        const LdsLevel &Q = P.lev[a];
+        const Desc &G = descs[Q.desc];
+        // class arrays are padded allocations, the others whole words
+        auto put = [&](const void *src, int off, long long bytes) {
+            const int n = (int)((bytes + 3) / 4);
+            gcp<uint32_t> sw = (gcp<uint32_t>)src;
+            for (int w = threadIdx.x; w < n; w += kBlock) img[off / 4 + w] = sw[w];
+        };
+        put(G.cls, Q.cls, Q.nn);
+        put(G.gidx, Q.gidx, 4LL * Q.ng);
+        put(G.gcode, Q.gcode, 4LL * Q.ng);
+        put(G.gtau, Q.gtau, 24LL * Q.ng);
+        put(G.gdtau, Q.gdtau, 8LL * Q.ng);
+        put(G.ilist, Q.ilist, 4LL * Q.ni);
+        put(G.bneed, Q.bneed, 4LL * Q.nbn);
+    }
+}
+
 template <int D, typename T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__restrict__ descs,
                                                                const LdsProg *__restrict__ progs,
@@ -982,17 +1036,13 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
     const LdsProg &P = progs[blockIdx.x];
     if (!st[P.slot].active) return;
     __shared__ LdsView<T> V[kMaxLevels];
-    // staging: one flat list of copies (4-byte words; every staged array is
-    // a whole number of words, class arrays are padded allocations).  Thread
-    // a sets up level a: its view and its kStage copy entries (word counts
-    // at first, turned into offsets by the scan below; an empty entry is
-    // never the segment of a word).  The top level's u is staged only when
-    // it is the caller's array: else its unknowns are zero after the
-    // restriction, and its other nodes are not read before the extension
-    // writes them, so it is zero-filled like the levels below.
-    constexpr int kStage = 9;
-    __shared__ const uint32_t *csrc[kMaxLevels * kStage];
-    __shared__ int cdst[kMaxLevels * kStage], cbeg[kMaxLevels * kStage + 1];
+    // Thread a sets up the view of level a.  The LDS block starts with the
+    // arrays fixed during a solve, copied from the program's image; the top
+    // level's u and rhs follow from HBM: whole when it is the caller's finest
+    // level (its box values are read), else rhs at its unknowns only (the
+    // other entries are never read) and u zero-filled (after the restriction
+    // its unknowns are zero, and its other nodes are written by the
+    // extension before they are read).
     const int top = P.top;
     const bool finest = P.finest != 0;
     if ((int)threadIdx.x <= top) {
@@ -1030,74 +1080,31 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
         W.rptr = (gcp<int>)G.rptr;
         W.ridx = (gcp<int>)G.ridx;
         W.rcoef = (gcp<double>)G.rcoef;
-        int e = a * kStage;
-        auto add = [&](const void *src, int lds_off, long long bytes) {
-            csrc[e] = (const uint32_t *)src;
-            cdst[e] = lds_off / 4;
-            cbeg[e] = (int)((bytes + 3) / 4);
-            e++;
-        };
-        add(G.cls, Q.cls, Q.nn);
-        add(G.gidx, Q.gidx, 4LL * Q.ng);
-        add(G.gcode, Q.gcode, 4LL * Q.ng);
-        add(G.gtau, Q.gtau, 24LL * Q.ng);
-        add(G.gdtau, Q.gdtau, 8LL * Q.ng);
-        add(G.ilist, Q.ilist, 4LL * Q.ni);
-        add(G.bneed, Q.bneed, 4LL * Q.nbn);
-        add(G.rhs, Q.rhs, a == top ? (long long)sizeof(T) * Q.nn : 0);
-        add(G.u, Q.u, a == top && finest ? (long long)sizeof(T) * Q.nn : 0);
+    }
+    lds_copy_words((lp<uint32_t>)lds, (gcp<uint32_t>)P.image, P.static_words);
+    const Desc &GT = descs[P.lev[top].desc];
+    if (finest) {
+        const LdsLevel &Q = P.lev[top];
+        lds_copy_words((lp<uint32_t>)(lds + Q.u), (gcp<uint32_t>)GT.u, (int)((sizeof(T) * Q.nn) / 4));
+        lds_copy_words((lp<uint32_t>)(lds + Q.rhs), (gcp<uint32_t>)GT.rhs, (int)((sizeof(T) * Q.nn) / 4));
     }
     __syncthreads();
-    const int n = (top + 1) * kStage;
-    if (threadIdx.x == 0) {
-        int w = 0;
-        for (int e = 0; e < n; e++) {
-            const int c = cbeg[e];
-            cbeg[e] = w;
-            w += c;
-        }
-        cbeg[n] = w;
-    }
-    __syncthreads();
-    {
-        // U words per thread per round: the segment searches first, then
-        // every load, then the LDS stores, so that the loads of a round are
-        // in flight together
-        const int total = cbeg[n];
-        lp<uint32_t> words = (lp<uint32_t>)lds;
-        constexpr int U = 16;
-        for (int w0 = threadIdx.x; w0 < total; w0 += U * kCoarseThreads) {
-            // segment of each word: the last entry starting at or before it,
-            // by a fixed-step search run for the U words side by side
-            int w[U], lo[U];
+    if (!finest) {
+        const LdsView<T> &W = V[top];
+        gcp<T> rhs = (gcp<T>)GT.rhs;
+        for (int t0 = threadIdx.x; t0 < W.ni + W.ng; t0 += 4 * kCoarseThreads) {
+            int pk[4];
+            T v[4];
 #pragma unroll
-            for (int k = 0; k < U; k++) {
-                w[k] = min(w0 + k * kCoarseThreads, total - 1);
-                lo[k] = 0;
+            for (int k = 0; k < 4; k++) {
+                const int t = min(t0 + k * kCoarseThreads, W.ni + W.ng - 1);
+                pk[k] = t < W.ni ? W.ilist[t] : W.gidx[t - W.ni];
             }
-            // branch-free steps: each reads cbeg for all U words, then waits once
-            for (int step = 1 << (31 - __clz(n)); step > 0; step >>= 1) {
-                int cb[U];
 #pragma unroll
-                for (int k = 0; k < U; k++) cb[k] = cbeg[min(lo[k] + step, n)];
+            for (int k = 0; k < 4; k++) v[k] = rhs[pk[k]];
 #pragma unroll
-                for (int k = 0; k < U; k++) pin(cb[k]);
-#pragma unroll
-                for (int k = 0; k < U; k++) lo[k] = lo[k] + step < n && cb[k] <= w[k] ? lo[k] + step : lo[k];
-            }
-            const uint32_t *sp[U];
-            int dst[U];
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                sp[k] = csrc[lo[k]] + (w[k] - cbeg[lo[k]]);
-                dst[k] = cdst[lo[k]] + (w[k] - cbeg[lo[k]]);
-            }
-            uint32_t v[U];
-#pragma unroll
-            for (int k = 0; k < U; k++) v[k] = *(gcp<uint32_t>)sp[k];
-#pragma unroll
-            for (int k = 0; k < U; k++)
-                if (w0 + k * kCoarseThreads < total) words[dst[k]] = v[k];
+            for (int k = 0; k < 4; k++)
+                if (t0 + k * kCoarseThreads < W.ni + W.ng) W.rhs[pk[k]] = v[k];
         }
     }
     for (int a = 0; a <= top; a++) {
@@ -1268,6 +1275,11 @@ void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, 
         DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2);
     else
         DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2);
+}
+
+void launch_lds_images(const Desc *descs, const LdsProg *progs, int nprog, hipStream_t s) {
+    if (nprog <= 0) return;
+    hipLaunchKernelGGL(k_lds_images, dim3(nprog), dim3(kBlock), 0, s, descs, progs);
 }
 
 void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,

@@ -35,6 +35,8 @@ void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, 
 // the same on the levels staged in LDS (lds_bytes of dynamic LDS per workgroup)
 void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,
                        const SlotState *st, int nu1, int nu2, hipStream_t s);
+// fill the programs' images (their levels' arrays fixed during a solve, at their LDS offsets)
+void launch_lds_images(const Desc *descs, const LdsProg *progs, int nprog, hipStream_t s);
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
                       hipStream_t s);
 
