@@ -509,6 +509,23 @@ __device__ void coarse_solve_block(const Desc &L, double *b) {
 }
 
 // ----------------------------------------------------------------- kernels
+// The two-list mapping of xcd_block with each XCD's blocks of the second
+// list dispatched before its blocks of the first: the second list holds the
+// blocks with the longer dependent-load chains (ghost rows, sparse rows),
+// which should not start last.
+__device__ __forceinline__ int xcd_block_second_first(int nfirst) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b % kXcds, i = b / kXcds;
+    const int qa = nfirst / kXcds, ra = nfirst % kXcds;
+    const int qt = nb / kXcds, rt = nb % kXcds;
+    const int na = qa + (x < ra ? 1 : 0);
+    const int abeg = x * qa + min(x, ra);
+    const int tbeg = x * qt + min(x, rt);
+    const int nsec = qt + (x < rt ? 1 : 0) - na;
+    if (i < nsec) return nfirst + (tbeg - abeg) + i;
+    return abeg + (i - nsec);
+}
+
 #define CHUNK_ITEM CHUNK_ITEM_AT(xcd_block())
 #define CHUNK_ITEM_AT(lblock)                                     \
     const Item it = items[lblock];                                \
@@ -533,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const Desc *__restrict__
                                                         const Item *__restrict__ items, int ngch,
                                                         const Item *__restrict__ bch,
                                                         const SlotState *__restrict__ st) {
-    const int lb = xcd_block(ngch);
+    const int lb = xcd_block_second_first(ngch);
     if (lb < ngch) {
         CHUNK_ITEM_AT(lb)
         ghost_apply<T>(L, e, live);
@@ -561,7 +578,7 @@ template <int D, typename Tu, typename Tr, bool NORM>
 __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st, double *__restrict__ partials) {
-    const int lb = xcd_block(nseg_blocks);
+    const int lb = xcd_block_second_first(nseg_blocks);
     if (lb < nseg_blocks) {
         SEG_ITEM_AT(lb)
         double r2 = seg_residual<D, Tu, Tr>(L, it, lane, live);
@@ -685,7 +702,7 @@ template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st, int red) {
-    const int lb = xcd_block(nseg_blocks);
+    const int lb = xcd_block_second_first(nseg_blocks);
     if (lb < nseg_blocks) {
         SEG_ITEM_AT(lb)
         seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live, red != 0);
