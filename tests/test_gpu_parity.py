@@ -56,7 +56,8 @@ def build_pair(name, **opt):
     Problem = _gpu()
     c = CASES[name]()
     opt = {**CASE_OPTS.get(name, {}), **opt}
-    o_opts = oracle.Options(**{k: v for k, v in opt.items() if k in ("dtau_mode", "dtau_const", "ext_iters", "restrict_mode")})
+    o_opts = oracle.Options(**{k: v for k, v in opt.items()
+                               if k in ("dtau_mode", "dtau_const", "ext_iters", "restrict_mode", "nu1", "nu2")})
     O = oracle.Problem(c.d, c.N, c.phi, o_opts)
     G = Problem(c.d, c.N, c.phi, **opt)
     return c, O, G
@@ -215,6 +216,18 @@ def test_solve_parity_fp64(name):
 def test_solve_parity_dtau_modes(mode, const):
     c, O, G, it, ho, uo, st, hg, ug = solve_pair("circle65", dtau_mode=mode, dtau_const=const)
     assert abs(st.cycles - it) <= 1 and floor_close(hg, ho)
+    assert _close(oracle_after(c, O, st.cycles), ug, 1e-12)
+
+
+@pytest.mark.parametrize("nu1,nu2", [(1, 1), (0, 2), (3, 0), (2, 2)])
+def test_solve_parity_smoothing_counts(nu1, nu2):
+    """V(nu1, nu2) on the 65^3 flower: the launched levels' first red
+    half-sweep rides on the restriction when nu1 > 0, and with nu2 = 0 the
+    band extension runs as its own launch.  Solution after the GPU's cycle
+    count against the oracle's after as many cycles."""
+    c, O, G, it, ho, uo, st, hg, ug = solve_pair("flower3d_65", nu1=nu1, nu2=nu2)
+    assert st.status == 0 and abs(st.cycles - it) <= 1
+    assert floor_close(hg, ho)
     assert _close(oracle_after(c, O, st.cycles), ug, 1e-12)
 
 
