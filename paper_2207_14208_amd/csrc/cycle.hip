@@ -302,6 +302,24 @@ __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int
     ((gp<T>)C.u)[pc] = (T)0;
 }
 
+// The restriction of coarse node q of a segment (one node per lane: its 3^d
+// box of fine residuals and classes is 54 loads, all in flight at once).
+template <int D, typename T>
+__device__ __forceinline__ void seg_restrict_one(const Desc &C, const Desc &F, const Item &it, int q, bool live,
+                                                 bool red) {
+    const Seg s = seg_of(it);
+    const int qq = q < s.len ? q : 0;
+    T fv, uv;
+    int cc;
+    restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, red, fv, uv, cc);
+    pin(fv);
+    pin(uv);
+    pin(cc);
+    if (!live || q >= s.len || cc != C_INSIDE) return;
+    ((gp<T>)C.u)[s.p0 + q] = uv;
+    ((gp<T>)C.rhs)[s.p0 + q] = fv;
+}
+
 // restrict_ghost by the eight lanes sub of a group (one coarse ghost each group)
 template <typename T>
 __device__ __forceinline__ void restrict_ghost_group(const Desc &C, const Desc &F, int g, int sub, bool live) {
@@ -704,8 +722,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const Desc *__restrict__ de
                                                      const SlotState *__restrict__ st, int red) {
     const int lb = xcd_block_second_first(nseg_blocks);
     if (lb < nseg_blocks) {
-        SEG_ITEM_AT(lb)
-        seg_restrict<D, T>(L, descs[it.x - 1], it, lane, live, red != 0);
+        // two wavefronts per segment, one coarse node per lane
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int hidx = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + wave);
+        if (hidx >= 2 * nseg) return;
+        const Item it = items[hidx >> 1];
+        const Desc L = descs[it.x];
+        const bool live = st[L.slot].active != 0;
+        seg_restrict_one<D, T>(L, descs[it.x - 1], it, (hidx & 1) * 64 + lane, live, red != 0);
         return;
     }
     const int rb = lb - nseg_blocks;
@@ -1257,7 +1281,7 @@ void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, i
 
 void launch_restrict(int d, int fp32, const Desc *descs, const Item *csegs, int nseg, const Item *cgch, int ncgch,
                      const SlotState *st, hipStream_t s, int red) {
-    const int sb = blocks_for_segs(nseg);
+    const int sb = blocks_for_segs(2 * nseg);  // two wavefronts per coarse segment
     if (sb + ncgch <= 0) return;
     dim3 g(sb + ncgch * kRowLanes), b(kBlock);
     if (fp32)
