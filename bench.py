@@ -76,9 +76,11 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles in the CPU sample")
-    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served"], default="flower257",
+    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served", "rho_sweep"],
+                    default="flower257",
                     help="flower257: the headline single solve; mixed513: 513^3 FP64 against mixed precision; "
-                         "batched: 512 2D star problems; served: the continuous-batching request loop")
+                         "batched: 512 2D star problems; served: the continuous-batching request loop; "
+                         "rho_sweep: convergence factors of the paper's 2D tests, batched")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -97,6 +99,8 @@ def main():
         return bench_batched(args)
     if args.workload == "mixed513":
         return bench_mixed(args)
+    if args.workload == "rho_sweep":
+        return bench_rho_sweep(args)
     if args.workload == "served":
         return bench_served(args)
     import numpy as np
@@ -332,6 +336,58 @@ def bench_mixed(args):
     out["fp64"] = res["fp64"]
     out["mixed"] = res["mixed"]
     out["speedup_mixed_vs_fp64"] = res["mixed"]["unknowns_per_s"] / res["fp64"]["unknowns_per_s"]
+    print(json.dumps(out))
+
+
+def bench_rho_sweep(args):
+    """Convergence factors (homogeneous problem, U(-1,1) start, mean of
+    rho^(11..15)) of the paper's 2D tests, all in one batch: circle and
+    flower for N = 64..1024 under the three Delta-tau modes, and the
+    rectangle for theta = 0.1..0.9 against a constant Delta-tau scan.  The
+    oracle runs the circle N = 256 spec (same protocol and cycle) as the CPU
+    sample."""
+    import torch
+
+    from paper_2207_14208_amd import experiments as X
+    specs = [X.Spec(dom, n, dt) for dom in ("circle", "flower") for n in (64, 128, 256, 512, 1024)
+             for dt in ("opt_exp", "opt_poly", "const:1.75")]
+    specs += [X.Spec("rectangle", 128, f"const:{dt}", theta=th) for th in (0.1, 0.3, 0.5, 0.7, 0.9)
+              for dt in (0.5, 1.0, 1.5, 1.75, 2.0, 2.5)]
+    X.rho_sweep(specs[:3])  # load the kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = X.rho_sweep(specs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    table = {}
+    for r in res:
+        s = r["spec"]
+        key = f"{s['domain']}" + (f" theta={s['theta']}" if s["domain"] == "rectangle" else f" N={s['N']}")
+        table.setdefault(key, {})[s["dtau"]] = round(r["rho"], 4)
+    out = {"metric": "convergence-factor problems per second (16 V-cycles each, batched)", "value": len(specs) / el,
+           "unit": "problems/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": el * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (paper's 2D domains, homogeneous problem, seeded U(-1,1) start)",
+           "config": {"workload": "rho sweep: circle and flower N=64..1024 x {opt_exp, opt_poly, const 1.75}, "
+                                  "rectangle N=128 theta 0.1..0.9 x const dtau 0.5..2.5; V(2,1) red-black",
+                      "problems": len(specs)},
+           "rho": table}
+    if not args.no_cpu_baseline:
+        import numpy as np
+
+        import oracle
+        from paper_2207_14208_amd import workloads as W
+        oracle.build()
+        spec = X.Spec("circle", 256, "opt_exp")
+        t1 = time.perf_counter()
+        O = oracle.Problem(2, 256, W.sample(2, 256, X.DOMAINS["circle"][1](256, 0.5)), oracle.Options(max_cycles=16))
+        O.set_rhs(np.zeros(O.nodes(0)), np.zeros(O.counts(0)[1]))
+        u = X.initial_guess(O.classes(0), spec.seed)
+        _, hist = O.solve(u, 0.0, 16)
+        cpu_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "problems/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle (plain C, FP64, 1 thread): the circle N=256 opt_exp spec, setup "
+                                         f"and 16 V-cycles, {cpu_s:.2f} s; rho {X.rho_from_history(hist):.4f}"}
     print(json.dumps(out))
 
 

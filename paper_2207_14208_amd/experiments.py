@@ -1,0 +1,155 @@
+"""Convergence-factor sweeps on the GPU.
+
+The protocol of Sec. 2.2 and Sec. 3.1 (set-up of the 2D and 3D tests): the
+homogeneous problem (f = g = 0, g_B = 0), an initial guess drawn uniformly
+from (-1, 1) on the unknowns, and the asymptotic factor approximated by the
+mean of rho^(m) = ||r^(m)|| / ||r^(m-1)|| over m = 11..15.  A run that
+diverges or stops before cycle 15 counts as rho = 1 (the paper cuts its
+plots there).  The solver is the GPU V(nu1, nu2) cycle with red-black
+smoothing, so the values are those of that cycle, not of the paper's GS-LEX
+two-grid runs; the oracle run with the same smoother and cycle gives the
+same factors.
+
+Every problem of a sweep with the same dimension runs in one batch
+(bcmg_batch_*): one launch per kernel serves all of them, whatever their
+grid sizes and Delta-tau settings.
+
+    python -m paper_2207_14208_amd.experiments circle --N 64 128 256 --dtau opt_exp opt_poly const:1.75
+    python -m paper_2207_14208_amd.experiments rectangle --N 128 --theta 0.1 0.5 0.9 --dtau const:1.0 const:1.75
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _native as N
+from . import workloads as W
+
+DTAU_MODES = {"opt_exp": N.DTAU_OPT_EXP, "opt_poly": N.DTAU_OPT_POLY, "const": N.DTAU_CONST}
+
+# domains of the paper's tests: dimension and phi(N, theta)
+DOMAINS = {
+    "box2d": (2, lambda n, th: W.phi_full_box),
+    "circle": (2, lambda n, th: W.phi_circle_paper()),
+    "flower": (2, lambda n, th: W.phi_flower2d()),
+    "ellipsoid": (3, lambda n, th: W.phi_ellipsoid()),
+    # the rectangle of Sec. 3.2 in [-1,1]^2: the domain is x <= x_V with
+    # x_V = 1 - theta h, so every ghost lies at the same distance theta h
+    "rectangle": (2, lambda n, th: W.phi_halfspace(1.0 - th * 2.0 / n)),
+}
+
+FIRST, LAST = 11, 15  # rho^(m) averaged over these cycles
+
+
+@dataclass(frozen=True)
+class Spec:
+    domain: str
+    N: int
+    dtau: str = "opt_exp"      # opt_exp | opt_poly | const:<value>
+    theta: float = 0.5         # rectangle only
+    seed: int = 0
+
+    @property
+    def dim(self) -> int:
+        return DOMAINS[self.domain][0]
+
+    def dtau_mode(self) -> tuple[int, float]:
+        if self.dtau.startswith("const"):
+            _, _, v = self.dtau.partition(":")
+            return N.DTAU_CONST, float(v or 1.0)
+        return DTAU_MODES[self.dtau], 1.0
+
+
+def rho_from_history(hist, first: int = FIRST, last: int = LAST) -> float:
+    """Mean of hist[m] / hist[m-1] over m = first..last, capped at 1; 1 when
+    the history is shorter or not finite."""
+    h = np.asarray(hist, dtype=np.float64)
+    if h.size <= last or not np.all(np.isfinite(h[: last + 1])) or np.any(h[first - 1: last] <= 0.0):
+        return 1.0
+    r = h[first: last + 1] / h[first - 1: last]
+    return float(min(1.0, r.mean()))
+
+
+def initial_guess(cls: np.ndarray, seed: int) -> np.ndarray:
+    """U(-1, 1) on INSIDE and GHOST nodes, 0 elsewhere (BOXDIR holds g_B = 0)."""
+    u = W.random_guess(cls.size, seed)
+    u[(cls != N.INSIDE) & (cls != N.GHOST)] = 0.0
+    return u
+
+
+def _problem(spec: Spec, cycles: int):
+    import torch
+
+    from .solver import Problem
+
+    d, phi_of = DOMAINS[spec.domain]
+    mode, const = spec.dtau_mode()
+    G = Problem(d, spec.N, W.sample(d, spec.N, phi_of(spec.N, spec.theta)), dtau_mode=mode, dtau_const=const,
+                max_cycles=cycles)
+    ng = G.level_info(0)["n_ghost"]
+    G.set_data(torch.zeros(G.nodes, dtype=torch.float64, device="cuda"),
+               torch.zeros(max(ng, 1), dtype=torch.float64, device="cuda")[:ng])
+    cls = G.classes(0).cpu().numpy()
+    u = torch.from_numpy(initial_guess(cls, spec.seed)).cuda()
+    return G, u
+
+
+def rho_sweep(specs: list[Spec], cycles: int = LAST + 1, batched: bool = True) -> list[dict]:
+    """rho for every spec; problems of one dimension share a batch."""
+    from .solver import Batch
+
+    out: list[dict | None] = [None] * len(specs)
+    by_dim: dict[int, list[int]] = {}
+    for i, s in enumerate(specs):
+        by_dim.setdefault(s.dim, []).append(i)
+    for dim, idx in by_dim.items():
+        groups = [idx] if batched else [[i] for i in idx]
+        for grp in groups:
+            probs = [_problem(specs[i], cycles) for i in grp]
+            B = Batch(len(grp))
+            slots = [B.add(G, u, 0.0) for G, u in probs]
+            B.run(cycles, 4)
+            for i, s, (G, u) in zip(grp, slots, probs):
+                st, hist = B.stats(s, cycles)
+                out[i] = {"spec": specs[i].__dict__, "rho": rho_from_history(hist), "cycles": st.cycles,
+                          "status": N.STATUS_NAMES.get(st.status, st.status),
+                          "n_ghost": G.level_info(0)["n_ghost"], "history": [float(x) for x in hist]}
+            B.close()
+            for G, _ in probs:
+                G.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("domain", choices=list(DOMAINS))
+    ap.add_argument("--N", type=int, nargs="+", default=[64, 128, 256])
+    ap.add_argument("--dtau", nargs="+", default=["opt_exp", "opt_poly", "const:1.75"])
+    ap.add_argument("--theta", type=float, nargs="+", default=[0.5])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--json", action="store_true", help="print one JSON object per spec")
+    a = ap.parse_args()
+    thetas = a.theta if a.domain == "rectangle" else [math.nan]
+    specs = [Spec(a.domain, n, dt, th if a.domain == "rectangle" else 0.5, a.seed)
+             for n in a.N for th in thetas for dt in a.dtau]
+    t0 = time.perf_counter()
+    res = rho_sweep(specs)
+    el = time.perf_counter() - t0
+    for r in res:
+        if a.json:
+            print(json.dumps({k: v for k, v in r.items() if k != "history"}))
+        else:
+            s = r["spec"]
+            th = f" theta={s['theta']:.2f}" if a.domain == "rectangle" else ""
+            print(f"{s['domain']} N={s['N']}{th} dtau={s['dtau']}: rho={r['rho']:.4f} ({r['status']}, "
+                  f"{r['n_ghost']} ghosts)")
+    print(f"{len(specs)} problems in {el:.2f} s")
+
+
+if __name__ == "__main__":
+    main()
