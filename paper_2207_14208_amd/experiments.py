@@ -16,6 +16,12 @@ grid sizes and Delta-tau settings.
 
     python -m paper_2207_14208_amd.experiments circle --N 64 128 256 --dtau opt_exp opt_poly const:1.75
     python -m paper_2207_14208_amd.experiments rectangle --N 128 --theta 0.1 0.5 0.9 --dtau const:1.0 const:1.75
+    python -m paper_2207_14208_amd.experiments spectrum --N 128 --theta 0.2 0.5 --dtau opt_exp const:0.7
+    python -m paper_2207_14208_amd.experiments theta-hist --N 1024 2048
+
+Diagnostics (Sec. 3.2, Sec. 3.3): the DFT of the residual along the
+rectangle's ghost column after fine-grid relaxations, and the histogram of
+the ghosts' theta~ on curved domains.
 """
 from __future__ import annotations
 
@@ -125,15 +131,84 @@ def rho_sweep(specs: list[Spec], cycles: int = LAST + 1, batched: bool = True) -
     return out
 
 
+# ------------------------------------------------------------ diagnostics
+def boundary_dft(rb) -> tuple[np.ndarray, np.ndarray, float]:
+    """DFT of the residual along a straight ghost column (Sec. 3.2): with M
+    entries, R_k = (1/M) sum_j r_j exp(-i alpha_k j), alpha_k = -pi + 2 pi k / M
+    (k, j = 1..M).  Returns the alpha_k in (0, pi), the amplitudes 2|R_k|
+    (the symmetric mode included) and the ratio of the mean amplitude over
+    the high frequencies (alpha > pi/2) to that over the low ones."""
+    rb = np.asarray(rb, dtype=np.float64)
+    m = rb.size
+    j = np.arange(1, m + 1)
+    alpha = -np.pi + np.arange(1, m + 1) * 2.0 * np.pi / m
+    R = (rb[None, :] * np.exp(-1j * alpha[:, None] * j[None, :])).sum(axis=1) / m
+    pos = alpha > 0
+    a, amp = alpha[pos], 2.0 * np.abs(R[pos])
+    lo, hi = amp[a < np.pi / 2], amp[a > np.pi / 2]
+    return a, amp, float(hi.mean() / lo.mean()) if lo.size and hi.size and lo.mean() > 0 else math.inf
+
+
+def boundary_residual_spectrum(N: int, theta: float, dtau: str = "opt_exp", relax: int = 10, seed: int = 0) -> dict:
+    """The rectangle's ghost-column residual after `relax` fine-grid
+    relaxations (interior red-black sweeps and the ghost step) of the
+    homogeneous problem from a U(-1, 1) start, and its DFT (Sec. 3.2)."""
+    import torch
+
+    G, u = _problem(Spec("rectangle", N, dtau, theta=theta, seed=seed), cycles=1)
+    rhs = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+    G.level_smooth(0, u, rhs, relax)
+    r = torch.zeros_like(rhs)
+    G.level_residual(0, u, rhs, r)
+    gi = G.ghost_info(0)
+    rb = r[gi["idx"].long()].cpu().numpy()  # the ghost list ascends in y: the column in order
+    a, amp, ratio = boundary_dft(rb)
+    out = {"N": N, "theta": theta, "dtau": dtau, "dtau_value": float(gi["dtau"][0]), "relaxations": relax,
+           "alpha": a.tolist(), "amplitude": amp.tolist(), "high_over_low": ratio}
+    G.close()
+    return out
+
+
+def theta_histogram(domain: str, N: int, bins: int = 10) -> dict:
+    """Distribution of the ghosts' normalised distance theta~ to the boundary
+    on the finest level (Sec. 3.3 remark on curved domains)."""
+    from .solver import Problem
+
+    d, phi_of = DOMAINS[domain]
+    G = Problem(d, N, W.sample(d, N, phi_of(N, 0.5)))
+    eta = G.ghost_info(0)["eta"].cpu().numpy()
+    G.close()
+    counts, edges = np.histogram(eta, bins=bins, range=(0.0, 1.0))
+    return {"domain": domain, "N": N, "n_ghost": int(eta.size), "counts": counts.tolist(), "edges": edges.tolist(),
+            "min": float(eta.min()) if eta.size else None, "max": float(eta.max()) if eta.size else None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("domain", choices=list(DOMAINS))
+    ap.add_argument("domain", choices=list(DOMAINS) + ["spectrum", "theta-hist"],
+                    help="a domain for a rho sweep; 'spectrum': the rectangle's boundary-residual DFT for each "
+                         "--theta and --dtau at the first --N; 'theta-hist': the theta~ histogram of circle and "
+                         "flower at each --N")
     ap.add_argument("--N", type=int, nargs="+", default=[64, 128, 256])
     ap.add_argument("--dtau", nargs="+", default=["opt_exp", "opt_poly", "const:1.75"])
     ap.add_argument("--theta", type=float, nargs="+", default=[0.5])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--json", action="store_true", help="print one JSON object per spec")
     a = ap.parse_args()
+    if a.domain == "spectrum":
+        for th in a.theta:
+            for dt in a.dtau:
+                r = boundary_residual_spectrum(a.N[0], th, dt, seed=a.seed)
+                print(f"rectangle N={a.N[0]} theta={th:.2f} dtau={dt} ({r['dtau_value']:.3f}): "
+                      f"high/low amplitude {r['high_over_low']:.3f}")
+        return
+    if a.domain == "theta-hist":
+        for dom in ("circle", "flower"):
+            for n in a.N:
+                r = theta_histogram(dom, n)
+                print(f"{dom} N={n}: {r['n_ghost']} ghosts, theta~ in [{r['min']:.4f}, {r['max']:.4f}], "
+                      f"deciles {r['counts']}")
+        return
     thetas = a.theta if a.domain == "rectangle" else [math.nan]
     specs = [Spec(a.domain, n, dt, th if a.domain == "rectangle" else 0.5, a.seed)
              for n in a.N for th in thetas for dt in a.dtau]

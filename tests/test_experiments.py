@@ -53,3 +53,17 @@ def test_initial_guess_only_on_unknowns():
     u = X.initial_guess(cls, 3)
     unk = (cls == N.INSIDE) | (cls == N.GHOST)
     assert np.all(u[~unk] == 0.0) and np.all(np.abs(u[unk]) < 1.0) and np.all(u[unk] != 0.0)
+
+
+def test_boundary_dft_of_a_pure_mode():
+    """A cosine on one grid frequency alpha_m has amplitude 2|R_m| = 1 there
+    and none elsewhere (the M frequencies are orthogonal over j = 1..M)."""
+    m = 127
+    alpha = -np.pi + np.arange(1, m + 1) * 2 * np.pi / m
+    for k in (70, 110):  # a low and a high positive frequency
+        a0 = alpha[k - 1]
+        a, amp, ratio = X.boundary_dft(np.cos(a0 * np.arange(1, m + 1)))
+        i = int(np.argmin(np.abs(a - a0)))
+        assert amp[i] == pytest.approx(1.0, abs=1e-12)
+        assert np.max(np.delete(amp, i)) < 1e-12
+        assert (ratio > 1.0) == (a0 > np.pi / 2)

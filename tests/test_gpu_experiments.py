@@ -73,3 +73,43 @@ def test_rectangle_and_circle_findings():
     circ = {r["spec"]["dtau"]: r["rho"] for r in X.rho_sweep(
         [X.Spec("circle", 128, "const:1.75"), X.Spec("circle", 128, "opt_exp")])}
     assert circ["const:1.75"] >= 0.3 and circ["opt_exp"] < circ["const:1.75"]
+
+
+def oracle_spectrum(N, theta, dtau, relax=10, seed=0):
+    spec = X.Spec("rectangle", N, dtau, theta=theta, seed=seed)
+    mode, const = spec.dtau_mode()
+    O = oracle.Problem(2, N, W.sample(2, N, X.DOMAINS["rectangle"][1](N, theta)),
+                       oracle.Options(dtau_mode=mode, dtau_const=const))
+    O.set_rhs(np.zeros(O.nodes(0)), np.zeros(O.counts(0)[1]))
+    u = X.initial_guess(O.classes(0), seed)
+    rhs = O.rhs(0)
+    O.smooth(0, u, rhs, steps=relax)
+    return X.boundary_dft(O.residual(0, u, rhs)[O.ghosts(0)["idx"]])
+
+
+def test_boundary_spectrum_matches_oracle_and_paper():
+    """Sec. 3.2 (DFT of the ghost-column residual after 10 relaxations): the
+    optimal Delta-tau leaves the smallest share of high frequencies; with the
+    red-black interior sweeps this holds for theta = 0.2 and 0.5."""
+    for theta in (0.2, 0.5):
+        opt = X.boundary_residual_spectrum(128, theta, "opt_exp")
+        a, amp, ratio = oracle_spectrum(128, theta, "opt_exp")
+        assert np.allclose(opt["amplitude"], amp, rtol=1e-8, atol=1e-12 * max(amp))
+        assert opt["high_over_low"] == pytest.approx(ratio, rel=1e-8)
+        for f in (0.5, 2.0):
+            other = X.boundary_residual_spectrum(128, theta, f"const:{f * opt['dtau_value']}")
+            assert opt["high_over_low"] < other["high_over_low"], (theta, f)
+
+
+def test_theta_histogram_matches_oracle_and_paper():
+    """Sec. 3.3 remark: on curved domains theta~ fills [0, 1], nearly
+    uniformly away from 1 and thinning as it approaches 1."""
+    for dom in ("circle", "flower"):
+        r = X.theta_histogram(dom, 1024)
+        O = oracle.Problem(2, 1024, W.sample(2, 1024, X.DOMAINS[dom][1](1024, 0.5)))
+        want, _ = np.histogram(O.ghosts(0)["eta"], bins=10, range=(0.0, 1.0))
+        assert np.all(np.abs(np.array(r["counts"]) - want) <= 1), (r["counts"], want.tolist())
+        c = np.array(r["counts"], dtype=float)
+        body = c[:8]
+        assert np.all(np.abs(body - body.mean()) <= 0.25 * body.mean()), c
+        assert c[9] < 0.5 * body.mean() and r["max"] < 1.0 and r["min"] >= 0.0
