@@ -1582,6 +1582,22 @@ static bcmg_status batch_launch_cycles(bcmg_batch *b, int cycles) {
     return BCMG_OK;
 }
 
+// after a synchronisation: add the timed launches to the process-wide counters
+static void drain_timing(bcmg_batch *b) {
+    if (b->tev.empty()) return;
+    for (auto &pr : b->tev) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+        if (e != hipSuccess) continue;
+        g_timing.ms += ms;
+        g_timing.launches++;
+    }
+    b->tev.clear();
+    g_timing.nodes = b->fine_inside;
+}
+
 bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host) {
     if (!b || cycles < 1) return fail(BCMG_ERR_INVALID, "bad argument");
     bcmg_status st = batch_join(b);
@@ -1590,19 +1606,7 @@ bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host)
     if (st) return st;
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState) * b->cap, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    if (!b->tev.empty()) {
-        for (auto &pr : b->tev) {
-            float ms = 0.f;
-            hipError_t e = hipEventElapsedTime(&ms, pr.first, pr.second);
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
-            if (e != hipSuccess) continue;
-            g_timing.ms += ms;
-            g_timing.launches++;
-        }
-        b->tev.clear();
-        g_timing.nodes = b->fine_inside;
-    }
+    drain_timing(b);
     if (active_host)
         for (int s = 0; s < b->cap; s++) active_host[s] = b->prob[s] && b->h_state[s].active ? 1 : 0;
     return BCMG_OK;
@@ -1677,8 +1681,31 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     b->h_state[0].active = 1;
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
+    if ((st = batch_join(b))) return st;
+    // The one-cycle graph is replayed k times between host checks, with k
+    // the number of cycles the observed convergence rate still needs (at
+    // least 1, at most 16): the host waits on the device once per check
+    // rather than once per cycle.  Cycles replayed after convergence find
+    // the slot inactive and change nothing.
+    int k = 1, checked_cycles = 0;
+    double checked_sq = -1.0;
     while (b->h_state[0].active) {
-        if ((st = bcmg_batch_step(b, 1, nullptr))) return st;
+        for (int i = 0; i < k; i++)
+            if ((st = batch_launch_cycles(b, 1))) return st;
+        HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        drain_timing(b);
+        const SlotState &S = b->h_state[0];
+        k = 1;
+        const int dc = S.cycles - checked_cycles;
+        if (S.active && checked_sq > 0.0 && dc > 0 && S.lastsq > 0.0 && S.lastsq < checked_sq && S.tolsq > 0.0) {
+            const double rate = std::log(S.lastsq / checked_sq) / dc;  // log of rho^2 per cycle, < 0
+            const double need = std::log(S.tolsq / S.lastsq) / rate;   // cycles still needed
+            if (need > 1.0) k = (int)std::min(16.0, std::floor(need));
+            k = std::max(1, std::min(k, S.max_cycles - S.cycles));
+        }
+        checked_cycles = S.cycles;
+        checked_sq = S.lastsq;
     }
     HIPCHK(hipEventRecord(e1, b->stream));
     HIPCHK(hipEventSynchronize(e1));
