@@ -26,6 +26,7 @@ DTAU_OPT_EXP, DTAU_OPT_POLY, DTAU_CONST = 0, 1, 2
 RESTRICT_RENORM_FW, RESTRICT_PLAIN_MEAN = 0, 1
 SMOOTH_RB, SMOOTH_LEX = 0, 1
 CYCLE_V, CYCLE_TGCS = 0, 1
+BC_DIRICHLET, BC_NEUMANN = 0, 1
 
 
 class _Opts(C.Structure):
@@ -33,6 +34,7 @@ class _Opts(C.Structure):
         ("nu1", C.c_int), ("nu2", C.c_int), ("coarsest_N", C.c_int), ("max_cycles", C.c_int),
         ("dtau_mode", C.c_int), ("dtau_const", C.c_double), ("ext_iters", C.c_int),
         ("restrict_mode", C.c_int), ("smoother", C.c_int), ("cycle", C.c_int),
+        ("bc", C.c_int), ("reaction", C.c_double),
     ]
 
 
@@ -62,6 +64,9 @@ def lib():
         L.or_default_options.argtypes = [C.POINTER(_Opts)]
         L.or_dtau.restype = d
         L.or_dtau.argtypes = [i, d, i, d]
+        L.or_dtau_neumann.restype = d
+        L.or_dtau_neumann.argtypes = [i, d, i, d]
+        L.or_get_ghost_nd.argtypes = [vp, i, vp]
         L.or_classify.argtypes = [i, i, vp, vp]
         for name, args in [
             ("or_num_levels", [vp]), ("or_level_N", [vp, i]), ("or_coarse_singular", [vp]),
@@ -114,14 +119,22 @@ class Options:
     restrict_mode: int = RESTRICT_RENORM_FW
     smoother: int = SMOOTH_RB
     cycle: int = CYCLE_V
+    bc: int = BC_DIRICHLET
+    reaction: float = 0.0
 
     def _c(self) -> _Opts:
         return _Opts(self.nu1, self.nu2, self.coarsest_N, self.max_cycles, self.dtau_mode,
-                     float(self.dtau_const), self.ext_iters, self.restrict_mode, self.smoother, self.cycle)
+                     float(self.dtau_const), self.ext_iters, self.restrict_mode, self.smoother, self.cycle,
+                     self.bc, float(self.reaction))
 
 
 def dtau(d: int, theta: float, mode: int = DTAU_OPT_EXP, const: float = 1.0) -> float:
     return lib().or_dtau(d, float(theta), mode, float(const))
+
+
+def dtau_neumann(d: int, theta: float, mode: int = DTAU_OPT_EXP, const: float = 1.0) -> float:
+    """Delta tau / h of a Neumann ghost row."""
+    return lib().or_dtau_neumann(d, float(theta), mode, float(const))
 
 
 def classify(d: int, N: int, phi: np.ndarray) -> np.ndarray:
@@ -181,8 +194,10 @@ class Problem:
         g = dict(idx=np.empty(ng, np.int64), w=np.empty((ng, 3), np.int32), s=np.empty((ng, 3), np.int32),
                  fb=np.empty(ng, np.int32), eta=np.empty(ng), n=np.empty((ng, 3)), q=np.empty((ng, 3)),
                  tau=np.empty((ng, 3)), dtau=np.empty(ng))
+        g["nd"] = np.zeros((ng, 3))
         if ng:
             lib().or_get_ghosts(self.h, l, *[_p(g[k]) for k in ("idx", "w", "s", "fb", "eta", "n", "q", "tau", "dtau")])
+            lib().or_get_ghost_nd(self.h, l, _p(g["nd"]))
         return g
 
     def coarse_singular(self) -> bool:

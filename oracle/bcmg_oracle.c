@@ -42,6 +42,9 @@
 #define OR_CYCLE_V 0
 #define OR_CYCLE_TGCS 1
 
+#define OR_BC_DIRICHLET 0
+#define OR_BC_NEUMANN 1
+
 #define OR_MAXLEV 16
 
 typedef struct {
@@ -54,6 +57,8 @@ typedef struct {
     int restrict_mode;   /* RENORM_FW or PLAIN_MEAN */
     int smoother;        /* RB (red-black GS) or LEX (GS-LEX) for the interior */
     int cycle;           /* V-cycle or two-grid correction scheme */
+    int bc;              /* condition on Gamma: DIRICHLET (B u = u) or NEUMANN (B u = grad u . n), Sec. 3.3 */
+    double reaction;     /* c >= 0 in c u - Laplace u = f (c = 1: the reaction-diffusion tests of Sec. 3.3 / 4.2) */
 } or_options;
 
 typedef struct {
@@ -73,6 +78,9 @@ typedef struct {
     double *gq;          /* [ng][3] projection Q */
     double *gtau;        /* [ng][3] local coordinates of Q in the stencil */
     double *gdtau;       /* fictitious time step */
+    double *gnd;         /* [ng][3] Neumann rows: coefficient of d/dt_k of the interpolant (t_k local) */
+    int bc;              /* boundary row type of every ghost (OR_BC_*) */
+    double reaction;     /* c of the interior row */
     double *u, *rhs, *r, *e; /* work arrays (coarse levels own u and rhs) */
 } or_level;
 
@@ -131,6 +139,8 @@ void or_default_options(or_options *o) {
     o->restrict_mode = OR_RESTRICT_RENORM_FW;
     o->smoother = OR_SMOOTH_RB;
     o->cycle = OR_CYCLE_V;
+    o->bc = OR_BC_DIRICHLET;
+    o->reaction = 0.0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -169,6 +179,59 @@ double or_dtau(int d, double theta, int mode, double dtau_const) {
         } else {
             double c[3];
             or_coeff(t, c);
+            g = fabs(c[2] * exp(-2.0 * pv[v]) + c[1] * exp(-pv[v]) + c[0]);
+        }
+        if (g < gmin) gmin = g;
+        if (g > gmax) gmax = g;
+    }
+    return 2.0 / (gmin + gmax);
+}
+
+/* Coefficients of the quadratic Neumann boundary row in units of 1/h,
+ * eq. (coeffN): c_0, c_{-1}, c_{-2}. */
+static void or_coeff_n(double t, double c[3]) {
+    c[0] = 1.5 - t;
+    c[1] = 2.0 * (t - 1.0);
+    c[2] = 0.5 - t;
+}
+
+/*
+ * Delta tau / h for Neumann rows as a function of theta~ (eq. DtauOptTheta
+ * with Prop. optN in 2D and Prop. opt3DN in 3D); the caller multiplies by h.
+ *  POLY:  2 / (min G0 + max G0), G0 = sum_r c_{-r} e^{-r p} with the
+ *         coefficients of eq. (coeffN), over the same vertices as the
+ *         Dirichlet form.  G0 is monotone in p (Lemma fnostatN) and positive
+ *         (Lemma G0posN), so the vertices give the extremes.
+ *  EXP:   Remark exptheta2D: G0 = p exp(-p theta) over p in
+ *         [acosh(2), acosh(2d-1)].  This G0 is not monotone in p: its maximum
+ *         over the interval is at p = 1/theta when that point lies inside,
+ *         its minimum at an end.
+ *  CONST: dtau_const (the constant is given in units of h).
+ *  d = 1: p = 0 makes both optimal forms vanish; the ghost row is then
+ *         relaxed by its own Gauss-Seidel step (returns HUGE_VAL, which the
+ *         caller caps at 1/c_0).
+ */
+double or_dtau_neumann(int d, double theta, int mode, double dtau_const) {
+    if (mode == OR_DTAU_CONST) return dtau_const;
+    double t = theta < 1.0 ? theta : 1.0;
+    if (t < 0.0) t = 0.0;
+    if (d == 1) return HUGE_VAL;
+    double pv[5];
+    int nv = 0;
+    for (int i = 1; i < d; i++) pv[nv++] = acosh(1.0 + i);
+    pv[nv++] = acosh(2.0 * d - 1.0);
+    if (mode == OR_DTAU_OPT_EXP && t > 0.0) {
+        double pstar = 1.0 / t;
+        if (pstar > pv[0] && pstar < pv[nv - 1]) pv[nv++] = pstar;
+    }
+    double gmin = INFINITY, gmax = -INFINITY;
+    for (int v = 0; v < nv; v++) {
+        double g;
+        if (mode == OR_DTAU_OPT_EXP) {
+            g = pv[v] * exp(-pv[v] * t);
+        } else {
+            double c[3];
+            or_coeff_n(t, c);
             g = fabs(c[2] * exp(-2.0 * pv[v]) + c[1] * exp(-pv[v]) + c[0]);
         }
         if (g < gmin) gmin = g;
@@ -240,6 +303,38 @@ static double or_lagrange(int w, int m, double t) {
     return t * (t - 1.0) / 2.0;
 }
 
+/* d/dt of the Lagrange basis on nodes 0..w-1 at t */
+static double or_lagrange_dt(int w, int m, double t) {
+    if (w == 1) return 0.0;
+    if (w == 2) return m == 0 ? -1.0 : 1.0;
+    if (m == 0) return t - 1.5;
+    if (m == 1) return 2.0 - 2.0 * t;
+    return t - 0.5;
+}
+
+/*
+ * Weight of block node m (node G - m o s) in the ghost row B u~(Q) (eq. BCh),
+ * u~ the tensor-product interpolant of widths w at local coordinates tau:
+ *   Dirichlet: u~(Q)            = sum_m prod_k L_{m_k}(tau_k) u_m
+ *   Neumann:   grad u~(Q) . n   = sum_m sum_k nd_k L'_{m_k}(tau_k) prod_{j!=k} L_{m_j}(tau_j) u_m
+ * with nd_k = dt_k/dx_k n_k = -s_k n_k / h (t_k grows along -s_k).
+ */
+static double or_row_weight(int bc, const int w[3], const double tau[3], const double nd[3], const int m[3]) {
+    if (bc == OR_BC_DIRICHLET) {
+        double wgt = 1.0;
+        for (int k = 0; k < 3; k++) wgt *= or_lagrange(w[k], m[k], tau[k]);
+        return wgt;
+    }
+    double acc = 0.0;
+    for (int k = 0; k < 3; k++) {
+        double term = nd[k] * or_lagrange_dt(w[k], m[k], tau[k]);
+        for (int j = 0; j < 3; j++)
+            if (j != k) term *= or_lagrange(w[j], m[j], tau[j]);
+        acc += term;
+    }
+    return acc;
+}
+
 /* Tensor-product quadratic interpolant of phi on the 3^d block
  * {I - m o s : m_k in 0..2} evaluated at local coordinates t. */
 static double or_phi_tilde(const or_level *L, const int I[3], const int s[3], const double t[3]) {
@@ -261,7 +356,10 @@ static double or_phi_tilde(const or_level *L, const int I[3], const int s[3], co
     return val;
 }
 
-/* Is the block {I - m o s : 0 <= m_k < w_k} made of in-box INSIDE/GHOST nodes? */
+/* Is the block {I - m o s : 0 <= m_k < w_k} made of in-box INSIDE/GHOST
+ * nodes?  Neumann rows also admit BOXDIR nodes (known values g_B): a ghost
+ * where Gamma meets a box face otherwise has no block with a derivative
+ * along the normal. */
 static int or_block_valid(const or_level *L, const int I[3], const int s[3], const int w[3]) {
     int m[3];
     for (m[2] = 0; m[2] < w[2]; m[2]++)
@@ -271,29 +369,30 @@ static int or_block_valid(const or_level *L, const int I[3], const int s[3], con
                 for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
                 if (!or_in_box(L, J)) return 0;
                 unsigned char c = L->cls[or_index(L, J)];
+                if (c == OR_BOXDIR && L->bc == OR_BC_NEUMANN) continue;
                 if (c != OR_INSIDE && c != OR_GHOST) return 0;
             }
     return 1;
 }
 
-/* c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block) */
-static int or_block_dominant(const or_level *L, const int I[3], const int s[3], const int w[3], const double tau[3], double f) {
-    double c0 = 1.0, off = 0.0;
+/* c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block); a
+ * Neumann row also needs c_0 > 0 (a width-1 axis carries no derivative) */
+static int or_block_dominant(const or_level *L, const int I[3], const int s[3], const int w[3], const double tau[3],
+                             const double nd[3], double f) {
+    double c0 = 0.0, off = 0.0;
     int m[3];
     for (m[2] = 0; m[2] < w[2]; m[2]++)
         for (m[1] = 0; m[1] < w[1]; m[1]++)
             for (m[0] = 0; m[0] < w[0]; m[0]++) {
                 int J[3];
-                double wgt = 1.0;
-                for (int k = 0; k < 3; k++) {
-                    J[k] = I[k] - m[k] * s[k];
-                    wgt *= or_lagrange(w[k], m[k], tau[k]);
-                }
+                for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
+                double wgt = or_row_weight(L->bc, w, tau, nd, m);
                 if (m[0] == 0 && m[1] == 0 && m[2] == 0)
                     c0 = wgt;
                 else if (L->cls[or_index(L, J)] == OR_GHOST)
                     off += fabs(wgt);
             }
+    if (L->bc == OR_BC_NEUMANN && !(c0 > 0.0)) return 0;
     return c0 >= f * off;
 }
 
@@ -404,18 +503,45 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
      * geometry is under-resolved, lose the full stencil) */
     const int(*cand)[3] = d == 3 ? cand3 : (d == 2 ? cand2 : cand1);
     int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
+    /* Neumann rows: coefficient of d/dt_k in n . grad (t_k = (x_G - x)_k s_k / h) */
+    double nd[3] = {0.0, 0.0, 0.0};
+    if (L->bc == OR_BC_NEUMANN)
+        for (int k = 0; k < d; k++) nd[k] = -(double)s[k] * n[k] / L->h;
     int w[3] = {1, 1, 1};
+    int found = 0;
     for (int c = 0; c < ncand; c++) {
         int wt[3] = {1, 1, 1};
         for (int r = 0; r < d; r++) wt[ord[r]] = cand[c][r];
         if (!or_block_valid(L, I, s, wt)) continue;
         double tt[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(n[k]) : 0.0;
-        if (!or_block_dominant(L, I, s, wt, tt, level > 0 ? 1.0 : 0.5)) continue;
+        if (!or_block_dominant(L, I, s, wt, tt, nd, level > 0 ? 1.0 : 0.5)) continue;
         w[0] = wt[0];
         w[1] = wt[1];
         w[2] = wt[2];
+        found = 1;
         break;
+    }
+    /* a Neumann row with no admissible block (every candidate has a width-1
+     * axis along the whole normal, or fails the test above): the one-sided
+     * difference (u_G - u_J) / h towards the first INSIDE axis neighbour J
+     * (order -x, +x, -y, +y, -z, +z), flagged in fb with bit 2 */
+    int last_resort = -1;
+    if (!found && L->bc == OR_BC_NEUMANN) {
+        for (int k = 0; k < d && last_resort < 0; k++)
+            for (int sgn = -1; sgn <= 1 && last_resort < 0; sgn += 2) {
+                int J[3] = {I[0], I[1], I[2]};
+                J[k] += sgn;
+                if (or_in_box(L, J) && L->cls[or_index(L, J)] == OR_INSIDE) {
+                    last_resort = k;
+                    s[k] = -sgn;
+                }
+            }
+        for (int k = 0; k < 3; k++) {
+            w[k] = k == last_resort ? 2 : 1;
+            nd[k] = k == last_resort ? -1.0 / L->h : 0.0;
+        }
+        fb |= 2;
     }
 
     for (int k = 0; k < 3; k++) {
@@ -424,18 +550,20 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
         L->gn[3 * gi + k] = n[k];
         double xk = k < d ? -1.0 + I[k] * L->h : 0.0;
         L->gq[3 * gi + k] = k < d ? xk - eta * L->h * n[k] : 0.0;
-        L->gtau[3 * gi + k] = (k < d && w[k] >= 2) ? eta * fabs(n[k]) : 0.0;
+        L->gtau[3 * gi + k] = (k < d && w[k] >= 2 && last_resort < 0) ? eta * fabs(n[k]) : 0.0;
+        L->gnd[3 * gi + k] = nd[k];
     }
     L->geta[gi] = eta;
     L->gfb[gi] = fb;
-    double dt = or_dtau(d, eta, o->dtau_mode, o->dtau_const);
+    double dt = L->bc == OR_BC_NEUMANN ? L->h * or_dtau_neumann(d, eta, o->dtau_mode, o->dtau_const)
+                                       : or_dtau(d, eta, o->dtau_mode, o->dtau_const);
     /* never relax a ghost row beyond its own Gauss-Seidel step dtau = 1/c_0
      * (the value the relaxation reduces to at theta = 0, Sec. 2.1); on the
      * quadratic row of the BLFA this bound is inactive in 2D and within 3%
      * in 3D, it only tames the shortened stencils */
     if (o->dtau_mode != OR_DTAU_CONST) {
-        double c0 = 1.0;
-        for (int k = 0; k < 3; k++) c0 *= or_lagrange(w[k], 0, L->gtau[3 * gi + k]);
+        const int m0[3] = {0, 0, 0};
+        double c0 = or_row_weight(L->bc, w, &L->gtau[3 * gi], nd, m0);
         if (c0 > 0.0 && dt * c0 > 1.0) dt = 1.0 / c0;
     }
     L->gdtau[gi] = dt;
@@ -444,7 +572,8 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
 /* ------------------------------------------------------------------------- */
 /* Operators                                                                  */
 
-/* sum_m w_m u(G - m o s) over the ghost block (eq. BCh, Dirichlet) */
+/* sum_m w_m u(G - m o s) over the ghost block (eq. BCh; the weights of
+ * or_row_weight for the level's boundary type) */
 static double or_ghost_row(const or_level *L, long gi, const double *u) {
     long p = L->gidx[gi];
     int I[3];
@@ -452,27 +581,48 @@ static double or_ghost_row(const or_level *L, long gi, const double *u) {
     const int *w = &L->gw[3 * gi];
     const int *s = &L->gs[3 * gi];
     const double *tau = &L->gtau[3 * gi];
+    const double *nd = &L->gnd[3 * gi];
     double acc = 0.0;
     int m[3];
     for (m[2] = 0; m[2] < w[2]; m[2]++)
         for (m[1] = 0; m[1] < w[1]; m[1]++)
             for (m[0] = 0; m[0] < w[0]; m[0]++) {
                 int J[3];
-                double wgt = 1.0;
-                for (int k = 0; k < 3; k++) {
-                    J[k] = I[k] - m[k] * s[k];
-                    wgt *= or_lagrange(w[k], m[k], tau[k]);
-                }
+                for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
+                double wgt = or_row_weight(L->bc, w, tau, nd, m);
                 acc += wgt * u[or_index(L, J)];
             }
     return acc;
 }
 
-/* interior row (eq. Laph and its 1D/3D analogues): (2d u_P - sum nbrs)/h^2 */
+/* the part of the ghost row on BOXDIR block nodes (Neumann rows only) */
+static double or_ghost_row_boxdir(const or_level *L, long gi, const double *u) {
+    long p = L->gidx[gi];
+    int I[3];
+    or_coords(L, p, I);
+    const int *w = &L->gw[3 * gi];
+    const int *s = &L->gs[3 * gi];
+    double acc = 0.0;
+    int m[3];
+    for (m[2] = 0; m[2] < w[2]; m[2]++)
+        for (m[1] = 0; m[1] < w[1]; m[1]++)
+            for (m[0] = 0; m[0] < w[0]; m[0]++) {
+                int J[3];
+                for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
+                long q = or_index(L, J);
+                if (L->cls[q] == OR_BOXDIR) acc += or_row_weight(L->bc, w, &L->gtau[3 * gi], &L->gnd[3 * gi], m) * u[q];
+            }
+    return acc;
+}
+
+/* interior row (eq. Laph and its 1D/3D analogues) of c u - Laplace u:
+ * (2d u_P - sum nbrs)/h^2 + c u_P  (c = 0: the Poisson problem) */
 static double or_lap(const or_level *L, long p, const double *u) {
     double s = 0.0;
     for (int k = 0; k < L->d; k++) s += u[p + L->st[k]] + u[p - L->st[k]];
-    return (2.0 * L->d * u[p] - s) / (L->h * L->h);
+    double v = (2.0 * L->d * u[p] - s) / (L->h * L->h);
+    if (L->reaction != 0.0) v += L->reaction * u[p];
+    return v;
 }
 
 /* A u on INSIDE and GHOST rows, 0 elsewhere (the system A_h u_h = f_h) */
@@ -514,13 +664,14 @@ double or_norm(or_problem *P, int l, const double *r) {
 void or_smooth(or_problem *P, int l, double *u, const double *rhs) {
     or_level *L = &P->lev[l];
     double h2 = L->h * L->h;
+    double diag = 2.0 * L->d + L->reaction * h2; /* h^2 times the row's own coefficient */
     int I[3];
     if (P->opt.smoother == OR_SMOOTH_LEX) {
         for (long p = 0; p < L->nn; p++) {
             if (L->cls[p] != OR_INSIDE) continue;
             double s = 0.0;
             for (int k = 0; k < L->d; k++) s += u[p + L->st[k]] + u[p - L->st[k]];
-            u[p] = (h2 * rhs[p] + s) / (2.0 * L->d);
+            u[p] = (h2 * rhs[p] + s) / diag;
         }
     } else {
         for (int colour = 0; colour < 2; colour++) {
@@ -530,7 +681,7 @@ void or_smooth(or_problem *P, int l, double *u, const double *rhs) {
                 if (((I[0] + I[1] + I[2]) & 1) != colour) continue;
                 double s = 0.0;
                 for (int k = 0; k < L->d; k++) s += u[p + L->st[k]] + u[p - L->st[k]];
-                u[p] = (h2 * rhs[p] + s) / (2.0 * L->d);
+                u[p] = (h2 * rhs[p] + s) / diag;
             }
         }
     }
@@ -754,7 +905,7 @@ static void or_coarse_factor(or_problem *P) {
     double ih2 = 1.0 / (L->h * L->h);
     for (long row = 0; row < L->ni; row++) {
         long p = P->cmap[row];
-        P->lu[row * nc + row] += 2.0 * L->d * ih2;
+        P->lu[row * nc + row] += 2.0 * L->d * ih2 + L->reaction;
         for (int k = 0; k < L->d; k++) {
             for (int sgn = -1; sgn <= 1; sgn += 2) {
                 long q = p + sgn * L->st[k];
@@ -770,17 +921,16 @@ static void or_coarse_factor(or_problem *P) {
         const int *w = &L->gw[3 * gi];
         const int *s = &L->gs[3 * gi];
         const double *tau = &L->gtau[3 * gi];
+        const double *nd = &L->gnd[3 * gi];
         int m[3];
         for (m[2] = 0; m[2] < w[2]; m[2]++)
             for (m[1] = 0; m[1] < w[1]; m[1]++)
                 for (m[0] = 0; m[0] < w[0]; m[0]++) {
                     int J[3];
-                    double wgt = 1.0;
-                    for (int k = 0; k < 3; k++) {
-                        J[k] = I[k] - m[k] * s[k];
-                        wgt *= or_lagrange(w[k], m[k], tau[k]);
-                    }
-                    P->lu[row * nc + pos[or_index(L, J)]] += wgt;
+                    for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
+                    double wgt = or_row_weight(L->bc, w, tau, nd, m);
+                    long q = or_index(L, J);
+                    if (pos[q] >= 0) P->lu[row * nc + pos[q]] += wgt; /* BOXDIR: right-hand side */
                 }
     }
     free(pos);
@@ -835,6 +985,8 @@ void or_coarse_solve(or_problem *P, double *u, const double *rhs) {
                     long q = p + sgn * L->st[k];
                     if (L->cls[q] == OR_BOXDIR) b[row] += u[q] * ih2;
                 }
+        else
+            b[row] -= or_ghost_row_boxdir(L, row - L->ni, u);
     }
     const double *A = P->lu;
     for (long k = 0; k < nc; k++) {
@@ -966,6 +1118,9 @@ static void or_level_geometry(or_level *L, int level, const or_options *o) {
     L->gq = (double *)malloc(sizeof(double) * 3 * ng);
     L->gtau = (double *)malloc(sizeof(double) * 3 * ng);
     L->gdtau = (double *)malloc(sizeof(double) * ng);
+    L->gnd = (double *)malloc(sizeof(double) * 3 * ng);
+    L->bc = o->bc;
+    L->reaction = o->reaction;
     long c = 0;
     for (long p = 0; p < L->nn; p++)
         if (L->cls[p] == OR_GHOST) L->gidx[c++] = p;
@@ -1034,6 +1189,7 @@ void or_destroy(or_problem *P) {
         free(L->gq);
         free(L->gtau);
         free(L->gdtau);
+        free(L->gnd);
     }
     free(P->cmap);
     free(P->lu);
@@ -1072,6 +1228,11 @@ void or_get_ghosts(or_problem *P, int l, long *idx, int *w, int *s, int *fb, dou
     if (q) memcpy(q, L->gq, sizeof(double) * 3 * ng);
     if (tau) memcpy(tau, L->gtau, sizeof(double) * 3 * ng);
     if (dtau) memcpy(dtau, L->gdtau, sizeof(double) * ng);
+}
+
+/* Neumann derivative coefficients nd[ng*3] (0 for Dirichlet rows) */
+void or_get_ghost_nd(or_problem *P, int l, double *nd) {
+    memcpy(nd, P->lev[l].gnd, sizeof(double) * 3 * P->lev[l].ng);
 }
 
 /* Finest-level right-hand side: f on INSIDE nodes, g(Q) on ghost rows
