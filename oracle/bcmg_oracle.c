@@ -989,6 +989,8 @@ void or_coarse_solve(or_problem *P, double *u, const double *rhs) {
             b[row] -= or_ghost_row_boxdir(L, row - L->ni, u);
     }
     const double *A = P->lu;
+    /* the factorisation swapped whole rows, multipliers included (P A = L U
+     * with P the interchanges in order): permute b first, then L y = P b */
     for (long k = 0; k < nc; k++) {
         long pr = P->piv[k];
         if (pr != k) {
@@ -996,8 +998,9 @@ void or_coarse_solve(or_problem *P, double *u, const double *rhs) {
             b[k] = b[pr];
             b[pr] = t;
         }
-        for (long i = k + 1; i < nc; i++) b[i] -= A[i * nc + k] * b[k];
     }
+    for (long k = 0; k < nc; k++)
+        for (long i = k + 1; i < nc; i++) b[i] -= A[i * nc + k] * b[k];
     for (long k = nc - 1; k >= 0; k--) {
         double s = b[k];
         for (long j = k + 1; j < nc; j++) s -= A[k * nc + j] * b[j];

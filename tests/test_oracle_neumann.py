@@ -216,6 +216,39 @@ def test_test1n_convergence_factors_match_the_paper():
     assert max(opt) < min(consts.values())
 
 
+def spheres_phi():
+    rng = np.random.Generator(np.random.PCG64(7))
+    cen = rng.uniform(-0.7, 0.7, size=(30, 3))
+    rad = rng.uniform(0.05, 0.2, size=30)
+    return W.phi_spheres(cen, rad)
+
+
+def test_coarse_solve_is_exact_when_it_pivots():
+    """The coarsest Neumann operator of a 65^3 union of small spheres needs
+    row interchanges; the direct solve still satisfies A u = rhs exactly
+    (Sec. 2.1: the coarse problem is solved exactly), checked against the
+    operator applied column by column and a dense solve."""
+    P = oracle.Problem(3, 64, W.sample(3, 64, spheres_phi()), oracle.Options(bc=NEU, reaction=1.0))
+    l = P.L - 1
+    cls = P.classes(l)
+    unk = np.nonzero((cls == oracle.INSIDE) | (cls == oracle.GHOST))[0]
+    A = np.zeros((len(unk), len(unk)))
+    for j, q in enumerate(unk):
+        e = np.zeros(cls.size)
+        e[q] = 1.0
+        A[:, j] = P.apply_A(l, e)[unk]
+    assert np.linalg.cond(A) < 1e4
+    # partial pivoting must swap rows here (the diagonal is not dominant)
+    assert any(abs(A[k, k]) < np.abs(A[k + 1:, k]).max(initial=0.0) for k in range(len(unk)))
+    rng = np.random.default_rng(17)
+    rhs = np.zeros(cls.size)
+    rhs[unk] = rng.standard_normal(len(unk))
+    u = np.zeros(cls.size)
+    P.coarse_solve(u, rhs)
+    assert np.abs(A @ u[unk] - rhs[unk]).max() <= 1e-12 * np.abs(rhs).max()
+    assert np.allclose(u[unk], np.linalg.solve(A, rhs[unk]), rtol=1e-11, atol=1e-12)
+
+
 def test_coarse_solve_with_boxdir_in_neumann_blocks():
     N = 64
     P = oracle.Problem(2, N, W.sample(2, N, line_phi(N)), oracle.Options(bc=NEU))
