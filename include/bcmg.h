@@ -59,9 +59,17 @@ typedef int32_t bcmg_status;
 #define BCMG_FP64 0   /* every step in FP64 */
 #define BCMG_MIXED 1  /* FP32 cycle on the correction, FP64 residual, update and coarse solve */
 
+/* Dirichlet rows (Neumann rows: dtau / h, with the forms of Prop. optN /
+ * opt3DN and G0 = p e^{-p t} over p in [acosh 2, acosh(2d-1)], whose maximum
+ * may be interior at p = 1/t) */
 #define BCMG_DTAU_OPT_EXP 0  /* dtau = 2/(e^{-p1 t} + e^{-pd t}), Remark exptheta2D */
-#define BCMG_DTAU_OPT_POLY 1 /* dtau = 2/(min|G0| + max|G0|), Prop. opt / opt3D, eq. coeff */
-#define BCMG_DTAU_CONST 2    /* dtau = dtau_const on every ghost (the constant strategy) */
+#define BCMG_DTAU_OPT_POLY 1 /* dtau = 2/(min|G0| + max|G0|), Prop. opt / opt3D, eq. coeff (coeffN) */
+#define BCMG_DTAU_CONST 2    /* dtau = dtau_const on every ghost (Neumann: dtau_const * h) */
+
+/* boundary condition B u = g on Gamma (Sec. 3.3; the box faces keep the
+ * Dirichlet data g_B) */
+#define BCMG_BC_DIRICHLET 0  /* B u = u */
+#define BCMG_BC_NEUMANN 1    /* B u = grad u . n, n the ghost's outward unit normal */
 
 #define BCMG_RESTRICT_RENORM_FW 0 /* FW weights renormalised over the admissible nodes */
 #define BCMG_RESTRICT_PLAIN_MEAN 1 /* unweighted mean over the admissible nodes */
@@ -80,6 +88,9 @@ typedef struct {
     int32_t ext_iters;     /* K: Jacobi sweeps of the normal extension (default 4, 1..8) */
     int32_t restrict_mode; /* BCMG_RESTRICT_* */
     int32_t seg_len;       /* row tile: nodes per row segment handled by one wavefront (64 or 128, default 128) */
+    int32_t bc;            /* BCMG_BC_* on Gamma (default Dirichlet) */
+    double reaction;       /* c >= 0 of c u - Laplace u = f (default 0: Poisson; 1: the reaction-diffusion
+                              tests of Sec. 3.3 / Sec. 4.2 with Neumann rows) */
 } bcmg_options;
 
 typedef struct {
@@ -146,7 +157,12 @@ bcmg_status bcmg_classes(const bcmg_problem *prob, int32_t level, uint8_t *cls_d
  *   q_dev     double[3*n_ghost]  projection Q = G - eta h n
  *   tau_dev   double[3*n_ghost]  local coordinates of Q along each stencil axis
  *   dtau_dev  double[n_ghost]    fictitious time step of the ghost row
- *   fallback_dev int32[n_ghost]  1 if the root search fell back to the first-order distance
+ *   fallback_dev int32[n_ghost]  bit 0: the root search fell back to the first-order
+ *                                distance; bit 1: a Neumann row with no admissible
+ *                                block, replaced by (u_G - u_J)/h towards the first
+ *                                INSIDE axis neighbour J
+ * Neumann rows are the normal derivative of the tensor-product interpolant
+ * at Q, sum_k n_k d/dx_k; their blocks may contain BOXDIR nodes.
  */
 bcmg_status bcmg_ghost_info(const bcmg_problem *prob, int32_t level, int32_t *idx_dev, int32_t *code_dev,
                             double *eta_dev, double *normal_dev, double *q_dev, double *tau_dev, double *dtau_dev,
@@ -155,7 +171,8 @@ bcmg_status bcmg_ghost_info(const bcmg_problem *prob, int32_t level, int32_t *id
 /*
  * Right-hand side of the finest level: f_dev (nodes; used on INSIDE nodes) and
  * gq_dev (n_ghost values g(Q) in ghost-list order, the boundary data at the
- * projections returned by bcmg_ghost_info).  Both copied; NULL f means 0.
+ * projections returned by bcmg_ghost_info; for Neumann rows the normal
+ * derivative along each ghost's normal).  Both copied; NULL f means 0.
  */
 bcmg_status bcmg_set_data(bcmg_problem *prob, const double *f_dev, const double *gq_dev);
 

@@ -59,6 +59,7 @@ struct LevelH {
     double *phi = nullptr;
     int *gidx = nullptr, *gcode = nullptr, *gfb = nullptr;
     double *gtau = nullptr, *gdtau = nullptr, *geta = nullptr, *gn = nullptr, *gq = nullptr;
+    double *gnd = nullptr;                 // Neumann derivative coefficients [3*ng] (Neumann problems only)
     int *bidx = nullptr;
     long long ne = 0, nr = 0;              // entries of the extension / restriction rows
     int *bneed = nullptr;                  // band entries read by the prolongation (levels >= 1)
@@ -130,6 +131,7 @@ struct bcmg_batch {
     hipEvent_t join = nullptr;
     long long fine_inside = 0;          // INSIDE nodes on the finest aligned level
     int d = 0, fp32 = 0, nu1 = 2, nu2 = 1, K = 4, max_hist = 0;
+    int neu = 0;                        // some slot has Neumann ghost rows (set at rebuild)
     std::vector<bcmg_problem *> prob;
     std::vector<double *> u;
     std::vector<double> rtol;
@@ -314,6 +316,8 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
     D.cmap = V.cmap;
     D.slot = slot;
     D.restrict_mode = P->opt.restrict_mode;
+    D.gnd = P->opt.bc == BCMG_BC_NEUMANN ? V.gnd : nullptr;
+    D.reaction = P->opt.reaction;
     return D;
 }
 
@@ -443,10 +447,11 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         (st = dalloc_t(P, &V.gtau, 3 * ng)) || (st = dalloc_t(P, &V.gdtau, ng)) || (st = dalloc_t(P, &V.geta, ng)) ||
         (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gnew, ng)))
         return st;
+    if (P->opt.bc == BCMG_BC_NEUMANN && (st = dalloc_t(P, &V.gnd, 3 * ng))) return st;
     launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
     PHASE("ghost list", l);
-    launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const, V.gcode,
-                          V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, s);
+    launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const,
+                          P->opt.bc, V.gcode, V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, V.gnd, s);
     PHASE("geometry", l);
     // extension band (only levels that restrict or receive a prolongation need it)
     {
@@ -549,8 +554,8 @@ bcmg_status setup_coarse(bcmg_problem *P) {
         (st = dalloc_t(P, &V.cmap, (size_t)std::max(1, ncmax))) ||
         (st = dalloc_t(P, &work, (size_t)std::max(1, 2 * ncmax * ncmax))) || (st = dalloc_t(P, &info, 2)))
         return st;
-    launch_coarse_setup(P->d, V.N, V.h, V.cls, V.gidx, (int)V.ng, V.gcode, V.gtau, work, V.ainv, V.cmap, info,
-                        P->stream);
+    launch_coarse_setup(P->d, V.N, V.h, V.cls, V.gidx, (int)V.ng, V.gcode, V.gtau, P->opt.bc, V.gnd, P->opt.reaction,
+                        work, V.ainv, V.cmap, info, P->stream);
     int h[2];
     HIPCHK(hipMemcpyAsync(h, info, sizeof h, hipMemcpyDeviceToHost, P->stream));
     HIPCHK(hipStreamSynchronize(P->stream));
@@ -633,6 +638,8 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->ext_iters = 4;
     o->restrict_mode = BCMG_RESTRICT_RENORM_FW;
     o->seg_len = kSegLen;
+    o->bc = BCMG_BC_DIRICHLET;
+    o->reaction = 0.0;
     return BCMG_OK;
 }
 
@@ -653,6 +660,8 @@ static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
     if (o->ext_iters < 1 || o->ext_iters > 8) return fail(BCMG_ERR_INVALID, "ext_iters must be in 1..8");
     if (o->restrict_mode != 0 && o->restrict_mode != 1) return fail(BCMG_ERR_INVALID, "bad restrict_mode");
     if (o->seg_len != 64 && o->seg_len != 128) return fail(BCMG_ERR_INVALID, "seg_len must be 64 or 128");
+    if (o->bc != BCMG_BC_DIRICHLET && o->bc != BCMG_BC_NEUMANN) return fail(BCMG_ERR_INVALID, "bad bc");
+    if (!(o->reaction >= 0.0 && std::isfinite(o->reaction))) return fail(BCMG_ERR_INVALID, "reaction must be >= 0");
     return BCMG_OK;
 }
 
@@ -881,7 +890,8 @@ bcmg_status bcmg_level_smooth(bcmg_problem *P, int32_t l, double *u, const doubl
     for (int i = 0; i < steps; i++) {
         launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 0, P->d_stepst, P->stream);
         launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 1, P->d_stepst, P->stream);
-        launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream);
+        launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream, nullptr, 0,
+                           P->opt.bc == BCMG_BC_NEUMANN);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
@@ -902,7 +912,7 @@ bcmg_status bcmg_level_residual(bcmg_problem *P, int32_t l, const double *u, con
         P->partials_cap = need;
     }
     launch_residual(P->d, 0, 0, norm_host ? 1 : 0, P->d_step, segs, P->n_seg[l], gch, P->n_gch[l], P->d_stepst,
-                    P->d_partials, P->stream);
+                    P->d_partials, P->stream, P->opt.bc == BCMG_BC_NEUMANN);
     if (norm_host) {
         NormRange R{0, P->n_seg[l], 0, P->n_gch[l]};
         HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
@@ -969,7 +979,8 @@ bcmg_status bcmg_coarse_solve(bcmg_problem *P, double *u, const double *rhs) {
         for (int i = 0; i < 50; i++) {
             launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 0, P->d_stepst, P->stream);
             launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[l], 1, P->d_stepst, P->stream);
-            launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream);
+            launch_ghost_relax(P->d, 0, P->d_step, gch, P->n_gch[l], P->d_stepst, P->stream, nullptr, 0,
+                           P->opt.bc == BCMG_BC_NEUMANN);
         }
     } else {
         int lvl = l;
@@ -1091,6 +1102,7 @@ static size_t lds_plan(const bcmg_problem *P, int top, LdsProg *lp) {
         q[a2].gcode = take(4 * V.ng);
         q[a2].gtau = take(24 * V.ng);
         q[a2].gdtau = take(8 * V.ng);
+        q[a2].gnd = P->opt.bc == BCMG_BC_NEUMANN ? take(24 * V.ng) : -1;
         q[a2].ilist = take(4 * V.ni);
         q[a2].bneed = take(4 * V.nbn);
     }
@@ -1210,6 +1222,9 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     const int nfgch = (int)(items.size() - fgch0);
     std::vector<int> coarse;
     b->fine_inside = 0;
+    b->neu = 0;
+    for (int s = 0; s < b->cap; s++)
+        if (b->prob[s] && b->prob[s]->opt.bc == BCMG_BC_NEUMANN) b->neu = 1;
     for (int s = 0; s < b->cap; s++)
         if (b->prob[s]) {
             coarse.push_back(base[s] + b->prob[s]->L - 1);
@@ -1394,7 +1409,7 @@ static void smooth(bcmg_batch *b, int a, const Item *ext = nullptr, int next = 0
     timed_sweep(b, a, 0, first);
     timed_sweep(b, a, 1);
     const Lists &L = b->lv[a];
-    launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream, ext, next);
+    launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream, ext, next, b->neu);
 }
 
 // one V(nu1, nu2) cycle over every slot, levels aligned at the coarsest grid.
@@ -1409,15 +1424,17 @@ static void launch_vcycle(bcmg_batch *b) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
         for (int i = 0; i < b->nu1; i++) smooth(b, a, nullptr, 0, i == 0);
-        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s);
+        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu);
         // a coarse level cycled by launches gets its first red half-sweep here
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
                         b->nu1 > 0 && a - 1 > b->Ac);
     }
     if (b->lds_bytes)
-        launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s);
+        launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s,
+                          b->neu);
     else
-        launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s);
+        launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s,
+                            b->neu);
     for (int a = b->Ac + 1; a < b->A; a++) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
@@ -1435,7 +1452,7 @@ static void launch_vcycle(bcmg_batch *b) {
 // correction cycle) plus per-slot norm and convergence bookkeeping
 static void launch_outer_residual(bcmg_batch *b, int mode) {
     launch_residual(b->d, 0, b->fp32, 1, b->d_outer, b->fsegs, b->nfseg, b->fgch, b->nfgch, b->d_state, b->d_partials,
-                    b->stream);
+                    b->stream, b->neu);
     launch_norm_finish(b->d_ranges, b->cap, b->d_partials, b->nfseg, b->d_state, b->d_rtol2, b->d_hist,
                        b->hist_stride, mode, nullptr, b->stream);
 }
@@ -1743,7 +1760,8 @@ bcmg_status bcmg_residual_norm(bcmg_problem *P, const double *u, double *norm_ho
     bcmg_status st;
     if ((st = upload_step_descs(P, 0, 1, pu, pr, px))) return st;
     launch_residual(P->d, 0, 0, 1, P->d_step, P->d_stepitems + P->off_seg[0], P->n_seg[0],
-                    P->d_stepitems + P->off_gch[0], P->n_gch[0], P->d_stepst, P->d_partials, P->stream);
+                    P->d_stepitems + P->off_gch[0], P->n_gch[0], P->d_stepst, P->d_partials, P->stream,
+                    P->opt.bc == BCMG_BC_NEUMANN);
     NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};
     HIPCHK(hipMemcpyAsync(P->d_range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
     launch_norm_finish(P->d_range, 1, P->d_partials, P->n_seg[0], P->d_stepst, nullptr, nullptr, 0, 2, P->d_out,

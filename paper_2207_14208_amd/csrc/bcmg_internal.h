@@ -73,6 +73,9 @@ struct alignas(16) Desc {
     const int *cmap;          // [nc] node index of each unknown
     int slot;                 // problem slot (state / flags index)
     int restrict_mode;
+    const double *gnd;        // [3*ng] Neumann rows: coefficient of d/dt_k (t_k local, growing along -s_k);
+                              //   null: Dirichlet rows
+    double reaction;          // c of the interior row c u - Laplace u
 };
 
 // Per-slot solve state kept on the device.
@@ -112,6 +115,7 @@ struct LdsLevel {
     int ilist;                             // INSIDE nodes by colour
     int bneed;                             // needed band entries
     int gidx, gcode, gtau, gdtau, gnew;    // ghost records
+    int gnd;                               // Neumann derivative coefficients (< 0: Dirichlet rows)
 };
 
 // The aligned levels 0..top of one problem cycled in LDS by k_coarse_lds.

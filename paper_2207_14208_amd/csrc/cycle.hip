@@ -29,15 +29,27 @@ __device__ __forceinline__ double lagrange(int w, int m, double t) {
     return t * (t - 1.0) / 2.0;
 }
 
-// sum_m w_m u(G - m o s) of ghost g (eq. BCh, Dirichlet), tensor-product
-// Lagrange weights of widths w_k at the local coordinates tau_k of Q.  The
-// 3^d candidate nodes are loaded first (nodes outside the stencil read G
-// itself), then accumulated in lexicographic order of m.
+__device__ __forceinline__ double lagrange_dt(int w, int m, double t) {  // d/dt of lagrange
+    if (w == 1) return 0.0;
+    if (w == 2) return m == 0 ? -1.0 : 1.0;
+    if (m == 0) return t - 1.5;
+    if (m == 1) return 2.0 - 2.0 * t;
+    return t - 0.5;
+}
+
 // Left side of ghost row g, sum_m w_m u(G - m o s) (eq. BCh), from the
 // ghost's code (widths, signs) and local coordinates tau; PI/PD/PU are
-// pointers into global memory or LDS.
-template <int D, typename PI, typename PD, typename PU>
-__device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, long long sy, long long sz, int g, PU u) {
+// pointers into global memory or LDS.  Dirichlet rows: the tensor-product
+// Lagrange weights prod_k L_{m_k}(tau_k) of widths w_k.  Neumann rows (only
+// compiled with NEU, taken where neu): the normal derivative of that
+// interpolant, sum_k nd_k L'_{m_k}(tau_k) prod_{j != k} L_{m_j}(tau_j), with
+// the ghost's derivative coefficients nd = gnd[3g..3g+2].  The 3^d candidate
+// nodes are loaded first (nodes outside the stencil read G itself), then
+// accumulated in lexicographic order of m.  Kernels without NEU keep the
+// register footprint of the Dirichlet row.
+template <int D, bool NEU, typename PI, typename PD, typename PU>
+__device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, PD gnd, bool neu, long long sy, long long sz,
+                                               int g, PU u) {
     const long long p = gidx[g];
     const int code = gcode[g];
     int w[3];
@@ -65,6 +77,32 @@ __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, long 
                 val[m2][m1][m0] = (double)u[q];
             }
     double acc = 0.0;
+    if constexpr (NEU) {
+        if (neu) {
+            double da[3][3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double t = k < D ? gtau[3 * g + k] : 0.0;
+                const double nd = k < D ? gnd[3 * g + k] : 0.0;
+#pragma unroll
+                for (int m = 0; m < 3; m++) da[k][m] = nd * lagrange_dt(w[k], m, t);
+            }
+#pragma unroll
+            for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+                for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+                    for (int m0 = 0; m0 < 3; m0++) {
+                        if (!(m0 < w[0] && m1 < w[1] && m2 < w[2])) continue;
+                        double wgt = 0.0;
+                        wgt += da[0][m0] * la[1][m1] * la[2][m2];
+                        wgt += da[1][m1] * la[0][m0] * la[2][m2];
+                        wgt += da[2][m2] * la[0][m0] * la[1][m1];
+                        acc += wgt * val[m2][m1][m0];
+                    }
+            return acc;
+        }
+    }
 #pragma unroll
     for (int m2 = 0; m2 < M2; m2++)
 #pragma unroll
@@ -81,9 +119,10 @@ __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, long 
     return acc;
 }
 
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restrict__ u) {
-    return ghost_row_at<D>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, L.sy, L.sz, g, u);
+    return ghost_row_at<D, NEU>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, (gcp<double>)L.gnd,
+                                L.gnd != nullptr, L.sy, L.sz, g, u);
 }
 
 // ------------------------------------------------------------ node updates
@@ -123,7 +162,8 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
         double sum = xp + xm;
         if (D >= 2) sum += yp + ym;
         if (D >= 3) sum += zp + zm;
-        const double lap = (2.0 * D * up - sum) / L.h2;
+        double lap = (2.0 * D * up - sum) / L.h2;
+        if (L.reaction != 0.0) lap += L.reaction * up;  // c u - Laplace u
         rv[h] = fp - lap;
     }
 #pragma unroll
@@ -221,7 +261,7 @@ __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long
     uv = (T)0;
     if (red && (((X0 + X1 + X2) >> 1) & 1) == 0) {
         const T sum = (T)0;
-        uv = ((T)C.h2 * fv + sum) / (T)(2 * D);
+        uv = ((T)C.h2 * fv + sum) / (T)(2.0 * D + C.reaction * C.h2);
     }
 }
 
@@ -436,14 +476,14 @@ __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const 
 
 // Ghost relaxation (eq. rel with P_GG = I/dtau: new interior values, old ghost
 // values): increment, then u_G += increment in a second pass.
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __device__ __forceinline__ void ghost_delta(const Desc &L, int g, bool live) {
     gcp<T> u = (gcp<T>)L.u;
     gcp<T> rhs = (gcp<T>)L.rhs;
     const long long p = ((gcp<int>)L.gidx)[g];
     const double rg = (double)rhs[p];
     const double up = (double)u[p];
-    const double row = ghost_row<D, T>(L, g, u);
+    const double row = ghost_row<D, T, NEU>(L, g, u);
     const double v = (double)(T)(up + ((gcp<double>)L.gdtau)[g] * (rg - row));
     pin(v);
     if (!live) return;
@@ -459,11 +499,11 @@ __device__ __forceinline__ void ghost_apply(const Desc &L, int g, bool live) {
     ((gp<T>)L.u)[p] = v;
 }
 
-template <int D, typename Tu, typename Tr>
+template <int D, typename Tu, typename Tr, bool NEU>
 __device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live) {
     const long long pg = ((gcp<int>)L.gidx)[g];
     const double rg = (double)((gcp<Tu>)L.rhs)[pg];
-    const double r = rg - ghost_row<D, Tu>(L, g, (gcp<Tu>)L.u);
+    const double r = rg - ghost_row<D, Tu, NEU>(L, g, (gcp<Tu>)L.u);
     pin(r);
     if (!live) return 0.0;
     ((gp<Tr>)L.r)[pg] = (Tr)r;
@@ -552,12 +592,12 @@ __device__ __forceinline__ int xcd_block_second_first(int nfirst) {
     if ((int)threadIdx.x >= it.z) return;                         \
     const int e = it.y + threadIdx.x;
 
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__ descs,
                                                         const Item *__restrict__ items,
                                                         const SlotState *__restrict__ st) {
     CHUNK_ITEM
-    ghost_delta<D, T>(L, e, live);
+    ghost_delta<D, T, NEU>(L, e, live);
 }
 
 // Ghost step, second half: the new ghost values into u (chunk blocks), and,
@@ -592,7 +632,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Residual on INSIDE rows (segment blocks) and GHOST rows (chunk blocks);
 // with NORM, one partial sum of r^2 per segment, then one per ghost chunk,
 // each reduced in a fixed order.
-template <int D, typename Tu, typename Tr, bool NORM>
+template <int D, typename Tu, typename Tr, bool NORM, bool NEU>
 __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
                                                      const SlotState *__restrict__ st, double *__restrict__ partials) {
@@ -611,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     const Desc &L = descs[it.x];
     const bool live = st[L.slot].active != 0;
     double r2 = 0.0;
-    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr>(L, it.y + threadIdx.x, live);
+    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr, NEU>(L, it.y + threadIdx.x, live);
     if (NORM) {
         __shared__ double ws[kWavesPerBlock];
         r2 = wave_sum(r2);
@@ -799,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(const Desc *__restrict__ d
 constexpr int kCoarseThreads = 512;
 constexpr int kCoarseWaves = kCoarseThreads / 64;
 
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __device__ void blk_smooth(const Desc *descs, const Item *items, const CoarseLevel &lv) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int colour = 0; colour < 2; colour++) {
@@ -812,7 +852,7 @@ __device__ void blk_smooth(const Desc *descs, const Item *items, const CoarseLev
     const int grp = threadIdx.x / kChunk, t = threadIdx.x % kChunk, ngrp = kCoarseThreads / kChunk;
     for (int c = grp; c < lv.ngch; c += ngrp) {
         const Item it = items[lv.gch + c];
-        if (t < it.z) ghost_delta<D, T>(descs[it.x], it.y + t, true);
+        if (t < it.z) ghost_delta<D, T, NEU>(descs[it.x], it.y + t, true);
     }
     __syncthreads();
     for (int c = grp; c < lv.ngch; c += ngrp) {
@@ -833,7 +873,7 @@ __device__ void blk_extend(const Desc *descs, const Item *items, const CoarseLev
     __syncthreads();
 }
 
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__restrict__ descs,
                                                                  const Item *__restrict__ items,
                                                                  const CoarseProg *__restrict__ progs,
@@ -846,14 +886,14 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
     __shared__ double b[kCoarseMax];
     for (int a = P.top; a >= 1; a--) {
         const CoarseLevel &lv = P.lev[a];
-        for (int i = 0; i < nu1; i++) blk_smooth<D, T>(descs, items, lv);
+        for (int i = 0; i < nu1; i++) blk_smooth<D, T, NEU>(descs, items, lv);
         for (int s = wave; s < lv.nseg; s += kCoarseWaves) {
             const Item it = items[lv.seg + s];
             seg_residual<D, T, T>(descs[it.x], it, lane, true);
         }
         for (int c = grp; c < lv.ngch; c += ngrp) {
             const Item it = items[lv.gch + c];
-            if (t < it.z) ghost_residual<D, T, T>(descs[it.x], it.y + t, true);
+            if (t < it.z) ghost_residual<D, T, T, NEU>(descs[it.x], it.y + t, true);
         }
         __syncthreads();
         const CoarseLevel &cv = P.lev[a - 1];
@@ -873,7 +913,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
         if (L.nc > 0 && !L.singular) {
             coarse_solve_block<T>(L, b);
         } else if (L.nc > 0) {
-            for (int i = 0; i < 50; i++) blk_smooth<D, T>(descs, items, lv);
+            for (int i = 0; i < 50; i++) blk_smooth<D, T, NEU>(descs, items, lv);
         }
     }
     for (int a = 1; a <= P.top; a++) {
@@ -884,7 +924,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(const Desc *__r
             seg_prolong<D, T>(descs[it.x], descs[it.x + 1], it, lane, true);
         }
         __syncthreads();
-        for (int i = 0; i < nu2; i++) blk_smooth<D, T>(descs, items, lv);
+        for (int i = 0; i < nu2; i++) blk_smooth<D, T, NEU>(descs, items, lv);
     }
     // the error of the top level, extended for the prolongation that follows
     if (P.ext_top) blk_extend<T>(descs, items, P.lev[P.top]);
@@ -910,7 +950,9 @@ struct LdsView {
     gp<T> rg;  // the residual in HBM instead of r (null when r is in LDS)
     lp<int> gidx, gcode, ilist, bneed;
     int nbn;
-    lp<double> gtau, gdtau, gnew;
+    lp<double> gtau, gdtau, gnew, gnd;
+    bool neu;         // Neumann ghost rows (gnd valid)
+    double reaction;  // c of c u - Laplace u
     gcp<int> eptr, eidx, bidx, rptr, ridx;  // rows in HBM
     gcp<double> ecoef, rcoef;
 };
@@ -932,8 +974,8 @@ __device__ __forceinline__ void node_coords(int p, int n, int &i, int &j, int &k
     k = D >= 3 ? p / (n * n) : 0;
 }
 
-template <int D, typename T>
-__device__ void lds_smooth(const LdsView<T> &L) {
+template <int D, typename T, bool NEU>
+__device__ __forceinline__ void lds_smooth(const LdsView<T> &L) {
     for (int colour = 0; colour < 2; colour++) {
         const int beg = colour ? L.nred : 0, end = colour ? L.ni : L.nred;
         for (int t = beg + (int)threadIdx.x; t < end; t += kCoarseThreads) {
@@ -941,13 +983,13 @@ __device__ void lds_smooth(const LdsView<T> &L) {
             T sum = L.u[p + 1] + L.u[p - 1];
             if (D >= 2) sum += L.u[p + L.sy] + L.u[p - L.sy];
             if (D >= 3) sum += L.u[p + L.sz] + L.u[p - L.sz];
-            L.u[p] = ((T)L.h2 * L.rhs[p] + sum) / (T)(2 * D);
+            L.u[p] = ((T)L.h2 * L.rhs[p] + sum) / (T)(2.0 * D + L.reaction * L.h2);
         }
         __syncthreads();
     }
     for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) {
         const int p = L.gidx[g];
-        const double row = ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u);
+        const double row = ghost_row_at<D, NEU>(L.gidx, L.gcode, L.gtau, L.gnd, L.neu, L.sy, L.sz, g, L.u);
         L.gnew[g] = (double)(T)((double)L.u[p] + L.gdtau[g] * ((double)L.rhs[p] - row));
     }
     __syncthreads();
@@ -955,14 +997,15 @@ __device__ void lds_smooth(const LdsView<T> &L) {
     __syncthreads();
 }
 
-template <int D, typename T>
-__device__ void lds_residual(const LdsView<T> &L) {
+template <int D, typename T, bool NEU>
+__device__ __forceinline__ void lds_residual(const LdsView<T> &L) {
     for (int t = threadIdx.x; t < L.ni; t += kCoarseThreads) {
         const int p = L.ilist[t];
         double sum = (double)L.u[p + 1] + (double)L.u[p - 1];
         if (D >= 2) sum += (double)L.u[p + L.sy] + (double)L.u[p - L.sy];
         if (D >= 3) sum += (double)L.u[p + L.sz] + (double)L.u[p - L.sz];
-        const double lap = (2.0 * D * (double)L.u[p] - sum) / L.h2;
+        double lap = (2.0 * D * (double)L.u[p] - sum) / L.h2;
+        if (L.reaction != 0.0) lap += L.reaction * (double)L.u[p];
         const T v = (T)((double)L.rhs[p] - lap);
         if (L.rg)
             L.rg[p] = v;
@@ -971,7 +1014,7 @@ __device__ void lds_residual(const LdsView<T> &L) {
     }
     for (int g = threadIdx.x; g < L.ng; g += kCoarseThreads) {
         const int p = L.gidx[g];
-        const T v = (T)((double)L.rhs[p] - ghost_row_at<D>(L.gidx, L.gcode, L.gtau, L.sy, L.sz, g, L.u));
+        const T v = (T)((double)L.rhs[p] - ghost_row_at<D, NEU>(L.gidx, L.gcode, L.gtau, L.gnd, L.neu, L.sy, L.sz, g, L.u));
         if (L.rg)
             L.rg[p] = v;
         else
@@ -983,7 +1026,7 @@ __device__ void lds_residual(const LdsView<T> &L) {
 
 // coarse level C from the residual of the finer level F
 template <int D, typename T>
-__device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode) {
+__device__ __forceinline__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode) {
     for (int t = threadIdx.x; t < C.ni; t += kCoarseThreads) {
         const int p = C.ilist[t];
         int i, j, k;
@@ -1008,7 +1051,7 @@ __device__ void lds_restrict(const LdsView<T> &C, const LdsView<T> &F, int mode)
 }
 
 template <typename T>
-__device__ void lds_extend(const LdsView<T> &L) {
+__device__ __forceinline__ void lds_extend(const LdsView<T> &L) {
     for (int t = threadIdx.x; t < L.nbn * kRowLanes; t += kCoarseThreads) {  // by lane groups
         const int b = L.bneed[t / kRowLanes];
         const double v = row_dot_group(L.eidx, L.ecoef, L.eptr[b], L.eptr[b + 1], t % kRowLanes,
@@ -1019,7 +1062,7 @@ __device__ void lds_extend(const LdsView<T> &L) {
 }
 
 template <int D, typename T>
-__device__ void lds_prolong(const LdsView<T> &F, const LdsView<T> &C) {
+__device__ __forceinline__ void lds_prolong(const LdsView<T> &F, const LdsView<T> &C) {
     for (int t = threadIdx.x; t < F.ni + F.ng; t += kCoarseThreads) {
         const int p = t < F.ni ? F.ilist[t] : F.gidx[t - F.ni];
         int i, j, k;
@@ -1063,12 +1106,13 @@ __global__ __launch_bounds__(kBlock) void k_lds_images(const Desc *__restrict__ 
         put(G.gcode, Q.gcode, 4LL * Q.ng);
         put(G.gtau, Q.gtau, 24LL * Q.ng);
         put(G.gdtau, Q.gdtau, 8LL * Q.ng);
+        if (Q.gnd >= 0) put(G.gnd, Q.gnd, 24LL * Q.ng);
         put(G.ilist, Q.ilist, 4LL * Q.ni);
         put(G.bneed, Q.bneed, 4LL * Q.nbn);
     }
 }
 
-template <int D, typename T>
+template <int D, typename T, bool NEU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__restrict__ descs,
                                                                const LdsProg *__restrict__ progs,
                                                                const SlotState *__restrict__ st, int nu1, int nu2) {
@@ -1114,6 +1158,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
         W.gtau = lds_ptr<double>(lds, Q.gtau);
         W.gdtau = lds_ptr<double>(lds, Q.gdtau);
         W.gnew = lds_ptr<double>(lds, Q.gnew);
+        W.neu = Q.gnd >= 0;
+        W.gnd = lds_ptr<double>(lds, Q.gnd < 0 ? 0 : Q.gnd);
+        W.reaction = G.reaction;
         W.eptr = (gcp<int>)G.eptr;
         W.eidx = (gcp<int>)G.eidx;
         W.ecoef = (gcp<double>)G.ecoef;
@@ -1157,8 +1204,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
     __syncthreads();
     const int mode = descs[P.lev[0].desc].restrict_mode;
     for (int a = top; a >= 1; a--) {
-        for (int i = 0; i < nu1; i++) lds_smooth<D, T>(V[a]);
-        lds_residual<D, T>(V[a]);
+        for (int i = 0; i < nu1; i++) lds_smooth<D, T, NEU>(V[a]);
+        lds_residual<D, T, NEU>(V[a]);
         lds_restrict<D, T>(V[a - 1], V[a], mode);
     }
     {
@@ -1183,13 +1230,13 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_lds(const Desc *__res
             }
             __syncthreads();
         } else if (G.nc > 0) {
-            for (int i = 0; i < 50; i++) lds_smooth<D, T>(V[0]);
+            for (int i = 0; i < 50; i++) lds_smooth<D, T, NEU>(V[0]);
         }
     }
     for (int a = 1; a <= top; a++) {
         lds_extend<T>(V[a - 1]);
         lds_prolong<D, T>(V[a], V[a - 1]);
-        for (int i = 0; i < nu2; i++) lds_smooth<D, T>(V[a]);
+        for (int i = 0; i < nu2; i++) lds_smooth<D, T, NEU>(V[a]);
     }
     if (P.ext_top) lds_extend<T>(V[top]);
     const LdsView<T> &W = V[top];
@@ -1211,6 +1258,23 @@ static inline int blocks_for_segs(int nseg) { return (nseg + kWavesPerBlock - 1)
         if ((d) == 3) hipLaunchKernelGGL((KERNEL<3, T>), __VA_ARGS__);         \
     } while (0)
 
+#define DISPATCH_DB(d, KERNEL, T, B, ...)                                      \
+    do {                                                                       \
+        if ((d) == 1) hipLaunchKernelGGL((KERNEL<1, T, B>), __VA_ARGS__);      \
+        if ((d) == 2) hipLaunchKernelGGL((KERNEL<2, T, B>), __VA_ARGS__);      \
+        if ((d) == 3) hipLaunchKernelGGL((KERNEL<3, T, B>), __VA_ARGS__);      \
+    } while (0)
+
+// kernels with the Neumann ghost rows compiled in (neu: some problem of the
+// launch has them) or not
+#define DISPATCH_DN(d, neu, KERNEL, T, ...)                                    \
+    do {                                                                       \
+        if (neu)                                                               \
+            DISPATCH_DB(d, KERNEL, T, true, __VA_ARGS__);                      \
+        else                                                                   \
+            DISPATCH_DB(d, KERNEL, T, false, __VA_ARGS__);                     \
+    } while (0)
+
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s) {
     if (nseg <= 0) return;
@@ -1222,44 +1286,56 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
 }
 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
-                        hipStream_t s, const Item *bch, int nbch) {
+                        hipStream_t s, const Item *bch, int nbch, int neu) {
     if (ngch <= 0 && nbch <= 0) return;
     dim3 g(ngch), ga(ngch + nbch * kRowLanes), b(kBlock);
     if (fp32) {
-        if (ngch > 0) DISPATCH_D(d, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
         hipLaunchKernelGGL((k_ghost_apply<float>), ga, b, 0, s, descs, gch, ngch, bch, st);
     } else {
-        if (ngch > 0) DISPATCH_D(d, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
         hipLaunchKernelGGL((k_ghost_apply<double>), ga, b, 0, s, descs, gch, ngch, bch, st);
     }
 }
 
-template <typename Tu, typename Tr, bool NORM>
+template <typename Tu, typename Tr, bool NORM, bool NEU>
 static void residual_t(int d, const Desc *descs, const Item *segs, int nseg, const Item *gch, int ngch,
                        const SlotState *st, double *partials, hipStream_t s) {
     const int sb = blocks_for_segs(nseg);
     if (sb + ngch <= 0) return;
     dim3 g(sb + ngch), b(kBlock);
-    if (d == 1) hipLaunchKernelGGL((k_residual<1, Tu, Tr, NORM>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
-    if (d == 2) hipLaunchKernelGGL((k_residual<2, Tu, Tr, NORM>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
-    if (d == 3) hipLaunchKernelGGL((k_residual<3, Tu, Tr, NORM>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+    if (d == 1)
+        hipLaunchKernelGGL((k_residual<1, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+    if (d == 2)
+        hipLaunchKernelGGL((k_residual<2, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+    if (d == 3)
+        hipLaunchKernelGGL((k_residual<3, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+}
+
+template <bool NEU>
+static void residual_n(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
+                       const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s) {
+    if (!tu32 && !tr32) {
+        if (norm)
+            residual_t<double, double, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+        else
+            residual_t<double, double, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+    } else if (!tu32 && tr32) {
+        if (norm)
+            residual_t<double, float, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+        else
+            residual_t<double, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+    } else {
+        residual_t<float, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+    }
 }
 
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
-                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s) {
-    if (!tu32 && !tr32) {
-        if (norm)
-            residual_t<double, double, true>(d, descs, segs, nseg, gch, ngch, st, partials, s);
-        else
-            residual_t<double, double, false>(d, descs, segs, nseg, gch, ngch, st, partials, s);
-    } else if (!tu32 && tr32) {
-        if (norm)
-            residual_t<double, float, true>(d, descs, segs, nseg, gch, ngch, st, partials, s);
-        else
-            residual_t<double, float, false>(d, descs, segs, nseg, gch, ngch, st, partials, s);
-    } else {
-        residual_t<float, float, false>(d, descs, segs, nseg, gch, ngch, st, partials, s);
-    }
+                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu) {
+    if (neu)
+        residual_n<true>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s);
+    else
+        residual_n<false>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s);
 }
 
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
@@ -1309,13 +1385,13 @@ void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const Sl
 }
 
 void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
-                         const SlotState *st, int nu1, int nu2, hipStream_t s) {
+                         const SlotState *st, int nu1, int nu2, hipStream_t s, int neu) {
     if (nprog <= 0) return;
     dim3 g(nprog), b(kCoarseThreads);
     if (fp32)
-        DISPATCH_D(d, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2);
+        DISPATCH_DN(d, neu, k_coarse_cycle, float, g, b, 0, s, descs, items, progs, st, nu1, nu2);
     else
-        DISPATCH_D(d, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2);
+        DISPATCH_DN(d, neu, k_coarse_cycle, double, g, b, 0, s, descs, items, progs, st, nu1, nu2);
 }
 
 void launch_lds_images(const Desc *descs, const LdsProg *progs, int nprog, hipStream_t s) {
@@ -1324,13 +1400,13 @@ void launch_lds_images(const Desc *descs, const LdsProg *progs, int nprog, hipSt
 }
 
 void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,
-                       const SlotState *st, int nu1, int nu2, hipStream_t s) {
+                       const SlotState *st, int nu1, int nu2, hipStream_t s, int neu) {
     if (nprog <= 0) return;
     dim3 g(nprog), b(kCoarseThreads);
     if (fp32)
-        DISPATCH_D(d, k_coarse_lds, float, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
+        DISPATCH_DN(d, neu, k_coarse_lds, float, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
     else
-        DISPATCH_D(d, k_coarse_lds, double, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
+        DISPATCH_DN(d, neu, k_coarse_lds, double, g, b, lds_bytes, s, descs, progs, st, nu1, nu2);
 }
 
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,

@@ -10,11 +10,13 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
                      const SlotState *st, hipStream_t s);
 // Jacobi ghost step (new values into gnew, then applied); with bch, the
 // applying launch also extends the new field into the band chunks bch.
+// neu: some problem of the launch has Neumann ghost rows (selects the kernels
+// that carry them; the others keep the Dirichlet row's registers)
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
-                        hipStream_t s, const Item *bch = nullptr, int nbch = 0);
+                        hipStream_t s, const Item *bch = nullptr, int nbch = 0, int neu = 0);
 // tu32/tr32: element types of (u, rhs) and r; norm: write partial sums of r^2
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
-                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s);
+                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu = 0);
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s);
 // extension of u into the band chunks bch (ghost values read from u)
@@ -31,10 +33,10 @@ void launch_prolong(int d, int fp32, const Desc *descs, const Item *fsegs, int n
 void launch_coarse(int fp32, const Desc *descs, const int *list, int n, const SlotState *st, hipStream_t s);
 // one workgroup per program: the V-cycle on the program's coarse levels
 void launch_coarse_cycle(int d, int fp32, const Desc *descs, const Item *items, const CoarseProg *progs, int nprog,
-                         const SlotState *st, int nu1, int nu2, hipStream_t s);
+                         const SlotState *st, int nu1, int nu2, hipStream_t s, int neu = 0);
 // the same on the levels staged in LDS (lds_bytes of dynamic LDS per workgroup)
 void launch_coarse_lds(int d, int fp32, const Desc *descs, const LdsProg *progs, int nprog, size_t lds_bytes,
-                       const SlotState *st, int nu1, int nu2, hipStream_t s);
+                       const SlotState *st, int nu1, int nu2, hipStream_t s, int neu = 0);
 // fill the programs' images (their levels' arrays fixed during a solve, at their LDS offsets)
 void launch_lds_images(const Desc *descs, const LdsProg *progs, int nprog, hipStream_t s);
 void launch_ir_update(const Desc *descs, const Item *segs, int nseg, const SlotState *st, float *const *eptr,
@@ -51,8 +53,8 @@ int compact_blocks(long long nn);
 void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
                     int *total_dev, hipStream_t s);
 void launch_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls, const int *gidx,
-                           int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
-                           double *geta, double *gn, double *gq, int *gfb, hipStream_t s);
+                           int ng, int dtau_mode, double dtau_const, int bc, int *gcode, double *gtau, double *gdtau,
+                           double *geta, double *gn, double *gq, int *gfb, double *gnd, hipStream_t s);
 void launch_band_mark(int d, int N, const uint8_t *cls, const int *gidx, int ng, int K, uint8_t *mark,
                       hipStream_t s);
 void launch_band_records(int d, int N, double h, const double *phi, const uint8_t *cls, const int *bidx, int nb,
@@ -69,7 +71,8 @@ void launch_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c,
 void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag, hipStream_t s);
 void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s);
 void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
-                         const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s);
+                         const double *gtau, int bc, const double *gnd, double reaction, double *work, double *ainv,
+                         int *cmap, int *info, hipStream_t s);
 void launch_set_rhs(long long nn, const uint8_t *cls, const double *f, double *rhs, hipStream_t s);
 void launch_scatter_ghosts(const int *gidx, int ng, const double *gq, double *rhs, hipStream_t s);
 void launch_fill_boundary(long long nn, const uint8_t *cls, const double *gbox, double *u, hipStream_t s);

@@ -9,7 +9,8 @@ namespace bcmg {
 // ------------------------------------------------------------ node updates
 // Interior Gauss-Seidel on the nodes of one colour of a segment (red:
 // i+j+k even), one node per lane.  eq. GSLEX_2D in red-black order:
-// u_P = (h^2 f_P + sum of the 2d neighbours) / (2d).
+// u_P = (h^2 f_P + sum of the 2d neighbours) / (2d + c h^2), c the reaction
+// coefficient of c u - Laplace u (0 for Poisson).
 template <int D, typename T>
 __device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, int colour, bool live) {
     const Seg s = seg_of(it);
@@ -33,7 +34,7 @@ __device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, 
     T sum = xp + xm;
     if (D >= 2) sum += yp + ym;
     if (D >= 3) sum += zp + zm;
-    const T v = ((T)L.h2 * fp + sum) / (T)(2 * D);
+    const T v = ((T)L.h2 * fp + sum) / (T)(2.0 * D + L.reaction * L.h2);
     pin(v);
     pin(c);
     if (q >= s.len || c != C_INSIDE || !live) return;

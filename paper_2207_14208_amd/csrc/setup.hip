@@ -232,6 +232,33 @@ __device__ __forceinline__ double lag(int w, int m, double t) {
     return t * (t - 1.0) / 2.0;
 }
 
+__device__ __forceinline__ double lag_dt(int w, int m, double t) {  // d/dt of lag
+    if (w == 1) return 0.0;
+    if (w == 2) return m == 0 ? -1.0 : 1.0;
+    if (m == 0) return t - 1.5;
+    if (m == 1) return 2.0 - 2.0 * t;
+    return t - 0.5;
+}
+
+// Weight of block node m in a ghost row (eq. BCh): Dirichlet prod_k L_{m_k}(tau_k);
+// Neumann sum_k nd_k L'_{m_k}(tau_k) prod_{j != k} L_{m_j}(tau_j), the normal
+// derivative of the tensor-product interpolant (nd_k = -s_k n_k / h).
+__device__ double row_weight(int bc, const int w[3], const double tau[3], const double nd[3], const int m[3]) {
+    if (bc == BCMG_BC_DIRICHLET) {
+        double wgt = 1.0;
+        for (int k = 0; k < 3; k++) wgt *= lag(w[k], m[k], tau[k]);
+        return wgt;
+    }
+    double acc = 0.0;
+    for (int k = 0; k < 3; k++) {
+        double term = nd[k] * lag_dt(w[k], m[k], tau[k]);
+        for (int j = 0; j < 3; j++)
+            if (j != k) term *= lag(w[j], m[j], tau[j]);
+        acc += term;
+    }
+    return acc;
+}
+
 // tensor-product quadratic interpolant of phi on {I - m o s : m_k < 3}, from
 // the node values pv[m2][m1][m0] = phi(I - m o s), loaded once
 __device__ double phi_tilde_vals(const double pv[3][3][3], int d, const double t[3]) {
@@ -249,37 +276,38 @@ __device__ double phi_tilde_vals(const double pv[3][3][3], int d, const double t
     return val;
 }
 
-__device__ bool block_valid(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3]) {
+// block in the box and made of INSIDE/GHOST nodes (Neumann rows also take
+// BOXDIR nodes, whose values g_B are known)
+__device__ bool block_valid(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3], int bc) {
     for (int m2 = 0; m2 < w[2]; m2++)
         for (int m1 = 0; m1 < w[1]; m1++)
             for (int m0 = 0; m0 < w[0]; m0++) {
                 const int J[3] = {I[0] - m0 * s[0], I[1] - m1 * s[1], I[2] - m2 * s[2]};
                 if (!in_box(J, n - 1, d)) return false;
                 const uint8_t c = cls[index_of(J, n, d)];
+                if (c == C_BOXDIR && bc == BCMG_BC_NEUMANN) continue;
                 if (c != C_INSIDE && c != C_GHOST) return false;
             }
     return true;
 }
 
-// c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block)
+// c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block); a
+// Neumann row also needs c_0 > 0
 __device__ bool block_dominant(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3],
-                               const double tau[3], double f) {
-    double c0 = 1.0, off = 0.0;
+                               const double tau[3], const double nd[3], int bc, double f) {
+    double c0 = 0.0, off = 0.0;
     for (int m2 = 0; m2 < w[2]; m2++)
         for (int m1 = 0; m1 < w[1]; m1++)
             for (int m0 = 0; m0 < w[0]; m0++) {
                 const int m[3] = {m0, m1, m2};
-                int J[3];
-                double wgt = 1.0;
-                for (int k = 0; k < 3; k++) {
-                    J[k] = I[k] - m[k] * s[k];
-                    wgt *= lag(w[k], m[k], tau[k]);
-                }
+                const int J[3] = {I[0] - m0 * s[0], I[1] - m1 * s[1], I[2] - m2 * s[2]};
+                const double wgt = row_weight(bc, w, tau, nd, m);
                 if (m0 == 0 && m1 == 0 && m2 == 0)
                     c0 = wgt;
                 else if (cls[index_of(J, n, d)] == C_GHOST)
                     off += fabs(wgt);
             }
+    if (bc == BCMG_BC_NEUMANN && !(c0 > 0.0)) return false;
     return c0 >= f * off;
 }
 
@@ -304,16 +332,74 @@ __device__ double dtau_of(int d, double theta, int mode, double cnst) {
     return 2.0 / (gmin + gmax);
 }
 
+// First INSIDE axis neighbour of node p in the order -x, +x, -y, +y, -z, +z:
+// returns its axis (or -1) and sets side = +1 when it is p - e_k, -1 when it
+// is p + e_k.  Written as one straight pass with a single exit per outcome:
+// an if / else-if pair assigning the axis in both branches was compiled for
+// gfx950 so that the else-if branch kept the old axis.
+__device__ int first_inside_neighbour(const uint8_t *cls, long long p, const int I[3], int N, int n, int d,
+                                      int &side) {
+    int axis = -1, sd = 0;
+    long long str = 1;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const bool lo = k < d && axis < 0 && I[k] > 0 && cls[p - str] == C_INSIDE;
+        const bool hi = k < d && axis < 0 && !lo && I[k] < N && cls[p + str] == C_INSIDE;
+        sd = lo ? 1 : (hi ? -1 : sd);
+        axis = (lo || hi) ? k : axis;
+        str *= n;
+    }
+    side = sd;
+    return axis;
+}
+
+// dtau / h of a Neumann row (Prop. optN / opt3DN with eq. coeffN; the
+// exponential form G0 = p e^{-p t} of Remark exptheta2D over p in
+// [acosh 2, acosh(2d-1)], whose maximum lies at p = 1/t when that is inside;
+// 1D: HUGE_VAL, capped below at the row's Gauss-Seidel step)
+__device__ double dtau_neumann_of(int d, double theta, int mode, double cnst) {
+    if (mode == BCMG_DTAU_CONST) return cnst;
+    double t = theta < 1.0 ? theta : 1.0;
+    if (t < 0.0) t = 0.0;
+    if (d == 1) return HUGE_VAL;
+    const double plo = acosh(2.0), phi_ = acosh(2.0 * d - 1.0);
+    double gmin = INFINITY, gmax = -INFINITY;
+    for (int v = 0; v <= d; v++) {
+        double p;
+        if (v < d) {
+            p = v < d - 1 ? acosh(2.0 + v) : phi_;
+        } else {  // the interior maximum of p e^{-p t}
+            if (mode != BCMG_DTAU_OPT_EXP || !(t > 0.0)) break;
+            p = 1.0 / t;
+            if (!(p > plo && p < phi_)) break;
+        }
+        double g;
+        if (mode == BCMG_DTAU_OPT_EXP) {
+            g = p * exp(-p * t);
+        } else {
+            const double c0 = 1.5 - t, c1 = 2.0 * (t - 1.0), c2 = 0.5 - t;
+            g = fabs(c2 * exp(-2.0 * p) + c1 * exp(-p) + c0);
+        }
+        gmin = fmin(gmin, g);
+        gmax = fmax(gmax, g);
+    }
+    return 2.0 / (gmin + gmax);
+}
+
 // One ghost G: discrete normal, upwind signs, axis dominance, root eta in
 // [0,1] of phi~(G - eta h n) = 0 (bracket at 1, 60 bisections), first
 // admissible stencil widths (in the box, INSIDE/GHOST nodes only, row weight
 // on G at least f times its |weight| on the block's other ghosts: f = 1/2 on
 // the finest level, 1 on coarse levels), Q, tau and dtau(theta~ = eta)
 // bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 3.3 eqs. BCh, rel,
-// DtauOptTheta, Remark exptheta2D.
+// DtauOptTheta, Remark exptheta2D.  Neumann rows (bc): the derivative
+// coefficients gnd, blocks that may hold BOXDIR nodes, c_0 > 0, and with no
+// admissible block the difference (u_G - u_J)/h towards the first INSIDE axis
+// neighbour J (fb bit 1); dtau = h * dtau_neumann_of.
 __global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls,
-                                 const int *gidx, int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau,
-                                 double *gdtau, double *geta, double *gn, double *gq, int *gfb) {
+                                 const int *gidx, int ng, int dtau_mode, double dtau_const, int bc, int *gcode,
+                                 double *gtau, double *gdtau, double *geta, double *gn, double *gq, int *gfb,
+                                 double *gnd) {
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= ng) return;
     const int n = N + 1;
@@ -331,19 +417,10 @@ __global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level,
             nv[k] = g[k] / gnorm;
             key[k] = fabs(g[k]);
         }
-    } else {
-        bool found = false;
-        long long str = 1;
-        for (int k = 0; k < d && !found; k++) {
-            if (I[k] > 0 && cls[p - str] == C_INSIDE) {
-                nv[k] = 1.0;
-                found = true;
-            } else if (I[k] < N && cls[p + str] == C_INSIDE) {
-                nv[k] = -1.0;
-                found = true;
-            }
-            str *= n;
-        }
+    } else {  // unit vector from the first INSIDE axis neighbour to G
+        int side = 0;
+        const int ax = first_inside_neighbour(cls, p, I, N, n, d, side);
+        for (int k = 0; k < d; k++) nv[k] = k == ax ? (double)side : 0.0;
         for (int k = 0; k < d; k++) key[k] = fabs(nv[k]);
     }
     int s[3] = {1, 1, 1};
@@ -401,47 +478,68 @@ __global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level,
     const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     const int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
+    double nd[3] = {0.0, 0.0, 0.0};
+    if (bc == BCMG_BC_NEUMANN)
+        for (int k = 0; k < d; k++) nd[k] = -(double)s[k] * nv[k] / h;
     int w[3] = {1, 1, 1};
+    bool chosen = false;
     for (int c = 0; c < ncand; c++) {
         const int *cd = d == 3 ? cand3[c] : (d == 2 ? cand2[c] : cand1[c]);
         int wt[3] = {1, 1, 1};
         for (int r = 0; r < d; r++) wt[ord[r]] = cd[r];
-        if (!block_valid(cls, n, d, I, s, wt)) continue;
+        if (!block_valid(cls, n, d, I, s, wt, bc)) continue;
         double tt[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(nv[k]) : 0.0;
-        if (!block_dominant(cls, n, d, I, s, wt, tt, level > 0 ? 1.0 : 0.5)) continue;
+        if (!block_dominant(cls, n, d, I, s, wt, tt, nd, bc, level > 0 ? 1.0 : 0.5)) continue;
         w[0] = wt[0];
         w[1] = wt[1];
         w[2] = wt[2];
+        chosen = true;
         break;
     }
+    int axis = -1;  // Neumann row with no admissible block: one-sided difference along this axis
+    if (!chosen && bc == BCMG_BC_NEUMANN) {
+        int side = 0;
+        axis = first_inside_neighbour(cls, p, I, N, n, d, side);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            w[k] = k == axis ? 2 : 1;
+            nd[k] = k == axis ? -1.0 / h : 0.0;
+            s[k] = k == axis ? side : s[k];
+        }
+        fb |= 2;
+    }
     int code = 0;
+    double tq[3];
     for (int k = 0; k < 3; k++) {
         code |= (w[k] & 3) << (2 * k);
         if (s[k] < 0) code |= 1 << (6 + k);
         gn[3 * gi + k] = nv[k];
         const double xk = k < d ? -1.0 + I[k] * h : 0.0;
         gq[3 * gi + k] = k < d ? xk - eta * h * nv[k] : 0.0;
-        gtau[3 * gi + k] = (k < d && w[k] >= 2) ? eta * fabs(nv[k]) : 0.0;
+        tq[k] = (k < d && w[k] >= 2 && axis < 0) ? eta * fabs(nv[k]) : 0.0;
+        gtau[3 * gi + k] = tq[k];
+        if (gnd) gnd[3 * gi + k] = nd[k];
     }
     gcode[gi] = code;
     geta[gi] = eta;
     gfb[gi] = fb;
-    double dt = dtau_of(d, eta, dtau_mode, dtau_const);
+    double dt = bc == BCMG_BC_NEUMANN ? h * dtau_neumann_of(d, eta, dtau_mode, dtau_const)
+                                      : dtau_of(d, eta, dtau_mode, dtau_const);
     if (dtau_mode != BCMG_DTAU_CONST) {  // at most the row's Gauss-Seidel step 1/c_0
-        double c0 = 1.0;
-        for (int k = 0; k < 3; k++) c0 *= lag(w[k], 0, gtau[3 * gi + k]);
+        const int m0[3] = {0, 0, 0};
+        const double c0 = row_weight(bc, w, tq, nd, m0);
         if (c0 > 0.0 && dt * c0 > 1.0) dt = 1.0 / c0;
     }
     gdtau[gi] = dt;
 }
 
 void launch_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls, const int *gidx,
-                           int ng, int dtau_mode, double dtau_const, int *gcode, double *gtau, double *gdtau,
-                           double *geta, double *gn, double *gq, int *gfb, hipStream_t s) {
+                           int ng, int dtau_mode, double dtau_const, int bc, int *gcode, double *gtau, double *gdtau,
+                           double *geta, double *gn, double *gq, int *gfb, double *gnd, hipStream_t s) {
     if (ng <= 0) return;
     hipLaunchKernelGGL(k_ghost_geometry, dim3((ng + 127) / 128), dim3(128), 0, s, d, N, level, h, phi, cls, gidx, ng,
-                       dtau_mode, dtau_const, gcode, gtau, gdtau, geta, gn, gq, gfb);
+                       dtau_mode, dtau_const, bc, gcode, gtau, gdtau, geta, gn, gq, gfb, gnd);
 }
 
 // ----------------------------------------------------------- extension band
@@ -848,7 +946,8 @@ void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, h
 // on [A | I].  info[0] = unknowns, info[1] = 1 if a pivot falls below
 // 1e-14 max|A| (singular: the cycle then smooths instead).
 __global__ void k_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
-                               const double *gtau, double *work, double *ainv, int *cmap, int *info) {
+                               const double *gtau, int bc, const double *gnd, double reaction, double *work,
+                               double *ainv, int *cmap, int *info) {
     const int n = N + 1;
     int nn = 1;
     for (int k = 0; k < d; k++) nn *= n;
@@ -885,7 +984,7 @@ __global__ void k_coarse_setup(int d, int N, double h, const uint8_t *cls, const
         for (int row = 0; row < nc; row++) {
             const int p = cmap[row];
             if (cls[p] == C_INSIDE) {
-                work[row * W + row] += 2.0 * d * ih2;
+                work[row * W + row] += 2.0 * d * ih2 + reaction;
                 int str = 1;
                 for (int k = 0; k < d; k++) {
                     if (pos[p - str] >= 0) work[row * W + pos[p - str]] -= ih2;
@@ -900,21 +999,21 @@ __global__ void k_coarse_setup(int d, int N, double h, const uint8_t *cls, const
             coords(gidx[g], n, d, I);
             const int code = gcode[g];
             int w[3], s[3];
+            double tau[3], nd[3];
             for (int k = 0; k < 3; k++) {
                 w[k] = k < d ? code_w(code, k) : 1;
                 s[k] = code_s(code, k);
+                tau[k] = k < d ? gtau[3 * g + k] : 0.0;
+                nd[k] = bc == BCMG_BC_NEUMANN ? gnd[3 * g + k] : 0.0;
             }
             for (int m2 = 0; m2 < w[2]; m2++)
                 for (int m1 = 0; m1 < w[1]; m1++)
                     for (int m0 = 0; m0 < w[0]; m0++) {
                         const int m[3] = {m0, m1, m2};
-                        int J[3];
-                        double wgt = 1.0;
-                        for (int k = 0; k < 3; k++) {
-                            J[k] = I[k] - m[k] * s[k];
-                            wgt *= lag(w[k], m[k], k < d ? gtau[3 * g + k] : 0.0);
-                        }
-                        work[row * W + pos[index_of(J, n, d)]] += wgt;
+                        const int J[3] = {I[0] - m0 * s[0], I[1] - m1 * s[1], I[2] - m2 * s[2]};
+                        const int q = pos[index_of(J, n, d)];
+                        // BOXDIR nodes of Neumann blocks carry 0 on coarse levels
+                        if (q >= 0) work[row * W + q] += row_weight(bc, w, tau, nd, m);
                     }
         }
         double amax = 0.0;
@@ -963,9 +1062,10 @@ __global__ void k_coarse_setup(int d, int N, double h, const uint8_t *cls, const
 }
 
 void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
-                         const double *gtau, double *work, double *ainv, int *cmap, int *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_setup, dim3(1), dim3(kBlock), 0, s, d, N, h, cls, gidx, ng, gcode, gtau, work, ainv,
-                       cmap, info);
+                         const double *gtau, int bc, const double *gnd, double reaction, double *work, double *ainv,
+                         int *cmap, int *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_setup, dim3(1), dim3(kBlock), 0, s, d, N, h, cls, gidx, ng, gcode, gtau, bc, gnd,
+                       reaction, work, ainv, cmap, info);
 }
 
 // ------------------------------------------------------------- data movement
