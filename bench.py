@@ -76,11 +76,12 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles in the CPU sample")
-    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served", "rho_sweep"],
+    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served", "rho_sweep", "neumann"],
                     default="flower257",
                     help="flower257: the headline single solve; mixed513: 513^3 FP64 against mixed precision; "
                          "batched: 512 2D star problems; served: the continuous-batching request loop; "
-                         "rho_sweep: convergence factors of the paper's 2D tests, batched")
+                         "rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: the "
+                         "257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -103,6 +104,8 @@ def main():
         return bench_rho_sweep(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "neumann":
+        return bench_neumann(args)
     import numpy as np
     import torch
 
@@ -336,6 +339,68 @@ def bench_mixed(args):
     out["fp64"] = res["fp64"]
     out["mixed"] = res["mixed"]
     out["speedup_mixed_vs_fp64"] = res["mixed"]["unknowns_per_s"] / res["fp64"]["unknowns_per_s"]
+    print(json.dumps(out))
+
+
+def bench_neumann(args):
+    """257^3 ellipsoid of Sec. 4.2, u = exp(x+y+z): the reaction-diffusion
+    problem u - Laplace u = f with Neumann rows (g = grad u(Q) . n) on the
+    whole boundary, against the Poisson problem with Dirichlet rows, both
+    FP64 V(2,1) to ||r|| <= 1e-10 ||r0||."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd import workloads as W
+    from paper_2207_14208_amd.solver import Problem
+    N = args.N
+    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
+           "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,
+           "warmup": args.warmup, "dtype": "f64"}
+    phi = torch.from_numpy(W.sample(3, N, W.phi_ellipsoid())).cuda()
+    xs = [torch.from_numpy(np.ascontiguousarray(a)).cuda().ravel() for a in W.node_coords(3, N)]
+    ue = torch.exp(xs[0] + xs[1] + xs[2])
+    res = {}
+    for name, bc, c in (("neumann", NAT.BC_NEUMANN, 1.0), ("dirichlet", NAT.BC_DIRICHLET, 0.0)):
+        G = Problem(3, N, phi, bc=bc, reaction=c, max_cycles=args.max_cycles)
+        gi = G.ghost_info(0)
+        q, n = gi["q"], gi["n"]
+        eq = torch.exp(q[:, 0] + q[:, 1] + q[:, 2])
+        g = eq * (n[:, 0] + n[:, 1] + n[:, 2]) if bc == NAT.BC_NEUMANN else eq
+        G.set_data(c * ue - 3.0 * ue, g)
+        info = G.level_info(0)
+        unknowns = info["n_inside"] + info["n_ghost"]
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            u = G.initial_guess(ue)
+            G.solve(u, 1e-10)
+        torch.cuda.synchronize()
+        el = 0.0
+        for _ in range(args.steps):
+            u = G.initial_guess(ue)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, hist = G.solve(u, 1e-10)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+        el /= args.steps
+        cls = G.classes(0)
+        m = cls == NAT.INSIDE
+        h = np.asarray(hist, dtype=np.float64)
+        res[name] = {"unknowns": unknowns, "n_ghost": info["n_ghost"], "unknowns_per_s": unknowns / el,
+                     "ms_per_solve": el * 1e3, "cycles": st.cycles, "status": NAT.STATUS_NAMES.get(st.status),
+                     "rho_last": float(h[-1] / h[-2]) if len(h) >= 2 and h[-2] > 0 else None,
+                     "max_err_vs_exact": (u[m] - ue[m]).abs().max().item()}
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    out["config"] = {"workload": f"3D ellipsoid, {N + 1}^3 nodes, u=exp(x+y+z): u - Laplace u with Neumann rows "
+                                 f"vs Poisson with Dirichlet rows, FP64 V(2,1) to 1e-10", "nodes_per_axis": N + 1}
+    out["value"] = res["neumann"]["unknowns_per_s"]
+    out["ms_per_step"] = res["neumann"]["ms_per_solve"]
+    out["neumann"] = res["neumann"]
+    out["dirichlet"] = res["dirichlet"]
     print(json.dumps(out))
 
 

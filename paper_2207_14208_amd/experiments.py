@@ -18,6 +18,12 @@ grid sizes and Delta-tau settings.
     python -m paper_2207_14208_amd.experiments rectangle --N 128 --theta 0.1 0.5 0.9 --dtau const:1.0 const:1.75
     python -m paper_2207_14208_amd.experiments spectrum --N 128 --theta 0.2 0.5 --dtau opt_exp const:0.7
     python -m paper_2207_14208_amd.experiments theta-hist --N 1024 2048
+    python -m paper_2207_14208_amd.experiments test1n --N 128 256 --bc neumann --dtau opt_exp const:1.0
+    python -m paper_2207_14208_amd.experiments circle --N 128 --bc neumann --reaction 1 --dtau opt_exp const:0.5
+
+Neumann rows (Sec. 3.3 Test1N, Test2N; Sec. 4.2): bc = "neumann"; the
+constant Delta tau is then given in units of h, and the reaction term c of
+c u - Laplace u keeps the all-Neumann problems non-singular.
 
 Diagnostics (Sec. 3.2, Sec. 3.3): the DFT of the residual along the
 rectangle's ghost column after fine-grid relaxations, and the histogram of
@@ -47,6 +53,9 @@ DOMAINS = {
     # the rectangle of Sec. 3.2 in [-1,1]^2: the domain is x <= x_V with
     # x_V = 1 - theta h, so every ghost lies at the same distance theta h
     "rectangle": (2, lambda n, th: W.phi_halfspace(1.0 - th * 2.0 / n)),
+    # Test1N of Sec. 3.3: the line through (1 - 7h/10, 0) with slope -1/sqrt(3)
+    # (Neumann rows on it, the box faces Dirichlet)
+    "test1n": (2, lambda n, th: (lambda x, y, h=2.0 / n: 0.5 * (x + math.sqrt(3.0) * y - 1.0 + 0.7 * h))),
 }
 
 FIRST, LAST = 11, 15  # rho^(m) averaged over these cycles
@@ -59,6 +68,8 @@ class Spec:
     dtau: str = "opt_exp"      # opt_exp | opt_poly | const:<value>
     theta: float = 0.5         # rectangle only
     seed: int = 0
+    bc: str = "dirichlet"      # dirichlet | neumann
+    reaction: float = 0.0      # c of c u - Laplace u
 
     @property
     def dim(self) -> int:
@@ -69,6 +80,9 @@ class Spec:
             _, _, v = self.dtau.partition(":")
             return N.DTAU_CONST, float(v or 1.0)
         return DTAU_MODES[self.dtau], 1.0
+
+    def bc_code(self) -> int:
+        return {"dirichlet": N.BC_DIRICHLET, "neumann": N.BC_NEUMANN}[self.bc]
 
 
 def rho_from_history(hist, first: int = FIRST, last: int = LAST) -> float:
@@ -96,7 +110,7 @@ def _problem(spec: Spec, cycles: int):
     d, phi_of = DOMAINS[spec.domain]
     mode, const = spec.dtau_mode()
     G = Problem(d, spec.N, W.sample(d, spec.N, phi_of(spec.N, spec.theta)), dtau_mode=mode, dtau_const=const,
-                max_cycles=cycles)
+                max_cycles=cycles, bc=spec.bc_code(), reaction=spec.reaction)
     ng = G.level_info(0)["n_ghost"]
     G.set_data(torch.zeros(G.nodes, dtype=torch.float64, device="cuda"),
                torch.zeros(max(ng, 1), dtype=torch.float64, device="cuda")[:ng])
@@ -193,6 +207,8 @@ def main():
     ap.add_argument("--dtau", nargs="+", default=["opt_exp", "opt_poly", "const:1.75"])
     ap.add_argument("--theta", type=float, nargs="+", default=[0.5])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--bc", choices=["dirichlet", "neumann"], default="dirichlet")
+    ap.add_argument("--reaction", type=float, default=0.0)
     ap.add_argument("--json", action="store_true", help="print one JSON object per spec")
     a = ap.parse_args()
     if a.domain == "spectrum":
@@ -210,7 +226,7 @@ def main():
                       f"deciles {r['counts']}")
         return
     thetas = a.theta if a.domain == "rectangle" else [math.nan]
-    specs = [Spec(a.domain, n, dt, th if a.domain == "rectangle" else 0.5, a.seed)
+    specs = [Spec(a.domain, n, dt, th if a.domain == "rectangle" else 0.5, a.seed, a.bc, a.reaction)
              for n in a.N for th in thetas for dt in a.dtau]
     t0 = time.perf_counter()
     res = rho_sweep(specs)
@@ -221,7 +237,8 @@ def main():
         else:
             s = r["spec"]
             th = f" theta={s['theta']:.2f}" if a.domain == "rectangle" else ""
-            print(f"{s['domain']} N={s['N']}{th} dtau={s['dtau']}: rho={r['rho']:.4f} ({r['status']}, "
+            print(f"{s['domain']} N={s['N']}{th} {s['bc']} c={s['reaction']:g} dtau={s['dtau']}: "
+                  f"rho={r['rho']:.4f} ({r['status']}, "
                   f"{r['n_ghost']} ghosts)")
     print(f"{len(specs)} problems in {el:.2f} s")
 
