@@ -38,6 +38,7 @@
 
 #define OR_SMOOTH_RB 0
 #define OR_SMOOTH_LEX 1
+#define OR_SMOOTH_JAC 2
 
 #define OR_CYCLE_V 0
 #define OR_CYCLE_TGCS 1
@@ -55,7 +56,7 @@ typedef struct {
     double dtau_const;
     int ext_iters;       /* K: sweeps of the normal extension */
     int restrict_mode;   /* RENORM_FW or PLAIN_MEAN */
-    int smoother;        /* RB (red-black GS) or LEX (GS-LEX) for the interior */
+    int smoother;        /* RB (red-black GS), LEX (GS-LEX) or JAC (weighted Jacobi) for the interior */
     int cycle;           /* V-cycle or two-grid correction scheme */
     int bc;              /* condition on Gamma: DIRICHLET (B u = u) or NEUMANN (B u = grad u . n), Sec. 3.3 */
     double reaction;     /* c >= 0 in c u - Laplace u = f (c = 1: the reaction-diffusion tests of Sec. 3.3 / 4.2) */
@@ -657,7 +658,10 @@ double or_norm(or_problem *P, int l, const double *r) {
 
 /*
  * One smoothing step (the REL-ALL preconditioner, eq. 2Ddiri:P): Gauss-Seidel
- * on the interior (eq. GSLEX_2D, or its red-black ordering), then one
+ * on the interior (eq. GSLEX_2D, or its red-black ordering), or weighted
+ * Jacobi (Sec. 2.1: P = omega diag + (1 - omega) I with omega = 2/3 in 1D;
+ * here omega = 2d/(2d+1), the d-dimensional form of that choice: 4/5 in 2D,
+ * 6/7 in 3D), then one
  * fictitious-time relaxation of every ghost row (eq. rel with DtauOptTheta)
  * using the new interior values and the old ghost values (P_GG = I/dtau).
  */
@@ -666,7 +670,19 @@ void or_smooth(or_problem *P, int l, double *u, const double *rhs) {
     double h2 = L->h * L->h;
     double diag = 2.0 * L->d + L->reaction * h2; /* h^2 times the row's own coefficient */
     int I[3];
-    if (P->opt.smoother == OR_SMOOTH_LEX) {
+    if (P->opt.smoother == OR_SMOOTH_JAC) {
+        double omega = 2.0 * L->d / (2.0 * L->d + 1.0);
+        double *unew = (double *)malloc(sizeof(double) * L->nn); /* new INSIDE values from the old field */
+        for (long p = 0; p < L->nn; p++) {
+            if (L->cls[p] != OR_INSIDE) continue;
+            double s = 0.0;
+            for (int k = 0; k < L->d; k++) s += u[p + L->st[k]] + u[p - L->st[k]];
+            unew[p] = u[p] + omega * ((h2 * rhs[p] + s) / diag - u[p]);
+        }
+        for (long p = 0; p < L->nn; p++)
+            if (L->cls[p] == OR_INSIDE) u[p] = unew[p];
+        free(unew);
+    } else if (P->opt.smoother == OR_SMOOTH_LEX) {
         for (long p = 0; p < L->nn; p++) {
             if (L->cls[p] != OR_INSIDE) continue;
             double s = 0.0;

@@ -9,6 +9,7 @@ factor is the largest spectral radius of M(theta) over the low frequencies.
 
 Smoothers:
   'lex' lexicographic Gauss-Seidel: diagonal, symbol sum_k e^{i th_k} / (2d - sum_k e^{-i th_k})
+  'jac' weighted Jacobi, omega = 2d/(2d+1): diagonal, symbol 1 - omega (1 - sum_k cos th_k / d)
   'rb'  red-black Gauss-Seidel: a red partial step is chi_R J + chi_B with J
         the Jacobi symbol and chi_R = (I + Pi)/2, chi_B = (I - Pi)/2, where Pi
         swaps each harmonic with its (pi,...,pi) shift (multiplication by
@@ -41,6 +42,9 @@ def two_grid_matrix(theta, d, smoother="rb", nu1=2, nu2=1):
     if smoother == "lex":
         S = np.diag([sum(np.exp(1j * t[k]) for k in range(d)) / (2 * d - sum(np.exp(-1j * t[k]) for k in range(d)))
                      for t in th])
+    elif smoother == "jac":
+        om = 2.0 * d / (2.0 * d + 1.0)
+        S = np.diag([1.0 - om * (1.0 - sum(np.cos(t[k]) for k in range(d)) / d) for t in th]).astype(complex)
     elif smoother == "rb":
         J = np.diag([sum(np.cos(t[k]) for k in range(d)) / d for t in th]).astype(complex)
         Pi = np.zeros((H, H))

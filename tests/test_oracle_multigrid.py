@@ -267,6 +267,16 @@ def test_redblack_two_grid_factor_matches_lfa(d, N):
     assert abs(got - want) <= 0.1 * want, (got, want)
 
 
+@pytest.mark.parametrize("d,N", [(1, 256), (2, 64), (3, 32)])
+def test_weighted_jacobi_two_grid_factor_matches_lfa(d, N):
+    """Weighted Jacobi (Sec. 2.1, omega = 2/3 in 1D and 2d/(2d+1) in d
+    dimensions) on the box: the oracle's two-grid factor against the local
+    Fourier analysis of the same smoother."""
+    got = rho(d, N, W.phi_full_box, oracle.SMOOTH_JAC, oracle.CYCLE_TGCS)
+    want = lfa.two_grid_factor(d, "jac", n=64 if d == 1 else (32 if d == 2 else 16))
+    assert abs(got - want) <= 0.1 * want, (got, want)
+
+
 @pytest.mark.parametrize("theta", [0.0, 0.5, 0.9])
 def test_1d_ghost_relaxation_keeps_optimal_factor(theta):
     """Sec. 2.2: with s = 3 the 1D factor stays at the interior optimum ~0.08."""
