@@ -262,7 +262,10 @@ bcmg_status bcmg_batch_run(bcmg_batch *b, int32_t cycles_per_step, int32_t max_s
 /* Final state of a slot (valid once inactive). hist_host may be NULL. */
 bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stats_host, double *hist_host);
 
-/* Device bytes a problem of this size would need (for admission control). */
+/* Device bytes a problem of this size would need (for admission control): an
+ * upper bound of what bcmg_problem_bytes reports after bcmg_setup, for
+ * Dirichlet and Neumann rows alike (its model: the node arrays of every level,
+ * a surface term for ghost and band records, and the arena's chunking). */
 bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64_t *bytes);
 
 /* Batch tuning parameters (take effect at the next step). */

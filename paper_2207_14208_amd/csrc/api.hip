@@ -675,7 +675,10 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
         tot += nn * (8.0 + 1.0 + 3.0 * esz) + 64.0 * std::pow(NN + 1.0, dim - 1) * 8.0;
         if (NN == N) tot += nn * 16.0;  // FP64 rhs + residual on the finest level
     }
-    *bytes = (int64_t)(tot * 1.1) + (1 << 20);
+    // arrays of up to a quarter chunk share 4 MiB arena chunks, and a chunk is
+    // only left when the next array does not fit, so each chunk is at least
+    // 3/4 used: held bytes <= 4/3 of the array bytes plus one open chunk
+    *bytes = (int64_t)(tot * 1.1 * 4.0 / 3.0) + (int64_t)kArenaChunk;
     return BCMG_OK;
 }
 

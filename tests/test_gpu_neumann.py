@@ -293,3 +293,50 @@ def test_neumann_mixed_precision(name):
     m = unknowns(cls)
     err = np.abs(u.cpu().numpy()[m] - ustar[m]).max() / np.abs(ustar[m]).max()
     assert err <= 1e-8, err
+
+
+@pytest.mark.parametrize("name", ["ellipsoid_react_65", "spheres_react_65", "circle_react_129", "flower_dirichlet_65"])
+def test_memory_estimate_covers_the_problem(name):
+    """bcmg_estimate_bytes (used for admission control) is at least what a
+    problem of that size holds, for Dirichlet and Neumann rows alike."""
+    _gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Problem, estimate_bytes
+    if name == "flower_dirichlet_65":
+        c = W.flower3d(64)
+        G = Problem(c.d, c.N, c.phi)
+    else:
+        c = CASES[name]()
+        G = Problem(c.d, c.N, c.phi, bc=NEU, reaction=c.c)
+    for prec in (N.FP64,):
+        est = estimate_bytes(c.d, c.N, prec)
+        assert G.device_bytes() <= est, (G.device_bytes(), est)
+    G.close()
+
+
+def test_pure_neumann_poisson_reports_not_converged():
+    """Neumann rows on the whole boundary with c = 0 make the problem
+    singular (Sec. 3.3): the coarsest operator is flagged singular and
+    smoothed instead of inverted, the residual stalls, and the solve ends
+    NOT_CONVERGED at max_cycles with finite norms that follow the oracle's."""
+    _gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Problem
+    n = 64
+    phi = W.sample(2, n, W.phi_circle_paper())
+    f = W.sample(2, n, lambda x, y: np.cos(3 * x) * np.sin(2 * y) + 0.3)
+    O = oracle.Problem(2, n, phi, oracle.Options(bc=NEU, reaction=0.0))
+    assert O.coarse_singular()
+    ng = O.counts(0)[1]
+    O.set_rhs(f, np.zeros(ng))
+    uo = np.zeros(O.nodes(0))
+    it, ho = O.solve(uo, 1e-10, 20)
+    assert it == -1
+    G = Problem(2, n, phi, bc=NEU, reaction=0.0, max_cycles=20)
+    G.set_data(f, np.zeros(ng))
+    ug = G.initial_guess()
+    st, hg = G.solve(ug, 1e-10)
+    assert st.status == N.ERR_NOT_CONVERGED and st.cycles == 20, st
+    hg = np.asarray(hg)
+    assert np.all(np.isfinite(hg))
+    assert floor_close(hg, ho)
