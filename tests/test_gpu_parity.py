@@ -243,3 +243,28 @@ def test_vcycle_and_residual_norm_match_oracle():
     assert _close(uo, ug.cpu().numpy(), 1e-12)
     rn_o = O.norm(0, O.residual(0, uo))
     assert abs(G.residual_norm(ug) - rn_o) <= 1e-10 * rn_o
+
+
+@pytest.mark.parametrize("name,d,N", [("circle4097", 2, 4096), ("flower3d_257", 3, 256)])
+def test_smoothing_parity_at_full_size(name, d, N):
+    """Finest levels at full size, with more row segments than the chip holds
+    wavefronts at once (the 257^3 flower has 16320): two smoothing steps on
+    random data against the oracle."""
+    _gpu()
+    from paper_2207_14208_amd.solver import Problem
+    phi_fn = W.phi_circle_paper() if d == 2 else W.phi_flower3d()
+    phi = W.sample(d, N, phi_fn)
+    O = oracle.Problem(d, N, phi)
+    G = Problem(d, N, phi)
+    assert G.level_info(0)["n_segments"] > 8 * 4 * 256
+    rng = np.random.default_rng(23)
+    cls = O.classes(0)
+    nn = cls.size
+    rhs = np.where(unknowns(cls), rng.standard_normal(nn), 0.0)
+    u = np.where(unknowns(cls), rng.uniform(-1, 1, nn), 0.0)
+    u[cls == oracle.BOXDIR] = rng.uniform(-1, 1, (cls == oracle.BOXDIR).sum())
+    uo = u.copy()
+    O.smooth(0, uo, rhs, steps=2)
+    ug = torch.from_numpy(u).cuda()
+    G.level_smooth(0, ug, torch.from_numpy(rhs).cuda(), 2)
+    assert _close(uo, ug.cpu().numpy())
