@@ -84,6 +84,8 @@ def parse():
                          "257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
+    ap.add_argument("--prepare-workers", type=int, default=2,
+                    help="served: host threads that sample and set up admitted requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel of "
                          "known size, for scaling hardware traffic counters)")

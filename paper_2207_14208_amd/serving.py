@@ -312,11 +312,12 @@ def bench(args) -> dict:
     slots = 64
     dtau = N.DTAU_OPT_POLY
     n_meas = getattr(args, "requests", 400)
+    workers = getattr(args, "prepare_workers", 2)
     n_warm = max(20, n_meas // 8)
     be = GPUBackend(slots, dtau)
     # capacity: every request available at t = 0
     sat = make_requests(max(64, n_meas // 4), seed=1, rate=0.0)
-    srv = Server(be, slots, budget)
+    srv = Server(be, slots, budget, workers=workers)
     t0 = time.perf_counter()
     st = run(srv, sat)
     sat_s = time.perf_counter() - t0
@@ -326,7 +327,7 @@ def bench(args) -> dict:
     print(f"served: capacity {mu:.2f} req/s from {len(st.completed)} requests in {sat_s:.1f} s", file=sys.stderr,
           flush=True)
     reqs = make_requests(n_warm + n_meas, seed=14208, rate=lam)
-    srv = Server(be, slots, budget)
+    srv = Server(be, slots, budget, workers=workers)
     st = run(srv, reqs)
     srv.close()
     print(f"served: {len(st.completed)} requests at {lam:.2f} req/s done", file=sys.stderr, flush=True)
@@ -343,6 +344,7 @@ def bench(args) -> dict:
         "config": {"workload": "served 3D sphere unions, sides {33,65,129,257}, 4-64 spheres, g=0, tol 1e-8, "
                                "Poisson arrivals at 70% of measured capacity",
                    "slots": slots, "hbm_budget_bytes": budget, "dtau": "OPT_POLY", "capacity_req_per_s": mu,
+                   "prepare_workers": workers,
                    "arrival_rate": lam},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "throughput_req_per_s": len(meas) / span,
