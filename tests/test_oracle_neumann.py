@@ -271,3 +271,19 @@ def test_coarse_solve_with_boxdir_in_neumann_blocks():
             J = I - np.array(m) * g["s"][gi][:2]
             hit += P.classes(0)[J[1] * Nn + J[0]] == oracle.BOXDIR
     assert hit > 0
+
+
+@pytest.mark.parametrize("d,N,phi_fn,consts", [(2, 128, W.phi_circle_paper(), (0.25, 0.5, 0.75, 1.0)),
+                                               (3, 32, W.phi_ellipsoid(), (0.5, 0.75, 1.0))])
+def test_neumann_optimal_dtau_beats_constants(d, N, phi_fn, consts):
+    """Test2N (the reaction-diffusion circle, Sec. 3.3) and the Neumann
+    ellipsoid (Sec. 4.2), TGCS with GS-LEX as in the paper: the optimal
+    dtau(theta~) of Prop. optN / opt3DN converges faster than every constant
+    dtau tried, the paper's finding for both tests."""
+    phi = W.sample(d, N, phi_fn)
+    base = dict(bc=NEU, reaction=1.0, cycle=oracle.CYCLE_TGCS, smoother=oracle.SMOOTH_LEX)
+    opt = max(rho_homogeneous(d, N, phi, oracle.Options(dtau_mode=m, **base))
+              for m in (oracle.DTAU_OPT_EXP, oracle.DTAU_OPT_POLY))
+    const = {k: rho_homogeneous(d, N, phi, oracle.Options(dtau_mode=oracle.DTAU_CONST, dtau_const=k, **base))
+             for k in consts}
+    assert opt < min(const.values()), (opt, const)
