@@ -334,9 +334,9 @@ __device__ double dtau_of(int d, double theta, int mode, double cnst) {
 
 // First INSIDE axis neighbour of node p in the order -x, +x, -y, +y, -z, +z:
 // returns its axis (or -1) and sets side = +1 when it is p - e_k, -1 when it
-// is p + e_k.  Written as one straight pass with a single exit per outcome:
-// an if / else-if pair assigning the axis in both branches was compiled for
-// gfx950 so that the else-if branch kept the old axis.
+// is p + e_k.  Written as a chain of selects: an if / else-if pair that
+// assigned the axis in both branches was compiled for gfx950 so that the
+// else-if branch kept the old axis.
 __device__ int first_inside_neighbour(const uint8_t *cls, long long p, const int I[3], int N, int n, int d,
                                       int &side) {
     int axis = -1, sd = 0;
@@ -362,16 +362,16 @@ __device__ double dtau_neumann_of(int d, double theta, int mode, double cnst) {
     double t = theta < 1.0 ? theta : 1.0;
     if (t < 0.0) t = 0.0;
     if (d == 1) return HUGE_VAL;
-    const double plo = acosh(2.0), phi_ = acosh(2.0 * d - 1.0);
+    const double p_lo = acosh(2.0), p_hi = acosh(2.0 * d - 1.0);
     double gmin = INFINITY, gmax = -INFINITY;
     for (int v = 0; v <= d; v++) {
         double p;
         if (v < d) {
-            p = v < d - 1 ? acosh(2.0 + v) : phi_;
+            p = v < d - 1 ? acosh(2.0 + v) : p_hi;
         } else {  // the interior maximum of p e^{-p t}
             if (mode != BCMG_DTAU_OPT_EXP || !(t > 0.0)) break;
             p = 1.0 / t;
-            if (!(p > plo && p < phi_)) break;
+            if (!(p > p_lo && p < p_hi)) break;
         }
         double g;
         if (mode == BCMG_DTAU_OPT_EXP) {
