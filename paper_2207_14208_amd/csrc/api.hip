@@ -1451,11 +1451,13 @@ static void launch_vcycle(bcmg_batch *b) {
     }
 }
 
-// finest FP64 residual (into r64, or into the FP32 right-hand side of the
-// correction cycle) plus per-slot norm and convergence bookkeeping
+// finest FP64 residual (into the FP32 right-hand side of the correction
+// cycle; an FP64 batch keeps only its norm, since the next cycle recomputes
+// r before the restriction reads it) plus per-slot norm and convergence
+// bookkeeping
 static void launch_outer_residual(bcmg_batch *b, int mode) {
     launch_residual(b->d, 0, b->fp32, 1, b->d_outer, b->fsegs, b->nfseg, b->fgch, b->nfgch, b->d_state, b->d_partials,
-                    b->stream, b->neu);
+                    b->stream, b->neu, b->fp32 ? 1 : 0);
     launch_norm_finish(b->d_ranges, b->cap, b->d_partials, b->nfseg, b->d_state, b->d_rtol2, b->d_hist,
                        b->hist_stride, mode, nullptr, b->stream);
 }

@@ -128,8 +128,10 @@ __device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restr
 // ------------------------------------------------------------ node updates
 // Residual of the INSIDE rows of a segment (two nodes per lane); returns the
 // lane's sum of r^2.
+// store false: only the lane's sum of r^2 is wanted (the FP64 convergence
+// check, whose residual the next cycle recomputes before it is read).
 template <int D, typename Tu, typename Tr>
-__device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane, bool live) {
+__device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane, bool live, bool store = true) {
     const Seg s = seg_of(it);
     double r2 = 0.0;
     gcp<Tu> __restrict__ u = (gcp<Tu>)L.u;
@@ -174,7 +176,7 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         if (lane + 64 * h < s.len && cc[h] == C_INSIDE && live) {
-            r[pp[h]] = (Tr)rv[h];
+            if (store) r[pp[h]] = (Tr)rv[h];
             r2 += rv[h] * rv[h];
         }
     }
@@ -500,13 +502,13 @@ __device__ __forceinline__ void ghost_apply(const Desc &L, int g, bool live) {
 }
 
 template <int D, typename Tu, typename Tr, bool NEU>
-__device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live) {
+__device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live, bool store = true) {
     const long long pg = ((gcp<int>)L.gidx)[g];
     const double rg = (double)((gcp<Tu>)L.rhs)[pg];
     const double r = rg - ghost_row<D, Tu, NEU>(L, g, (gcp<Tu>)L.u);
     pin(r);
     if (!live) return 0.0;
-    ((gp<Tr>)L.r)[pg] = (Tr)r;
+    if (store) ((gp<Tr>)L.r)[pg] = (Tr)r;
     return r * r;
 }
 
@@ -635,11 +637,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int D, typename Tu, typename Tr, bool NORM, bool NEU>
 __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ descs, const Item *__restrict__ items,
                                                      int nseg, const Item *__restrict__ gch, int nseg_blocks,
-                                                     const SlotState *__restrict__ st, double *__restrict__ partials) {
+                                                     const SlotState *__restrict__ st, double *__restrict__ partials,
+                                                     int store) {
     const int lb = xcd_block_second_first(nseg_blocks);
     if (lb < nseg_blocks) {
         SEG_ITEM_AT(lb)
-        double r2 = seg_residual<D, Tu, Tr>(L, it, lane, live);
+        double r2 = seg_residual<D, Tu, Tr>(L, it, lane, live, store != 0);
         if (NORM) {
             r2 = wave_sum(r2);
             if (lane == 0) partials[sidx] = r2;
@@ -651,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     const Desc &L = descs[it.x];
     const bool live = st[L.slot].active != 0;
     double r2 = 0.0;
-    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr, NEU>(L, it.y + threadIdx.x, live);
+    if ((int)threadIdx.x < it.z) r2 = ghost_residual<D, Tu, Tr, NEU>(L, it.y + threadIdx.x, live, store != 0);
     if (NORM) {
         __shared__ double ws[kWavesPerBlock];
         r2 = wave_sum(r2);
@@ -1300,42 +1303,46 @@ void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int
 
 template <typename Tu, typename Tr, bool NORM, bool NEU>
 static void residual_t(int d, const Desc *descs, const Item *segs, int nseg, const Item *gch, int ngch,
-                       const SlotState *st, double *partials, hipStream_t s) {
+                       const SlotState *st, double *partials, hipStream_t s, int store) {
     const int sb = blocks_for_segs(nseg);
     if (sb + ngch <= 0) return;
     dim3 g(sb + ngch), b(kBlock);
     if (d == 1)
-        hipLaunchKernelGGL((k_residual<1, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+        hipLaunchKernelGGL((k_residual<1, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials,
+                           store);
     if (d == 2)
-        hipLaunchKernelGGL((k_residual<2, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+        hipLaunchKernelGGL((k_residual<2, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials,
+                           store);
     if (d == 3)
-        hipLaunchKernelGGL((k_residual<3, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials);
+        hipLaunchKernelGGL((k_residual<3, Tu, Tr, NORM, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st, partials,
+                           store);
 }
 
 template <bool NEU>
 static void residual_n(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
-                       const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s) {
+                       const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int store) {
     if (!tu32 && !tr32) {
         if (norm)
-            residual_t<double, double, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+            residual_t<double, double, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
         else
-            residual_t<double, double, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+            residual_t<double, double, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
     } else if (!tu32 && tr32) {
         if (norm)
-            residual_t<double, float, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+            residual_t<double, float, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
         else
-            residual_t<double, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+            residual_t<double, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
     } else {
-        residual_t<float, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s);
+        residual_t<float, float, false, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
     }
 }
 
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
-                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu) {
+                     const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu,
+                     int store) {
     if (neu)
-        residual_n<true>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s);
+        residual_n<true>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store);
     else
-        residual_n<false>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s);
+        residual_n<false>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store);
 }
 
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
