@@ -268,3 +268,62 @@ def test_smoothing_parity_at_full_size(name, d, N):
     ug = torch.from_numpy(u).cuda()
     G.level_smooth(0, ug, torch.from_numpy(rhs).cuda(), 2)
     assert _close(uo, ug.cpu().numpy())
+
+
+def test_two_vcycles_parity_at_full_size():
+    """The headline configuration itself (257^3 flower, FP64 V(2,1)): two
+    whole V-cycles from u0 = 0 (g_B on the box faces) against the oracle's,
+    u within 1e-12 relative and the residual norm within 1e-10."""
+    _gpu()
+    from paper_2207_14208_amd.solver import Problem
+    c = W.flower3d(256)
+    O = oracle.Problem(c.d, c.N, c.phi)
+    G = Problem(c.d, c.N, c.phi)
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    for _ in range(2):
+        O.vcycle(uo)
+        G.vcycle(ug)
+    assert _close(uo, ug.cpu().numpy(), 1e-12)
+    rn_o = O.norm(0, O.residual(0, uo))
+    assert abs(G.residual_norm(ug) - rn_o) <= 1e-10 * rn_o
+
+
+def test_batch_with_the_largest_batched_side():
+    """The batched workload's largest side (1025^2 star) in a batch with a
+    small one: the same bits as alone, and the oracle's u after the GPU's
+    cycle count."""
+    _gpu()
+    from paper_2207_14208_amd.solver import Batch, Problem
+    cases = [W.star_case(0, 1025, 0.45, 0.08, 5), W.star_case(1, 65, 0.35, 0.05, 3)]
+
+    def make(c):
+        G = Problem(c.d, c.N, c.phi)
+        gg = G.ghost_info(0)
+        G.set_data(c.f, W.points_eval(c.g, gg["q"].cpu().numpy(), c.d))
+        return G, G.initial_guess(torch.from_numpy(c.gB).cuda())
+
+    alone = []
+    for c in cases:
+        G, u = make(c)
+        st, _ = G.solve(u, 1e-10)
+        assert st.status == 0
+        alone.append((st.cycles, u.cpu().numpy()))
+    B = Batch(2)
+    made = [make(c) for c in cases]
+    slots = [B.add(G, u, 1e-10) for G, u in made]
+    B.run(1, 200)
+    for (cyc, ua), (G, u), s in zip(alone, made, slots):
+        st, _ = B.stats(s)
+        assert st.status == 0 and st.cycles == cyc
+        assert np.array_equal(u.cpu().numpy(), ua)
+    c = cases[0]
+    O = oracle.Problem(c.d, c.N, c.phi)
+    og = O.ghosts(0)
+    O.set_rhs(c.f, W.points_eval(c.g, og["q"], c.d))
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    O.solve(uo, 0.0, alone[0][0])
+    assert _close(uo, alone[0][1], 1e-12)
