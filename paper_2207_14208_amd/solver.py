@@ -45,7 +45,13 @@ class SolveStats:
 
 
 class Problem:
-    """One level-set Poisson problem (bcmg_setup ... bcmg_destroy)."""
+    """One level-set problem (bcmg_setup ... bcmg_destroy).
+
+    Options are the fields of bcmg_options (include/bcmg.h), for example
+    nu1, nu2, precision (N.FP64 / N.MIXED), dtau_mode, dtau_const, and
+    bc = N.BC_NEUMANN with reaction = c for c u - Laplace u = f; the ghost
+    data given to set_data is then the normal derivative at each Q.
+    """
 
     def __init__(self, dim: int, N_: int, phi, options: N.bcmg_options | None = None, stream=None, **opt_kw):
         self.dim, self.N = dim, N_
