@@ -25,7 +25,7 @@ OUTSIDE, INSIDE, GHOST, BOXDIR = 0, 1, 2, 3
 DTAU_OPT_EXP, DTAU_OPT_POLY, DTAU_CONST = 0, 1, 2
 RESTRICT_RENORM_FW, RESTRICT_PLAIN_MEAN = 0, 1
 SMOOTH_RB, SMOOTH_LEX, SMOOTH_JAC = 0, 1, 2
-CYCLE_V, CYCLE_TGCS = 0, 1
+CYCLE_V, CYCLE_TGCS, CYCLE_W = 0, 1, 2
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 
 

@@ -42,6 +42,7 @@
 
 #define OR_CYCLE_V 0
 #define OR_CYCLE_TGCS 1
+#define OR_CYCLE_W 2
 
 #define OR_BC_DIRICHLET 0
 #define OR_BC_NEUMANN 1
@@ -57,7 +58,7 @@ typedef struct {
     int ext_iters;       /* K: sweeps of the normal extension */
     int restrict_mode;   /* RENORM_FW or PLAIN_MEAN */
     int smoother;        /* RB (red-black GS), LEX (GS-LEX) or JAC (weighted Jacobi) for the interior */
-    int cycle;           /* V-cycle or two-grid correction scheme */
+    int cycle;           /* V-cycle, two-grid correction scheme or W-cycle */
     int bc;              /* condition on Gamma: DIRICHLET (B u = u) or NEUMANN (B u = grad u . n), Sec. 3.3 */
     double reaction;     /* c >= 0 in c u - Laplace u = f (c = 1: the reaction-diffusion tests of Sec. 3.3 / 4.2) */
 } or_options;
@@ -1027,7 +1028,8 @@ void or_coarse_solve(or_problem *P, double *u, const double *rhs) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Cycles (Sec. 2.1: TGCS, and its recursion with gamma = 1: the V-cycle)     */
+/* Cycles (Sec. 2.1: TGCS, and its recursion with gamma = 1, the V-cycle, or  */
+/* gamma = 2, the W-cycle)                                                    */
 
 static void or_vcycle_level(or_problem *P, int l, double *u, const double *rhs);
 
@@ -1057,10 +1059,14 @@ static void or_vcycle_level(or_problem *P, int l, double *u, const double *rhs) 
     or_restrict(P, l, F->r, C->rhs);
     for (long p = 0; p < C->nn; p++) C->u[p] = 0.0;
     int inner_cycle = l + 1 < P->L - 1;
-    if (P->opt.cycle == OR_CYCLE_TGCS && l == 0 && inner_cycle)
+    if (P->opt.cycle == OR_CYCLE_TGCS && l == 0 && inner_cycle) {
         or_solve_level(P, 1, C->u, C->rhs, 1e-14);
-    else
-        or_vcycle_level(P, l + 1, C->u, C->rhs);
+    } else {
+        /* gamma cycles on the coarse residual equation; the coarsest level
+         * is solved exactly, once */
+        int gamma = P->opt.cycle == OR_CYCLE_W && inner_cycle ? 2 : 1;
+        for (int g = 0; g < gamma; g++) or_vcycle_level(P, l + 1, C->u, C->rhs);
+    }
     memcpy(C->e, C->u, sizeof(double) * C->nn);
     or_prolong(P, l, C->e, u);
     for (int i = 0; i < P->opt.nu2; i++) or_smooth(P, l, u, rhs);

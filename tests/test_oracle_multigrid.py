@@ -267,6 +267,20 @@ def test_redblack_two_grid_factor_matches_lfa(d, N):
     assert abs(got - want) <= 0.1 * want, (got, want)
 
 
+@pytest.mark.parametrize("d,N", [(2, 64), (3, 32)])
+def test_w_cycle_factor_is_the_two_grid_factor(d, N):
+    """Sec. 2.1: gamma = 2 coarse cycles per level (the W-cycle).  On the box
+    it reaches the two-grid factor (coarse problem solved exactly) and the
+    local Fourier analysis of it; the V-cycle (gamma = 1) is slower."""
+    w = rho(d, N, W.phi_full_box, oracle.SMOOTH_RB, oracle.CYCLE_W)
+    tg = rho(d, N, W.phi_full_box, oracle.SMOOTH_RB, oracle.CYCLE_TGCS)
+    v = rho(d, N, W.phi_full_box, oracle.SMOOTH_RB, oracle.CYCLE_V)
+    want = lfa.two_grid_factor(d, "rb", n=32 if d == 2 else 16)
+    assert abs(w - tg) <= 0.02 * tg, (w, tg)
+    assert abs(w - want) <= 0.1 * want, (w, want)
+    assert v > 1.2 * w, (v, w)
+
+
 @pytest.mark.parametrize("d,N", [(1, 256), (2, 64), (3, 32)])
 def test_weighted_jacobi_two_grid_factor_matches_lfa(d, N):
     """Weighted Jacobi (Sec. 2.1, omega = 2/3 in 1D and 2d/(2d+1) in d
