@@ -95,8 +95,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design is "
-                                   "described in DESIGN.md and not implemented)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding the grid "
+                                   "across GPUs is not implemented)"}))
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)

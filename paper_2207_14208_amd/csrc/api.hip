@@ -683,7 +683,7 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
 }
 
 // Keep freed problem memory in the device pool instead of returning it to
-// the driver at every synchronisation (problems come and go when serving).
+// the HIP runtime at every synchronisation (problems come and go when serving).
 static void keep_pool_memory() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return;

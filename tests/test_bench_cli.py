@@ -1,0 +1,19 @@
+"""Command-line contract of bench.py that needs no GPU."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    # The solver runs on one GPU: asking for more must end with exit code 2
+    # and one JSON line that names the error, before any GPU work starts.
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1
+    msg = json.loads(lines[0])
+    assert "error" in msg and "one GPU" in msg["error"]
