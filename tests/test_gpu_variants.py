@@ -124,3 +124,43 @@ def test_coarse_levels_in_lds_same_as_in_hbm(name, coarse_nodes):
     assert (s1, c1) == (s2, c2) and s1 == 0
     assert np.array_equal(h1, h2)
     assert np.array_equal(u1, u2)
+
+
+def test_mixed_precision_at_full_size():
+    """The 513^3 flower in the benchmark's configuration (mixed precision,
+    u0 = 0, g at the GPU's own projections, tolerance 1e-10), checked by
+    properties the oracle can compute at this size: its FP64 residual of the
+    final u meets the tolerance against its own r0, the GPU's r0 is the
+    oracle's, u is within 1e-8 of the GPU's FP64 solve, and both carry the
+    same discretisation error against the exact solution."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Problem
+    c = W.flower3d(512)
+    sols = {}
+    for prec in (N.MIXED, N.FP64):
+        G = Problem(3, c.N, torch.from_numpy(c.phi).cuda(), precision=prec)
+        q = G.ghost_info(0)["q"]
+        G.set_data(torch.from_numpy(c.f).cuda(), torch.exp(q[:, 0] + q[:, 1] + q[:, 2]))
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        st, _ = G.solve(u, 1e-10)
+        assert st.status == 0, st
+        sols[prec] = (st, u.cpu().numpy())
+        G.close()
+        del G, u, q
+        torch.cuda.empty_cache()
+    st, um = sols[N.MIXED]
+    _, ud = sols[N.FP64]
+    O = oracle.Problem(3, c.N, c.phi)
+    og = O.ghosts(0)
+    O.set_rhs(c.f, W.points_eval(c.g, og["q"], 3))
+    cls = O.classes(0)
+    m = (cls == oracle.INSIDE) | (cls == oracle.GHOST)
+    r0 = O.norm(0, O.residual(0, np.zeros(cls.size)))
+    assert abs(st.r0 - r0) <= 1e-10 * r0, (st.r0, r0)
+    rn = O.norm(0, O.residual(0, um))
+    assert rn <= 1.01 * 1e-10 * r0, (rn, r0)
+    assert np.abs(um[m] - ud[m]).max() <= 1e-8 * np.abs(ud[m]).max()
+    em = np.abs(um[m] - c.gB[m]).max()
+    ed = np.abs(ud[m] - c.gB[m]).max()
+    assert em <= 0.02 and abs(em - ed) <= 1e-8, (em, ed)
