@@ -327,3 +327,37 @@ def test_batch_with_the_largest_batched_side():
     uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
     O.solve(uo, 0.0, alone[0][0])
     assert _close(uo, alone[0][1], 1e-12)
+
+
+def test_largest_3d_grid_converges_at_second_order():
+    """The largest 3D grid the library accepts (1025^3, about 1.08e9 nodes):
+    a sphere of radius 0.55 with u = exp(x+y+z), solved in FP64 to 1e-10 at
+    513^3 and at 1025^3.  No oracle solve fits this size, so the checks are
+    properties that hold at any size: convergence, and the INSIDE error
+    against the exact solution falling like h^2 (the oracle gives a ratio of
+    2.9-3.3 per halving at 33^3-129^3 on the same domain; 2.5 is asserted)."""
+    _gpu()
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd.solver import Problem
+    err = {}
+    for N in (512, 1024):
+        x = -1.0 + torch.arange(N + 1, dtype=torch.float64, device="cuda") * (2.0 / N)
+        phi = (torch.sqrt((x[None, None, :] - 0.01) ** 2 + (x[None, :, None] - 0.02) ** 2 +
+                          (x[:, None, None] - 0.03) ** 2) - 0.55).reshape(-1)
+        f = (-3.0 * torch.exp(x[None, None, :] + x[None, :, None] + x[:, None, None])).reshape(-1)
+        G = Problem(3, N, phi)
+        del phi
+        q = G.ghost_info(0)["q"]
+        G.set_data(f, torch.exp(q[:, 0] + q[:, 1] + q[:, 2]))
+        del f, q
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        st, _ = G.solve(u, 1e-10)
+        assert st.status == 0 and st.r_final <= 1e-10 * st.r0, st
+        inside = G.classes(0) == NAT.INSIDE
+        G.close()
+        del G
+        ue = torch.exp(x[None, None, :] + x[None, :, None] + x[:, None, None]).reshape(-1)
+        err[N] = (u - ue)[inside].abs().max().item()
+        del u, ue, inside
+        torch.cuda.empty_cache()
+    assert err[1024] <= 3e-5 and err[1024] * 2.5 <= err[512], err
