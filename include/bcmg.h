@@ -125,8 +125,10 @@ bcmg_status bcmg_default_options(bcmg_options *opt);
  * Per level the setup classifies nodes, compacts the ghost list in ascending
  * node order, computes each ghost's upwind stencil, projection Q = G - eta h n,
  * theta~ = eta and dtau (eqs. BCh, rel, DtauOptTheta), the extension band and
- * the coarsest-level inverse.  Returns BCMG_ERR_INVALID for bad sizes/options
- * or non-finite phi.
+ * the coarsest-level inverse.  Returns BCMG_ERR_INVALID for bad sizes/options,
+ * non-finite phi, or a phi that is negative at no node (a domain with no
+ * unknowns).  Coarse levels with no INSIDE node are allowed: their correction
+ * is zero.
  */
 bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg_options *opt, void *stream,
                        bcmg_problem **out);

@@ -438,6 +438,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     V.ni = *h_total;
+    if (l == 0 && V.ni == 0) return fail(BCMG_ERR_INVALID, "phi < 0 at no node: the domain holds no unknowns");
     launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, nullptr, total_dev, s);
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -361,3 +361,54 @@ def test_largest_3d_grid_converges_at_second_order():
         del u, ue, inside
         torch.cuda.empty_cache()
     assert err[1024] <= 3e-5 and err[1024] * 2.5 <= err[512], err
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_one_node_domain(d):
+    """Degenerate domain: a disc (ball) of radius 0.3h holding one INSIDE
+    node, which lies off the coarse grids, so every coarse level is empty.
+    Classes, counts and ghost lists agree bit for bit on every level; with
+    dtau = 1 both sides converge in the same cycles to the same u, and with
+    the exponential dtau both diverge, as sub-h domains can under the optimal
+    dtau."""
+    Problem = _gpu()
+    from paper_2207_14208_amd import _native as NAT
+    N = 16
+    h = 2.0 / N
+    c0 = (0.13, 0.13, 0.13)[:d]
+    c = W.make_case("one_node", d, N, lambda *xs: np.sqrt(sum((x - a) ** 2 for x, a in zip(xs, c0))) - 0.3 * h,
+                    W.exp_sum(d))
+    for mode in (oracle.DTAU_CONST, oracle.DTAU_OPT_EXP):
+        O = oracle.Problem(d, N, c.phi, oracle.Options(dtau_mode=mode, dtau_const=1.0))
+        G = Problem(d, N, c.phi, dtau_mode=mode, dtau_const=1.0)
+        assert G.levels == O.L and O.counts(0) == (1, 2 * d)
+        for l in range(O.L):
+            assert np.array_equal(O.classes(l), G.classes(l).cpu().numpy())
+            info = G.level_info(l)
+            assert (info["n_inside"], info["n_ghost"]) == O.counts(l)
+            assert np.array_equal(O.ghosts(l)["idx"], G.ghost_info(l)["idx"].cpu().numpy().astype(np.int64))
+        assert all(O.counts(l) == (0, 0) for l in range(1, O.L))
+        _rhs_pair(c, O, G)
+        cls = O.classes(0)
+        uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+        it, _ = O.solve(uo, 1e-10, 100)
+        ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        st, _ = G.solve(ug, 1e-10)
+        if mode == oracle.DTAU_CONST:
+            assert it > 0 and st.status == NAT.OK and abs(st.cycles - it) <= 1, (it, st)
+            assert _close(oracle_after(c, O, st.cycles), ug.cpu().numpy(), 1e-12)
+        else:
+            assert it < 0 and st.status == NAT.ERR_DIVERGED, (it, st)
+
+
+def test_empty_and_non_finite_level_sets_are_rejected():
+    """phi >= 0 everywhere (no unknowns) and a NaN in phi: setup returns
+    BCMG_ERR_INVALID and the handle is never created."""
+    Problem = _gpu()
+    from paper_2207_14208_amd import _native as NAT
+    nan_at_one = -np.ones(17 * 17)
+    nan_at_one[100] = np.nan
+    for phi in (np.ones(17 * 17), np.zeros(17 * 17), nan_at_one):
+        with pytest.raises(NAT.BcmgError) as e:
+            Problem(2, 16, phi)
+        assert e.value.status == NAT.ERR_INVALID
