@@ -1,0 +1,59 @@
+"""Host logic of the rocprofv3 summaries (no GPU): kernel names, per-kernel
+aggregation and the copy-probe scaling of the HBM counters."""
+import csv
+
+import pytest
+
+from paper_2207_14208_amd import profsum
+
+
+def _write(path, header, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_short_names_keep_template_arguments_and_drop_parameters():
+    assert profsum._short("void bcmg::k_rb_sweep<3, double>(bcmg::Desc const*, int)") == "k_rb_sweep<3, double>"
+    assert profsum._short("k_norm_finish(NormRange const*, int)") == "k_norm_finish"
+    assert profsum._short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
+
+
+def test_trace_table_groups_by_kernel_and_grid(tmp_path):
+    hdr = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"]
+    _write(tmp_path / "t_kernel_trace.csv", hdr, [
+        ["void k_a<3, double>(int)", 1024, 0, 4000],
+        ["void k_a<3, double>(int)", 1024, 10, 2010],
+        ["void k_a<3, double>(int)", 256, 0, 1000],
+        ["void k_b(int)", 64, 0, 1000],
+    ])
+    rows, tot_ms = profsum.trace_table(str(tmp_path), top=10)
+    assert tot_ms == pytest.approx(8000 / 1e6)
+    assert rows[0] == ("k_a<3, double>", 1024, 2, pytest.approx(3.0), pytest.approx(75.0))
+    assert {(k, g) for k, g, *_ in rows[1:]} == {("k_a<3, double>", 256), ("k_b", 64)}
+
+
+def test_traffic_scales_counters_by_the_copy_probe(tmp_path):
+    # a 1 MiB copy whose FETCH_SIZE reads 512 KiB and WRITE_SIZE 1024 KiB:
+    # factors 2 and 1, so a kernel reading 100 KiB and writing 30 KiB moves
+    # 230 KiB per launch
+    hdr = ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    fd, wd = tmp_path / "f", tmp_path / "w"
+    fd.mkdir()
+    wd.mkdir()
+    _write(fd / "c_counter_collection.csv", hdr, [
+        ["elementwise_copy_kernel(int)", 4096, "FETCH_SIZE", 512.0],
+        ["void k_rb_sweep<3, double>(int)", 2048, "FETCH_SIZE", 90.0],
+        ["void k_rb_sweep<3, double>(int)", 2048, "FETCH_SIZE", 110.0],
+        ["void k_rb_sweep<3, double>(int)", 512, "FETCH_SIZE", 7.0],
+    ])
+    _write(wd / "c_counter_collection.csv", hdr, [
+        ["elementwise_copy_kernel(int)", 4096, "WRITE_SIZE", 1024.0],
+        ["void k_rb_sweep<3, double>(int)", 2048, "WRITE_SIZE", 30.0],
+        ["void k_rb_sweep<3, double>(int)", 512, "WRITE_SIZE", 2.0],
+    ])
+    t = profsum.traffic(str(fd), str(wd), "k_rb_sweep<3, double>", 0, 1 << 20)
+    assert t["grid"] == 2048 and t["dispatches"] == [2, 1]
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    assert t["bytes_per_launch"] == pytest.approx(230.0 * 1024)
