@@ -594,12 +594,25 @@ __device__ __forceinline__ int xcd_block_second_first(int nfirst) {
     if ((int)threadIdx.x >= it.z) return;                         \
     const int e = it.y + threadIdx.x;
 
+// Ghost step, first half: one wavefront-sized workgroup per quarter chunk, so
+// that the finest level's chunks spread their dependent gathers over every CU
+// (a whole chunk per workgroup leaves the 257^3 flower's 52,873 ghosts on 207
+// workgroups).  Each thread computes the same entry as with whole chunks.
+constexpr int kGhostSplit = 4;
+constexpr int kGhostBlock = kChunk / kGhostSplit;
+static_assert(kGhostBlock * kGhostSplit == kChunk, "a chunk splits into whole workgroups");
+
 template <int D, typename T, bool NEU>
-__global__ __launch_bounds__(kBlock) void k_ghost_delta(const Desc *__restrict__ descs,
-                                                        const Item *__restrict__ items,
-                                                        const SlotState *__restrict__ st) {
-    CHUNK_ITEM
-    ghost_delta<D, T, NEU>(L, e, live);
+__global__ __launch_bounds__(kGhostBlock) void k_ghost_delta(const Desc *__restrict__ descs,
+                                                             const Item *__restrict__ items,
+                                                             const SlotState *__restrict__ st) {
+    const int lb = xcd_block();
+    const Item it = items[lb / kGhostSplit];
+    const Desc &L = descs[it.x];
+    const bool live = st[L.slot].active != 0;
+    const int t = (lb % kGhostSplit) * kGhostBlock + (int)threadIdx.x;
+    if (t >= it.z) return;
+    ghost_delta<D, T, NEU>(L, it.y + t, live);
 }
 
 // Ghost step, second half: the new ghost values into u (chunk blocks), and,
@@ -1291,12 +1304,12 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
                         hipStream_t s, const Item *bch, int nbch, int neu) {
     if (ngch <= 0 && nbch <= 0) return;
-    dim3 g(ngch), ga(ngch + nbch * kRowLanes), b(kBlock);
+    dim3 g(ngch * kGhostSplit), gb(kGhostBlock), ga(ngch + nbch * kRowLanes), b(kBlock);
     if (fp32) {
-        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, float, g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, float, g, gb, 0, s, descs, gch, st);
         hipLaunchKernelGGL((k_ghost_apply<float>), ga, b, 0, s, descs, gch, ngch, bch, st);
     } else {
-        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, double, g, b, 0, s, descs, gch, st);
+        if (ngch > 0) DISPATCH_DN(d, neu, k_ghost_delta, double, g, gb, 0, s, descs, gch, st);
         hipLaunchKernelGGL((k_ghost_apply<double>), ga, b, 0, s, descs, gch, ngch, bch, st);
     }
 }
