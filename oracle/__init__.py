@@ -34,7 +34,7 @@ class _Opts(C.Structure):
         ("nu1", C.c_int), ("nu2", C.c_int), ("coarsest_N", C.c_int), ("max_cycles", C.c_int),
         ("dtau_mode", C.c_int), ("dtau_const", C.c_double), ("ext_iters", C.c_int),
         ("restrict_mode", C.c_int), ("smoother", C.c_int), ("cycle", C.c_int),
-        ("bc", C.c_int), ("reaction", C.c_double),
+        ("bc", C.c_int), ("reaction", C.c_double), ("ghost_dominance", C.c_int),
     ]
 
 
@@ -121,11 +121,12 @@ class Options:
     cycle: int = CYCLE_V
     bc: int = BC_DIRICHLET
     reaction: float = 0.0
+    ghost_dominance: int = 1   # 0: stencil widths by validity only (shows why the dominance test is needed)
 
     def _c(self) -> _Opts:
         return _Opts(self.nu1, self.nu2, self.coarsest_N, self.max_cycles, self.dtau_mode,
                      float(self.dtau_const), self.ext_iters, self.restrict_mode, self.smoother, self.cycle,
-                     self.bc, float(self.reaction))
+                     self.bc, float(self.reaction), int(self.ghost_dominance))
 
 
 def dtau(d: int, theta: float, mode: int = DTAU_OPT_EXP, const: float = 1.0) -> float:

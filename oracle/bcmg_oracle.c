@@ -61,6 +61,7 @@ typedef struct {
     int cycle;           /* V-cycle, two-grid correction scheme or W-cycle */
     int bc;              /* condition on Gamma: DIRICHLET (B u = u) or NEUMANN (B u = grad u . n), Sec. 3.3 */
     double reaction;     /* c >= 0 in c u - Laplace u = f (c = 1: the reaction-diffusion tests of Sec. 3.3 / 4.2) */
+    int ghost_dominance; /* 1: stencil widths must pass or_block_dominant; 0: validity only (test mode) */
 } or_options;
 
 typedef struct {
@@ -143,6 +144,7 @@ void or_default_options(or_options *o) {
     o->cycle = OR_CYCLE_V;
     o->bc = OR_BC_DIRICHLET;
     o->reaction = 0.0;
+    o->ghost_dominance = 1;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -295,6 +297,49 @@ static void or_grad(const or_level *L, const int I[3], double g[3]) {
     }
 }
 
+/*
+ * Discrete unit normal at node I (Sec. 3.3: n = grad_h phi / |grad_h phi|),
+ * the axis-dominance key |grad_h phi_k| and the upwind signs s_k (+1 when
+ * grad_h phi_k >= 0).  A zero discrete gradient takes the unit vector from
+ * the first INSIDE axis neighbour (order -x,+x,-y,+y,-z,+z) to I.  Returns
+ * |grad_h phi|.
+ */
+static double or_normal(const or_level *L, const int I[3], double n[3], double key[3], int s[3]) {
+    int d = L->d;
+    double g[3];
+    or_grad(L, I, g);
+    double gnorm = 0.0;
+    for (int k = 0; k < d; k++) gnorm += g[k] * g[k];
+    gnorm = sqrt(gnorm);
+    for (int k = 0; k < 3; k++) {
+        n[k] = 0.0;
+        key[k] = 0.0;
+        s[k] = 1;
+    }
+    if (gnorm > 0.0) {
+        for (int k = 0; k < d; k++) {
+            n[k] = g[k] / gnorm;
+            key[k] = fabs(g[k]);
+        }
+    } else {
+        int found = 0;
+        for (int k = 0; k < d && !found; k++) {
+            for (int sgn = -1; sgn <= 1 && !found; sgn += 2) {
+                int J[3] = {I[0], I[1], I[2]};
+                J[k] += sgn;
+                if (!or_in_box(L, J)) continue;
+                if (L->cls[or_index(L, J)] == OR_INSIDE) {
+                    n[k] = -(double)sgn;
+                    found = 1;
+                }
+            }
+        }
+        for (int k = 0; k < d; k++) key[k] = fabs(n[k]);
+    }
+    for (int k = 0; k < d; k++) s[k] = (gnorm > 0.0 ? g[k] : n[k]) >= 0.0 ? 1 : -1;
+    return gnorm;
+}
+
 /* Lagrange basis on nodes 0..w-1 evaluated at t (eq. coeff for w = 3,
  * the s = 2 coefficients of Sec. 2 for w = 2). */
 static double or_lagrange(int w, int m, double t) {
@@ -377,10 +422,23 @@ static int or_block_valid(const or_level *L, const int I[3], const int s[3], con
     return 1;
 }
 
-/* c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block); a
- * Neumann row also needs c_0 > 0 (a width-1 axis carries no derivative) */
+/*
+ * Admissibility of a ghost row's block beyond validity: the row's own weight
+ * c_0 must be at least the sum of |w_m| over the block's other GHOST nodes
+ * whose upwind signs differ from G's, plus half the sum over those oriented
+ * like G.
+ * Blocks extend against the signs, so a closed loop of ghost rows, each
+ * holding the next in its block, needs a sign change between two
+ * consecutive ghosts of the loop: every loop has a coupling of the first
+ * kind, and with full dominance there the ghost rows relaxed together
+ * cannot form a nearly singular (or expanding) block.  Couplings between
+ * ghosts of one orientation run one way; a row whose weight sits mostly on
+ * such ghosts still relaxes slowly (they do not respond to it within the
+ * step), which the half-weight term bounds.  A Neumann row also needs
+ * c_0 > 0 (a width-1 axis carries no derivative).
+ */
 static int or_block_dominant(const or_level *L, const int I[3], const int s[3], const int w[3], const double tau[3],
-                             const double nd[3], double f) {
+                             const double nd[3]) {
     double c0 = 0.0, off = 0.0;
     int m[3];
     for (m[2] = 0; m[2] < w[2]; m[2]++)
@@ -389,21 +447,27 @@ static int or_block_dominant(const or_level *L, const int I[3], const int s[3], 
                 int J[3];
                 for (int k = 0; k < 3; k++) J[k] = I[k] - m[k] * s[k];
                 double wgt = or_row_weight(L->bc, w, tau, nd, m);
-                if (m[0] == 0 && m[1] == 0 && m[2] == 0)
+                if (m[0] == 0 && m[1] == 0 && m[2] == 0) {
                     c0 = wgt;
-                else if (L->cls[or_index(L, J)] == OR_GHOST)
-                    off += fabs(wgt);
+                } else if (L->cls[or_index(L, J)] == OR_GHOST) {
+                    double nJ[3], kJ[3];
+                    int sJ[3];
+                    or_normal(L, J, nJ, kJ, sJ);
+                    if (sJ[0] != s[0] || sJ[1] != s[1] || sJ[2] != s[2]) off += fabs(wgt);
+                    else off += 0.5 * fabs(wgt);
+                }
             }
     if (L->bc == OR_BC_NEUMANN && !(c0 > 0.0)) return 0;
-    return c0 >= f * off;
+    return c0 >= off;
 }
 
 /*
  * Geometry of one ghost point G (Sec. 3.3, eqs. (BCh), (rel), (DtauOptTheta)):
  * normal n, upwind signs, stencil widths, projection Q = G - eta h n with
- * phi~(Q) = 0, local coordinates tau of Q, theta~ = |G-Q|/h = eta, Delta tau.
+ * phi~(Q) = 0, local coordinates tau of Q, theta~ (eta for a full-width row)
+ * and Delta tau.
  */
-static void or_ghost_geometry(or_level *L, int level, long gi, const or_options *o) {
+static void or_ghost_geometry(or_level *L, long gi, const or_options *o) {
     static const int cand3[7][3] = {{3, 3, 3}, {2, 2, 2}, {3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     static const int cand2[5][3] = {{3, 3, 1}, {2, 2, 1}, {3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
     static const int cand1[3][3] = {{3, 1, 1}, {2, 1, 1}, {1, 1, 1}};
@@ -412,38 +476,9 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
     int I[3];
     or_coords(L, p, I);
 
-    double g[3];
-    or_grad(L, I, g);
-    double gnorm = 0.0;
-    for (int k = 0; k < d; k++) gnorm += g[k] * g[k];
-    gnorm = sqrt(gnorm);
-
-    double n[3] = {0.0, 0.0, 0.0};
-    double key[3] = {0.0, 0.0, 0.0}; /* axis-dominance key */
-    if (gnorm > 0.0) {
-        for (int k = 0; k < d; k++) {
-            n[k] = g[k] / gnorm;
-            key[k] = fabs(g[k]);
-        }
-    } else {
-        /* zero discrete gradient: unit vector from the first INSIDE
-         * neighbour (order -x,+x,-y,+y,-z,+z) to G */
-        int found = 0;
-        for (int k = 0; k < d && !found; k++) {
-            for (int sgn = -1; sgn <= 1 && !found; sgn += 2) {
-                int J[3] = {I[0], I[1], I[2]};
-                J[k] += sgn;
-                if (!or_in_box(L, J)) continue;
-                if (L->cls[or_index(L, J)] == OR_INSIDE) {
-                    n[k] = -(double)sgn;
-                    found = 1;
-                }
-            }
-        }
-        for (int k = 0; k < d; k++) key[k] = fabs(n[k]);
-    }
-    int s[3] = {1, 1, 1};
-    for (int k = 0; k < d; k++) s[k] = (gnorm > 0.0 ? g[k] : n[k]) >= 0.0 ? 1 : -1;
+    double n[3], key[3]; /* unit normal, axis-dominance key */
+    int s[3];
+    double gnorm = or_normal(L, I, n, key, s);
 
     /* axes by dominance, descending; ties keep the lower axis first */
     int ord[3] = {0, 1, 2};
@@ -498,11 +533,9 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
 
     /* first admissible width vector (entries assigned to axes in dominance
      * order): block inside the box, made of INSIDE/GHOST nodes, and a row
-     * whose own weight c_0 is at least f times the sum of the |weights| of
-     * the other ghosts of the block: f = 1 on coarse levels (their ghost rows,
-     * relaxed together, then form a diagonally dominant block), f = 1/2 on
-     * the finest level (only strongly crossed pairs of ghost rows, where the
-     * geometry is under-resolved, lose the full stencil) */
+     * whose own weight c_0 is at least the sum of the |weights| of the other
+     * ghosts of the block (or_block_dominant; the option ghost_dominance = 0
+     * drops this second test, for the test that shows why it is needed) */
     const int(*cand)[3] = d == 3 ? cand3 : (d == 2 ? cand2 : cand1);
     int ncand = d == 3 ? 7 : (d == 2 ? 5 : 3);
     /* Neumann rows: coefficient of d/dt_k in n . grad (t_k = (x_G - x)_k s_k / h) */
@@ -517,7 +550,7 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
         if (!or_block_valid(L, I, s, wt)) continue;
         double tt[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(n[k]) : 0.0;
-        if (!or_block_dominant(L, I, s, wt, tt, nd, level > 0 ? 1.0 : 0.5)) continue;
+        if (o->ghost_dominance && !or_block_dominant(L, I, s, wt, tt, nd)) continue;
         w[0] = wt[0];
         w[1] = wt[1];
         w[2] = wt[2];
@@ -557,8 +590,28 @@ static void or_ghost_geometry(or_level *L, int level, long gi, const or_options 
     }
     L->geta[gi] = eta;
     L->gfb[gi] = fb;
-    double dt = L->bc == OR_BC_NEUMANN ? L->h * or_dtau_neumann(d, eta, o->dtau_mode, o->dtau_const)
-                                       : or_dtau(d, eta, o->dtau_mode, o->dtau_const);
+    /* theta~ of eq. (DtauOptTheta): the distance, along the normal, from G
+     * to the point where the row interpolates.  Remark (exptheta2D) reads
+     * G_0 as the value there of an error mode exp(-p (x_G - x).n / h) that
+     * decays along the normal.  A full-width row interpolates at Q itself,
+     * so theta~ = |G - Q| / h = eta.  A row with width-1 axes interpolates
+     * at Q projected onto the span of its other axes (tau_k = 0 on the
+     * width-1 ones), whose distance from G along n is eta * sum of n_k^2
+     * over the kept axes. */
+    double theta = eta;
+    if (last_resort < 0) {
+        int shortened = 0;
+        double nn2 = 0.0;
+        for (int k = 0; k < d; k++) {
+            if (w[k] >= 2)
+                nn2 += n[k] * n[k];
+            else
+                shortened = 1;
+        }
+        if (shortened) theta = eta * nn2;
+    }
+    double dt = L->bc == OR_BC_NEUMANN ? L->h * or_dtau_neumann(d, theta, o->dtau_mode, o->dtau_const)
+                                       : or_dtau(d, theta, o->dtau_mode, o->dtau_const);
     /* never relax a ghost row beyond its own Gauss-Seidel step dtau = 1/c_0
      * (the value the relaxation reduces to at theta = 0, Sec. 2.1); on the
      * quadratic row of the BLFA this bound is inactive in 2D and within 3%
@@ -1126,7 +1179,7 @@ static void or_level_alloc(or_level *L, int d, int N) {
     L->e = (double *)calloc(L->nn, sizeof(double));
 }
 
-static void or_level_geometry(or_level *L, int level, const or_options *o) {
+static void or_level_geometry(or_level *L, const or_options *o) {
     or_classify(L->d, L->N, L->phi, L->cls);
     L->ni = L->ng = 0;
     for (long p = 0; p < L->nn; p++) {
@@ -1149,7 +1202,7 @@ static void or_level_geometry(or_level *L, int level, const or_options *o) {
     long c = 0;
     for (long p = 0; p < L->nn; p++)
         if (L->cls[p] == OR_GHOST) L->gidx[c++] = p;
-    for (long gi = 0; gi < L->ng; gi++) or_ghost_geometry(L, level, gi, o);
+    for (long gi = 0; gi < L->ng; gi++) or_ghost_geometry(L, gi, o);
 }
 
 /*
@@ -1190,7 +1243,7 @@ or_problem *or_setup(int d, int N, const double *phi, const or_options *opt) {
             C->phi[pc] = F->phi[or_index(F, I)];
         }
     }
-    for (int l = 0; l < L; l++) or_level_geometry(&P->lev[l], l, opt);
+    for (int l = 0; l < L; l++) or_level_geometry(&P->lev[l], opt);
     or_coarse_factor(P);
     return P;
 }

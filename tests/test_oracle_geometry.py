@@ -176,7 +176,9 @@ def test_width_selection_reading(case):
     """Each ghost uses the first candidate width vector (entries assigned to
     axes in order of decreasing |grad phi_k|) whose upwind block lies in the
     box, holds only INSIDE/GHOST nodes, and whose row weight on G is at least
-    half of its total |weight| on the other ghosts of the block."""
+    its total |weight| on the block's other ghosts of different orientation
+    plus half of that on the ghosts oriented like G.  A second coding of
+    the rule in Python: an implementation cross-check, not a pin."""
     if case == "circle65":
         c = W.circle_65()
         d, N, phi = 2, c.N, c.phi
@@ -195,6 +197,8 @@ def test_width_selection_reading(case):
     ph = phi.reshape((N + 1,) * d)
     g = P.ghosts(0)
     crd = _coords(g["idx"], d, N)
+    gpos = {int(p): i for i, p in enumerate(g["idx"])}
+    strides = np.array([(N + 1) ** a for a in range(d)])
     used = set()
     for k in range(g["idx"].size):
         I = crd[k]
@@ -221,7 +225,8 @@ def test_width_selection_reading(case):
             return [(1 - t) * (2 - t) / 2, t * (2 - t), t * (t - 1) / 2][m]
 
         def dominant(wv):
-            # c_0 >= 1/2 of the |weights| on the other ghosts of the block (finest level)
+            # c_0 >= the |weights| on the block's other ghosts whose upwind
+            # signs differ from G's, plus half of those on ghosts oriented like G
             tau = [eta * abs(nrm[a]) if wv[a] >= 2 else 0.0 for a in range(d)]
             c0, off = None, 0.0
             for m in itertools.product(*[range(wv[a]) for a in range(d)]):
@@ -230,8 +235,9 @@ def test_width_selection_reading(case):
                 if not any(m):
                     c0 = wgt
                 elif cls[tuple(J[::-1])] == oracle.GHOST:
-                    off += abs(wgt)
-            return c0 >= 0.5 * off
+                    sJ = g["s"][gpos[int(np.dot(J, strides))], :d]
+                    off += abs(wgt) if np.any(sJ != s) else 0.5 * abs(wgt)
+            return c0 >= off
         chosen = None
         for cand in CANDS[d]:
             wv = [0] * d
