@@ -291,10 +291,35 @@ __device__ bool block_valid(const uint8_t *cls, int n, int d, const int I[3], co
     return true;
 }
 
-// c_0 >= f * (sum of |w_m| over the other GHOST nodes of the block); a
-// Neumann row also needs c_0 > 0
-__device__ bool block_dominant(const uint8_t *cls, int n, int d, const int I[3], const int s[3], const int w[3],
-                               const double tau[3], const double nd[3], int bc, double f) {
+__device__ int first_inside_neighbour(const uint8_t *cls, long long p, const int I[3], int N, int n, int d,
+                                      int &side);
+
+// upwind signs at node J (index q): s_k = +1 where the discrete gradient's
+// k-th component is >= 0; a zero gradient takes the direction from the first
+// INSIDE axis neighbour to J
+__device__ void upwind_signs(const double *phi, const uint8_t *cls, int N, int n, int d, double h, const int J[3],
+                             long long q, int sJ[3]) {
+    double g[3];
+    grad_at(phi, n, d, h, J, q, g);
+    double gn = 0.0;
+    for (int k = 0; k < d; k++) gn += g[k] * g[k];
+    gn = sqrt(gn);
+    sJ[0] = sJ[1] = sJ[2] = 1;
+    if (gn > 0.0) {
+        for (int k = 0; k < d; k++) sJ[k] = g[k] >= 0.0 ? 1 : -1;
+    } else {
+        int side = 0;
+        const int ax = first_inside_neighbour(cls, q, J, N, n, d, side);
+        for (int k = 0; k < d; k++) sJ[k] = (k == ax ? (double)side : 0.0) >= 0.0 ? 1 : -1;
+    }
+}
+
+// Admissibility beyond validity: c_0 >= sum of |w_m| over the block's other
+// GHOST nodes whose upwind signs differ from G's (every closed loop of ghost
+// rows holding each other has such a coupling) plus half the sum over those
+// oriented like G (one-way couplings); a Neumann row also needs c_0 > 0
+__device__ bool block_dominant(const double *phi, const uint8_t *cls, int N, int n, int d, double h, const int I[3],
+                               const int s[3], const int w[3], const double tau[3], const double nd[3], int bc) {
     double c0 = 0.0, off = 0.0;
     for (int m2 = 0; m2 < w[2]; m2++)
         for (int m1 = 0; m1 < w[1]; m1++)
@@ -302,13 +327,20 @@ __device__ bool block_dominant(const uint8_t *cls, int n, int d, const int I[3],
                 const int m[3] = {m0, m1, m2};
                 const int J[3] = {I[0] - m0 * s[0], I[1] - m1 * s[1], I[2] - m2 * s[2]};
                 const double wgt = row_weight(bc, w, tau, nd, m);
-                if (m0 == 0 && m1 == 0 && m2 == 0)
+                const long long q = index_of(J, n, d);
+                if (m0 == 0 && m1 == 0 && m2 == 0) {
                     c0 = wgt;
-                else if (cls[index_of(J, n, d)] == C_GHOST)
-                    off += fabs(wgt);
+                } else if (cls[q] == C_GHOST) {
+                    int sJ[3];
+                    upwind_signs(phi, cls, N, n, d, h, J, q, sJ);
+                    if (sJ[0] != s[0] || sJ[1] != s[1] || sJ[2] != s[2])
+                        off += fabs(wgt);
+                    else
+                        off += 0.5 * fabs(wgt);
+                }
             }
     if (bc == BCMG_BC_NEUMANN && !(c0 > 0.0)) return false;
-    return c0 >= f * off;
+    return c0 >= off;
 }
 
 __device__ double dtau_of(int d, double theta, int mode, double cnst) {
@@ -388,10 +420,10 @@ __device__ double dtau_neumann_of(int d, double theta, int mode, double cnst) {
 
 // One ghost G: discrete normal, upwind signs, axis dominance, root eta in
 // [0,1] of phi~(G - eta h n) = 0 (bracket at 1, 60 bisections), first
-// admissible stencil widths (in the box, INSIDE/GHOST nodes only, row weight
-// on G at least f times its |weight| on the block's other ghosts: f = 1/2 on
-// the finest level, 1 on coarse levels), Q, tau and dtau(theta~ = eta)
-// bounded by the row's Gauss-Seidel step 1/c_0.  Sec. 3.3 eqs. BCh, rel,
+// admissible stencil widths (in the box, INSIDE/GHOST nodes only, and
+// block_dominant), Q, tau and dtau(theta~) bounded by the row's Gauss-Seidel
+// step 1/c_0, with theta~ the normal distance from G to the row's
+// interpolation point.  Sec. 3.3 eqs. BCh, rel,
 // DtauOptTheta, Remark exptheta2D.  Neumann rows (bc): the derivative
 // coefficients gnd, blocks that may hold BOXDIR nodes, c_0 > 0, and with no
 // admissible block the difference (u_G - u_J)/h towards the first INSIDE axis
@@ -490,7 +522,7 @@ __global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level,
         if (!block_valid(cls, n, d, I, s, wt, bc)) continue;
         double tt[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < d; k++) tt[k] = wt[k] >= 2 ? eta * fabs(nv[k]) : 0.0;
-        if (!block_dominant(cls, n, d, I, s, wt, tt, nd, bc, level > 0 ? 1.0 : 0.5)) continue;
+        if (!block_dominant(phi, cls, N, n, d, h, I, s, wt, tt, nd, bc)) continue;
         w[0] = wt[0];
         w[1] = wt[1];
         w[2] = wt[2];
@@ -524,8 +556,23 @@ __global__ __launch_bounds__(128) void k_ghost_geometry(int d, int N, int level,
     gcode[gi] = code;
     geta[gi] = eta;
     gfb[gi] = fb;
-    double dt = bc == BCMG_BC_NEUMANN ? h * dtau_neumann_of(d, eta, dtau_mode, dtau_const)
-                                      : dtau_of(d, eta, dtau_mode, dtau_const);
+    // theta~: the distance along n from G to the point the row interpolates
+    // at; eta for a full-width row, eta * (sum of n_k^2 over the kept axes)
+    // for a row with width-1 axes (Q projected onto the span of the others)
+    double theta = eta;
+    if (axis < 0) {
+        bool shortened = false;
+        double nn2 = 0.0;
+        for (int k = 0; k < d; k++) {
+            if (w[k] >= 2)
+                nn2 += nv[k] * nv[k];
+            else
+                shortened = true;
+        }
+        if (shortened) theta = eta * nn2;
+    }
+    double dt = bc == BCMG_BC_NEUMANN ? h * dtau_neumann_of(d, theta, dtau_mode, dtau_const)
+                                      : dtau_of(d, theta, dtau_mode, dtau_const);
     if (dtau_mode != BCMG_DTAU_CONST) {  // at most the row's Gauss-Seidel step 1/c_0
         const int m0[3] = {0, 0, 0};
         const double c0 = row_weight(bc, w, tq, nd, m0);
