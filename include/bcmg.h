@@ -108,6 +108,28 @@ const char *bcmg_last_error(void);
 /* Library version (major*100 + minor). */
 int32_t bcmg_version(void);
 
+/*
+ * Device memory (not an operation of the paper: the plumbing that lets a
+ * host framework own HBM).  Every device allocation the library makes
+ * (problem hierarchies, batch tables, setup temporaries) goes through
+ *   alloc(bytes, stream, ctx) -> pointer, 256-byte aligned, or NULL on failure
+ *   free(ptr, bytes, stream, ctx)
+ * stream is the hipStream_t on which the memory is used: frees are
+ * stream-ordered (the memory may be handed out again only in that stream's
+ * order, as with hipFreeAsync), and alloc must return memory usable in that
+ * stream's order.  Both NULL (the default): a private stream-ordered pool per
+ * device that keeps freed memory for reuse; the process's default pool is
+ * not touched.  The source in effect when a problem is set up or a batch is
+ * created serves it until it is destroyed, so changing it later does not
+ * affect existing handles.  A NULL alloc result makes the calling setup or
+ * batch call fail with BCMG_ERR_OOM.  Giving one callback without the other
+ * is BCMG_ERR_INVALID.  The callbacks may be called from any thread that
+ * calls the library, and must be safe for that.
+ */
+typedef void *(*bcmg_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*bcmg_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+bcmg_status bcmg_set_allocator(bcmg_alloc_fn alloc, bcmg_free_fn free, void *ctx);
+
 /* Fill *opt with the defaults: V(2,1), coarsest N = 4, 100 cycles, FP64,
  * exponential-form dtau (Remark exptheta2D), K = 4, renormalised FW,
  * 128-node row segments. */
@@ -188,6 +210,7 @@ bcmg_status bcmg_vcycle(bcmg_problem *prob, double *u_dev);
 
 /* ||f - A u||_2 over INSIDE and GHOST rows of the finest level (host result). */
 bcmg_status bcmg_residual_norm(bcmg_problem *prob, const double *u_dev, double *norm_host);
+
 
 /*
  * Solve in place from the given u_dev until ||r^m|| <= rel_tol ||r^0||

@@ -1138,12 +1138,14 @@ int or_solve(or_problem *P, double *u, double tol, int max_cycles, double *hist)
     or_residual(P, 0, u, L->rhs, L->r);
     double r0 = or_norm(P, 0, L->r);
     if (hist) hist[0] = r0;
+    if (!isfinite(r0)) return -1; /* NaN or Inf in the data: diverged before any cycle */
     if (r0 == 0.0) return 0;
     for (int m = 1; m <= max_cycles; m++) {
         or_vcycle(P, u);
         or_residual(P, 0, u, L->rhs, L->r);
         double rm = or_norm(P, 0, L->r);
         if (hist) hist[m] = rm;
+        if (!isfinite(rm)) return -1;
         if (rm <= tol * r0) return m;
         /* divergence: non-finite, or growth past 1e3 x the larger of the first
          * two norms (the first cycle may raise the unscaled norm by O(h^-2)

@@ -80,7 +80,12 @@ PROTOTYPES = {
     "bcmg_timing_enable": (i32, [i32]),
     "bcmg_timing_read": (i32, [P(i64), P(dbl), P(i64)]),
     "bcmg_timing_sweeps": (i32, [vp, vp, i32, P(dbl)]),
+    "bcmg_set_allocator": (i32, [vp, vp, vp]),
 }
+
+# callback types of bcmg_set_allocator: alloc(bytes, stream, ctx) -> ptr, free(ptr, bytes, stream, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 
 
 def header_functions() -> list[str]:

@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libbcmg.so")
 SOURCES = {
     "api.hip": [],
     "cycle.hip": [],
+    "mem.hip": [],
     "setup.hip": ["-ffp-contract=off"],
 }
 

@@ -14,6 +14,7 @@
 
 #include "bcmg_internal.h"
 #include "launch.h"
+#include "mem.h"
 
 using namespace bcmg;
 
@@ -31,10 +32,12 @@ bcmg_status fail(bcmg_status s, const char *fmt, ...) {
     return s;
 }
 
-#define HIPCHK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return fail(BCMG_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? BCMG_ERR_OOM : BCMG_ERR_DEVICE, "%s: %s", #expr,   \
+                        hipGetErrorString(e_));                                                        \
     } while (0)
 
 // finest-level red-black sweep timing (bcmg_timing_*): while enabled, batches
@@ -83,6 +86,7 @@ struct bcmg_problem {
     int d = 0, N = 0, L = 0;
     bcmg_options opt{};
     hipStream_t stream = nullptr;
+    MemSource mem;            // where its device memory comes from (fixed at setup)
     int fp32 = 0;
     LevelH lev[kMaxLevels];
     double *rhs64 = nullptr;  // finest FP64 right-hand side (f on INSIDE, g(Q) on GHOST)
@@ -101,6 +105,7 @@ struct bcmg_problem {
     NormRange *d_range = nullptr;
     double *d_out = nullptr;
     Desc *h_stage = nullptr;  // pinned staging for descriptor uploads
+    int *d_lvl = nullptr;     // [1] index of the coarsest level (the coarse-solve list)
     bcmg_batch *solo = nullptr;
 };
 
@@ -126,6 +131,7 @@ struct Lists {
 
 struct bcmg_batch {
     int cap = 0;
+    MemSource mem;                      // where its device memory comes from (fixed at creation)
     hipStream_t stream = nullptr;       // private non-blocking stream (graph capture needs one)
     hipStream_t user_stream = nullptr;  // caller's stream, joined at every entry
     hipEvent_t join = nullptr;
@@ -205,14 +211,14 @@ thread_local PhaseTimer *t_phase = nullptr;
 // Zeroed device memory owned by the problem.  Small arrays are carved from
 // zeroed 4 MiB chunks (a problem has ~25 arrays per level: one allocation,
 // one fill and one free per chunk instead of per array); large arrays get
-// their own allocation.  All come from the device's stream-ordered pool.
+// their own allocation.  All come from the problem's memory source.
 constexpr size_t kArenaChunk = 4u << 20;
 
 static bcmg_status dalloc_raw(bcmg_problem *P, void **out, size_t bytes) {
-    hipError_t e = hipMallocAsync(out, bytes, P->stream);
+    hipError_t e = mem_alloc(P->mem, out, bytes, P->stream);
     if (e != hipSuccess) {
         *out = nullptr;
-        return fail(BCMG_ERR_OOM, "hipMallocAsync(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return fail(BCMG_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
     e = hipMemsetAsync(*out, 0, bytes, P->stream);
     if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -248,7 +254,7 @@ bcmg_status dalloc_t(bcmg_problem *P, T **out, size_t count) {
 }
 
 void free_problem_memory(bcmg_problem *P) {
-    for (void *p : P->allocs) hipFreeAsync(p, P->stream);
+    for (void *p : P->allocs) mem_free(P->mem, p, P->stream);
     P->allocs.clear();
     if (P->h_stage) hipHostFree(P->h_stage);
     P->h_stage = nullptr;
@@ -321,6 +327,32 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
     return D;
 }
 
+// Setup temporaries: returned to the memory source on every exit path.
+struct Temps {
+    hipStream_t s;
+    std::vector<void *> held;
+    explicit Temps(hipStream_t st) : s(st) {}
+    Temps(const Temps &) = delete;
+    Temps &operator=(const Temps &) = delete;
+    ~Temps() {
+        for (void *p : held) scratch_free(p, s);
+    }
+    template <typename T>
+    hipError_t get(T **p, size_t bytes) {
+        void *q = nullptr;
+        const hipError_t e = scratch_alloc(&q, bytes, s);
+        *p = (T *)q;
+        if (e == hipSuccess) held.push_back(q);
+        return e;
+    }
+    void put(void *p) {
+        auto it = std::find(held.begin(), held.end(), p);
+        if (it == held.end()) return;
+        held.erase(it);
+        scratch_free(p, s);
+    }
+};
+
 // ------------------------------------------------------------------ setup
 // Extension rows of a level: K sweeps of count, prefix sum and write; the
 // rows of the last sweep are kept (see k_erow).
@@ -332,15 +364,16 @@ bcmg_status build_ext_rows(bcmg_problem *P, LevelH &V, const int *bref, const do
         if ((st = dalloc_t(P, &V.eidx, 1)) || (st = dalloc_t(P, &V.ecoef, 1))) return st;
         return BCMG_OK;
     }
+    Temps tmp(s);
     int *counts = nullptr, *pptr = nullptr, *pidx = nullptr;
     double *pcf = nullptr;
-    HIPCHK(hipMallocAsync((void **)&counts, sizeof(int) * nb, s));
+    HIPCHK(tmp.get(&counts, sizeof(int) * nb));
     for (int j = 1; j <= K; j++) {
         int *optr = j == K ? V.eptr : nullptr;
-        if (!optr) HIPCHK(hipMallocAsync((void **)&optr, sizeof(int) * (nb + 1), s));
+        if (!optr) HIPCHK(tmp.get(&optr, sizeof(int) * (nb + 1)));
         launch_erow(P->d, V.N, V.cls, V.gidx, (int)V.ng, V.bidx, nb, bref, bw, j, pptr, pidx, pcf, nullptr, counts,
                     nullptr, nullptr, s);
-        launch_scan(counts, nb, optr, s);
+        HIPCHK(launch_scan(counts, nb, optr, s));
         HIPCHK(hipMemcpyAsync(h_total, optr + nb, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const size_t tot = (size_t)std::max(*h_total, 1);
@@ -352,21 +385,20 @@ bcmg_status build_ext_rows(bcmg_problem *P, LevelH &V, const int *bref, const do
             oidx = V.eidx;
             ocf = V.ecoef;
         } else {
-            HIPCHK(hipMallocAsync((void **)&oidx, sizeof(int) * tot, s));
-            HIPCHK(hipMallocAsync((void **)&ocf, sizeof(double) * tot, s));
+            HIPCHK(tmp.get(&oidx, sizeof(int) * tot));
+            HIPCHK(tmp.get(&ocf, sizeof(double) * tot));
         }
         launch_erow(P->d, V.N, V.cls, V.gidx, (int)V.ng, V.bidx, nb, bref, bw, j, pptr, pidx, pcf, optr, counts,
                     oidx, ocf, s);
         if (pptr) {
-            HIPCHK(hipFreeAsync(pptr, s));
-            HIPCHK(hipFreeAsync(pidx, s));
-            HIPCHK(hipFreeAsync(pcf, s));
+            tmp.put(pptr);
+            tmp.put(pidx);
+            tmp.put(pcf);
         }
         pptr = j == K ? nullptr : optr;
         pidx = j == K ? nullptr : oidx;
         pcf = j == K ? nullptr : ocf;
     }
-    HIPCHK(hipFreeAsync(counts, s));
     HIPCHK(hipStreamSynchronize(s));
     return BCMG_OK;
 }
@@ -381,16 +413,15 @@ bcmg_status build_needed_band(bcmg_problem *P, int l, int *counts, int *offsets,
     const size_t nb = (size_t)std::max<long long>(C.nb, 1);
     if ((st = dalloc_t(P, &C.bneed, nb))) return st;
     if (C.nb == 0) return BCMG_OK;
+    Temps tmp(s);
     uint8_t *mark = nullptr, *flag = nullptr;
-    HIPCHK(hipMallocAsync((void **)&mark, (size_t)C.nn, s));
-    HIPCHK(hipMallocAsync((void **)&flag, nb, s));
+    HIPCHK(tmp.get(&mark, (size_t)C.nn));
+    HIPCHK(tmp.get(&flag, nb));
     HIPCHK(hipMemsetAsync(mark, 0, (size_t)C.nn, s));
     launch_need_mark(P->d, F.N, F.cls, C.cls, mark, F.nn, s);
     launch_need_flags(C.bidx, (int)C.nb, mark, flag, s);
-    launch_compact(flag, (long long)C.nb, 1, counts, offsets, C.bneed, total_dev, s);
+    HIPCHK(launch_compact(flag, (long long)C.nb, 1, counts, offsets, C.bneed, total_dev, s));
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipFreeAsync(mark, s));
-    HIPCHK(hipFreeAsync(flag, s));
     HIPCHK(hipStreamSynchronize(s));
     C.nbn = *h_total;
     return BCMG_OK;
@@ -408,11 +439,12 @@ bcmg_status build_restrict_rows(bcmg_problem *P, int l, int *h_total) {
         if ((st = dalloc_t(P, &C.ridx, 1)) || (st = dalloc_t(P, &C.rcoef, 1))) return st;
         return BCMG_OK;
     }
+    Temps tmp(s);
     int *counts = nullptr;
-    HIPCHK(hipMallocAsync((void **)&counts, sizeof(int) * ng, s));
+    HIPCHK(tmp.get(&counts, sizeof(int) * ng));
     launch_rrow(P->d, C.N, C.gidx, ng, F.N, F.cls, F.gidx, (int)F.ng, F.bidx, (int)F.nb, F.eptr, F.eidx, F.ecoef,
                 P->opt.restrict_mode, nullptr, counts, nullptr, nullptr, s);
-    launch_scan(counts, ng, C.rptr, s);
+    HIPCHK(launch_scan(counts, ng, C.rptr, s));
     HIPCHK(hipMemcpyAsync(h_total, C.rptr + ng, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const size_t tot = (size_t)std::max(*h_total, 1);
@@ -420,7 +452,6 @@ bcmg_status build_restrict_rows(bcmg_problem *P, int l, int *h_total) {
     if ((st = dalloc_t(P, &C.ridx, tot)) || (st = dalloc_t(P, &C.rcoef, tot))) return st;
     launch_rrow(P->d, C.N, C.gidx, ng, F.N, F.cls, F.gidx, (int)F.ng, F.bidx, (int)F.nb, F.eptr, F.eidx, F.ecoef,
                 P->opt.restrict_mode, C.rptr, counts, C.ridx, C.rcoef, s);
-    HIPCHK(hipFreeAsync(counts, s));
     HIPCHK(hipStreamSynchronize(s));
     return BCMG_OK;
 }
@@ -434,12 +465,12 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     launch_classify(d, V.n, V.phi, V.cls, s);
     PHASE("classify", l);
     // counts of INSIDE and GHOST nodes, ghost list
-    launch_compact(V.cls, V.nn, C_INSIDE, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+    HIPCHK(launch_compact(V.cls, V.nn, C_INSIDE, scratch_counts, scratch_offsets, nullptr, total_dev, s));
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     V.ni = *h_total;
     if (l == 0 && V.ni == 0) return fail(BCMG_ERR_INVALID, "phi < 0 at no node: the domain holds no unknowns");
-    launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+    HIPCHK(launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, nullptr, total_dev, s));
     HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     V.ng = *h_total;
@@ -449,53 +480,47 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         (st = dalloc_t(P, &V.gn, 3 * ng)) || (st = dalloc_t(P, &V.gq, 3 * ng)) || (st = dalloc_t(P, &V.gnew, ng)))
         return st;
     if (P->opt.bc == BCMG_BC_NEUMANN && (st = dalloc_t(P, &V.gnd, 3 * ng))) return st;
-    launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s);
+    HIPCHK(launch_compact(V.cls, V.nn, C_GHOST, scratch_counts, scratch_offsets, V.gidx, total_dev, s));
     PHASE("ghost list", l);
     launch_ghost_geometry(d, V.N, l, V.h, V.phi, V.cls, V.gidx, (int)V.ng, P->opt.dtau_mode, P->opt.dtau_const,
                           P->opt.bc, V.gcode, V.gtau, V.gdtau, V.geta, V.gn, V.gq, V.gfb, V.gnd, s);
     PHASE("geometry", l);
     // extension band (only levels that restrict or receive a prolongation need it)
     {
+        Temps tmp(s);
         uint8_t *mark = nullptr;
-        void *tmp = nullptr;
-        HIPCHK(hipMallocAsync(&tmp, (size_t)V.nn, s));
-        mark = (uint8_t *)tmp;
+        HIPCHK(tmp.get(&mark, (size_t)V.nn));
         HIPCHK(hipMemsetAsync(mark, 0, (size_t)V.nn, s));
         launch_band_mark(d, V.N, V.cls, V.gidx, (int)V.ng, P->opt.ext_iters, mark, s);
-        launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, nullptr, total_dev, s);
+        HIPCHK(launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, nullptr, total_dev, s));
         HIPCHK(hipMemcpyAsync(h_total, total_dev, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         V.nb = *h_total;
         const size_t nb = (size_t)std::max<long long>(V.nb, 1);
         int *bref = nullptr;
         double *bw = nullptr;
-        if ((st = dalloc_t(P, &V.bidx, nb)) || (st = dalloc_t(P, &V.eptr, nb + 1))) {
-            hipFreeAsync(tmp, s);
-            return st;
-        }
-        HIPCHK(hipMallocAsync((void **)&bref, sizeof(int) * 3 * nb, s));
-        HIPCHK(hipMallocAsync((void **)&bw, sizeof(double) * 3 * nb, s));
-        launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, V.bidx, total_dev, s);
+        if ((st = dalloc_t(P, &V.bidx, nb)) || (st = dalloc_t(P, &V.eptr, nb + 1))) return st;
+        HIPCHK(tmp.get(&bref, sizeof(int) * 3 * nb));
+        HIPCHK(tmp.get(&bw, sizeof(double) * 3 * nb));
+        HIPCHK(launch_compact(mark, V.nn, 1, scratch_counts, scratch_offsets, V.bidx, total_dev, s));
         launch_band_records(d, V.N, V.h, V.phi, V.cls, V.bidx, (int)V.nb, bref, bw, s);
-        HIPCHK(hipFreeAsync(tmp, s));
+        tmp.put(mark);
         PHASE("band", l);
         st = build_ext_rows(P, V, bref, bw, h_total);
         PHASE("ext rows", l);
-        HIPCHK(hipFreeAsync(bref, s));
-        HIPCHK(hipFreeAsync(bw, s));
         if (st) return st;
     }
     // row segments of INSIDE/GHOST nodes
     {
+        Temps tmp(s);
         long long rows = 1;
         for (int k = 1; k < d; k++) rows *= V.n;
         int *ext = nullptr;
-        HIPCHK(hipMallocAsync((void **)&ext, sizeof(int) * 2 * rows, s));
+        HIPCHK(tmp.get(&ext, sizeof(int) * 2 * rows));
         launch_row_extent(d, V.n, V.cls, ext, ext + rows, s);
         std::vector<int> h(2 * rows);
         HIPCHK(hipMemcpyAsync(h.data(), ext, sizeof(int) * 2 * rows, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        HIPCHK(hipFreeAsync(ext, s));
         V.segs.clear();
         for (long long r = 0; r < rows; r++) {
             const int lo = h[r], hi = h[rows + r];
@@ -592,8 +617,10 @@ bcmg_status setup_step_tables(bcmg_problem *P) {
     if ((st = dalloc_t(P, &P->d_stepitems, all.size() + 1))) return st;
     HIPCHK(hipMemcpyAsync(P->d_stepitems, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice, P->stream));
     if ((st = dalloc_t(P, &P->d_step, P->L)) || (st = dalloc_t(P, &P->d_stepst, 1)) ||
-        (st = dalloc_t(P, &P->d_range, 1)) || (st = dalloc_t(P, &P->d_out, 1)))
+        (st = dalloc_t(P, &P->d_range, 1)) || (st = dalloc_t(P, &P->d_out, 1)) || (st = dalloc_t(P, &P->d_lvl, 1)))
         return st;
+    const int coarsest = P->L - 1;
+    HIPCHK(hipMemcpyAsync(P->d_lvl, &coarsest, sizeof(int), hipMemcpyHostToDevice, P->stream));
     SlotState one;
     memset(&one, 0, sizeof one);
     one.active = 1;
@@ -683,21 +710,10 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
     return BCMG_OK;
 }
 
-// Keep freed problem memory in the device pool instead of returning it to
-// the HIP runtime at every synchronisation (problems come and go when serving).
-static void keep_pool_memory() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    static std::mutex mu;
-    static bool done[64] = {false};
-    std::lock_guard<std::mutex> lock(mu);
-    if (dev < 0 || dev >= 64 || done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = UINT64_MAX;
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    done[dev] = true;
+bcmg_status bcmg_set_allocator(bcmg_alloc_fn alloc, bcmg_free_fn free, void *ctx) {
+    if ((alloc == nullptr) != (free == nullptr)) return fail(BCMG_ERR_INVALID, "give both callbacks or neither");
+    mem_set_source(alloc, free, ctx);
+    return BCMG_OK;
 }
 
 bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg_options *opt, void *stream,
@@ -717,7 +733,8 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
     P->N = N;
     P->opt = o;
     P->stream = (hipStream_t)stream;
-    keep_pool_memory();
+    P->mem = mem_current();
+    MemScope mem_scope(P->mem);  // setup temporaries come from the same source
     PhaseTimer timer(P->stream);
     t_phase = &timer;
     struct ClearPhase {
@@ -987,12 +1004,7 @@ bcmg_status bcmg_coarse_solve(bcmg_problem *P, double *u, const double *rhs) {
                            P->opt.bc == BCMG_BC_NEUMANN);
         }
     } else {
-        int lvl = l;
-        int *dl = nullptr;
-        HIPCHK(hipMallocAsync((void **)&dl, sizeof(int), P->stream));
-        HIPCHK(hipMemcpyAsync(dl, &lvl, sizeof(int), hipMemcpyHostToDevice, P->stream));
-        launch_coarse(0, P->d_step, dl, 1, P->d_stepst, P->stream);
-        HIPCHK(hipFreeAsync(dl, P->stream));
+        launch_coarse(0, P->d_step, P->d_lvl, 1, P->d_stepst, P->stream);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->stream));
@@ -1000,6 +1012,10 @@ bcmg_status bcmg_coarse_solve(bcmg_problem *P, double *u, const double *rhs) {
 }
 
 // ---------------------------------------------------------------- batches
+// device memory of a batch, ordered on its stream
+static hipError_t balloc(bcmg_batch *b, void **p, size_t bytes) { return mem_alloc(b->mem, p, bytes, b->stream); }
+static void bfree(bcmg_batch *b, void *p) { mem_free(b->mem, p, b->stream); }
+
 bcmg_status bcmg_batch_create(int32_t capacity, void *stream, bcmg_batch **out) {
     if (!out || capacity < 1 || capacity > 65536) return fail(BCMG_ERR_INVALID, "bad capacity");
     *out = nullptr;
@@ -1015,14 +1031,15 @@ bcmg_status bcmg_batch_create(int32_t capacity, void *stream, bcmg_batch **out) 
     b->u.assign(capacity, nullptr);
     b->rtol.assign(capacity, 0.0);
     b->hist_stride = 1001;
-    hipError_t e = hipMalloc((void **)&b->d_state, sizeof(SlotState) * capacity);
+    b->mem = mem_current();
+    hipError_t e = balloc(b, (void **)&b->d_state, sizeof(SlotState) * capacity);
     if (e == hipSuccess) e = hipMemsetAsync(b->d_state, 0, sizeof(SlotState) * capacity, b->stream);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_state, sizeof(SlotState) * capacity);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_rtol2, sizeof(double) * capacity);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_hist, sizeof(double) * capacity * b->hist_stride);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_ranges, sizeof(NormRange) * capacity);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_outer, sizeof(Desc) * capacity);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_eptr, sizeof(float *) * capacity);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->d_rtol2, sizeof(double) * capacity);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->d_hist, sizeof(double) * capacity * b->hist_stride);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->d_ranges, sizeof(NormRange) * capacity);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->d_outer, sizeof(Desc) * capacity);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->d_eptr, sizeof(float *) * capacity);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         bcmg_batch_destroy(b);
@@ -1051,20 +1068,20 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
     if (!b) return BCMG_OK;
     hipStreamSynchronize(b->stream);
     drop_graph(b);
-    hipFree(b->d_state);
+    bfree(b, b->d_state);
     if (b->h_state) hipHostFree(b->h_state);
-    hipFree(b->d_rtol2);
-    hipFree(b->d_hist);
-    hipFree(b->d_ranges);
-    hipFree(b->d_desc);
-    hipFree(b->d_outer);
-    hipFree(b->d_eptr);
-    hipFree(b->d_items);
-    hipFree(b->d_coarse);
-    hipFree(b->d_progs);
-    hipFree(b->d_lprogs);
-    hipFree(b->d_limage);
-    hipFree(b->d_partials);
+    bfree(b, b->d_rtol2);
+    bfree(b, b->d_hist);
+    bfree(b, b->d_ranges);
+    bfree(b, b->d_desc);
+    bfree(b, b->d_outer);
+    bfree(b, b->d_eptr);
+    bfree(b, b->d_items);
+    bfree(b, b->d_coarse);
+    bfree(b, b->d_progs);
+    bfree(b, b->d_lprogs);
+    bfree(b, b->d_limage);
+    bfree(b, b->d_partials);
     if (b->join) hipEventDestroy(b->join);
     if (b->stream) hipStreamDestroy(b->stream);
     delete b;
@@ -1308,25 +1325,25 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     // upload
     hipStream_t st = b->stream;
     if (descs.size() > b->desc_cap) {
-        hipFree(b->d_desc);
+        bfree(b, b->d_desc);
         b->desc_cap = std::max<size_t>(descs.size(), 2 * b->desc_cap);
-        HIPCHK(hipMalloc((void **)&b->d_desc, sizeof(Desc) * b->desc_cap));
+        HIPCHK(balloc(b, (void **)&b->d_desc, sizeof(Desc) * b->desc_cap));
     }
     if (items.size() + 1 > b->items_cap) {
-        hipFree(b->d_items);
+        bfree(b, b->d_items);
         b->items_cap = std::max<size_t>(items.size() + 1, 2 * b->items_cap);
-        HIPCHK(hipMalloc((void **)&b->d_items, sizeof(Item) * b->items_cap));
+        HIPCHK(balloc(b, (void **)&b->d_items, sizeof(Item) * b->items_cap));
     }
-    hipFree(b->d_coarse);
-    HIPCHK(hipMalloc((void **)&b->d_coarse, sizeof(int) * (coarse.size() + 1)));
-    hipFree(b->d_progs);
-    HIPCHK(hipMalloc((void **)&b->d_progs, sizeof(CoarseProg) * (progs.size() + 1)));
-    hipFree(b->d_lprogs);
-    HIPCHK(hipMalloc((void **)&b->d_lprogs, sizeof(LdsProg) * (lprogs.size() + 1)));
+    bfree(b, b->d_coarse);
+    HIPCHK(balloc(b, (void **)&b->d_coarse, sizeof(int) * (coarse.size() + 1)));
+    bfree(b, b->d_progs);
+    HIPCHK(balloc(b, (void **)&b->d_progs, sizeof(CoarseProg) * (progs.size() + 1)));
+    bfree(b, b->d_lprogs);
+    HIPCHK(balloc(b, (void **)&b->d_lprogs, sizeof(LdsProg) * (lprogs.size() + 1)));
     if (image_words + 1 > b->limage_cap) {
-        hipFree(b->d_limage);
+        bfree(b, b->d_limage);
         b->limage_cap = std::max(image_words + 1, 2 * b->limage_cap);
-        HIPCHK(hipMalloc((void **)&b->d_limage, sizeof(uint32_t) * b->limage_cap));
+        HIPCHK(balloc(b, (void **)&b->d_limage, sizeof(uint32_t) * b->limage_cap));
     }
     {
         size_t w = 0;
@@ -1337,9 +1354,9 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     }
     const size_t np = (size_t)nfseg + nfgch + 1;
     if (np > b->partials_cap) {
-        hipFree(b->d_partials);
+        bfree(b, b->d_partials);
         b->partials_cap = std::max(np, 2 * b->partials_cap);
-        HIPCHK(hipMalloc((void **)&b->d_partials, sizeof(double) * b->partials_cap));
+        HIPCHK(balloc(b, (void **)&b->d_partials, sizeof(double) * b->partials_cap));
     }
     hipStream_t cs = b->stream;
     if (!descs.empty())
@@ -1697,9 +1714,16 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     bcmg_status st = solo_attach(P, u, rtol);
     if (st) return st;
     bcmg_batch *b = P->solo;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.e0));
+    HIPCHK(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     HIPCHK(hipEventRecord(e0, b->stream));
     b->h_state[0].active = 1;
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
@@ -1734,8 +1758,6 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     bcmg_solve_stats s;
     if ((st = bcmg_batch_stats(b, 0, &s, hist))) return st;
     s.solve_ms = ms;
@@ -1805,9 +1827,16 @@ bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, d
     void *pu[1] = {scratch}, *pr[1] = {P->rhs64}, *px[1] = {V.r};
     if ((st = upload_step_descs(P, 0, 1, pu, pr, px))) return st;
     const Item *segs = P->d_stepitems + P->off_seg[0];
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.e0));
+    HIPCHK(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);  // warm
     HIPCHK(hipEventRecord(e0, P->stream));
     for (int i = 0; i < reps; i++) {
@@ -1818,8 +1847,6 @@ bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, d
     HIPCHK(hipEventSynchronize(e1));
     float t = 0.0f;
     HIPCHK(hipEventElapsedTime(&t, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     *ms = t;
     return BCMG_OK;
 }

@@ -727,13 +727,16 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
     if (out) out[s] = tot;
     SlotState &S = st[s];
     if (mode == 0) {
+        // a non-finite initial residual (a NaN or Inf in f, g(Q) or u0) ends
+        // the solve before any cycle, as a divergence
+        const bool finite = isfinite(tot);
         S.r0sq = tot;
         S.tolsq = rtol2[s] * tot;
         S.refsq = tot;
         S.lastsq = tot;
         S.cycles = 0;
-        S.status = BCMG_OK;
-        S.active = tot > 0.0 ? 1 : 0;
+        S.status = finite ? BCMG_OK : BCMG_ERR_DIVERGED;
+        S.active = finite && tot > 0.0 ? 1 : 0;
         if (hist) hist[(long long)s * hist_stride] = sqrt(tot);
     } else if (mode == 1) {
         const int c = S.cycles + 1;
@@ -741,10 +744,13 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
         S.lastsq = tot;
         if (hist && c < hist_stride) hist[(long long)s * hist_stride + c] = sqrt(tot);
         if (c == 1) S.refsq = fmax(S.r0sq, tot);
-        if (tot <= S.tolsq) {
+        if (!isfinite(tot)) {
+            S.active = 0;
+            S.status = BCMG_ERR_DIVERGED;
+        } else if (tot <= S.tolsq) {
             S.active = 0;
             S.status = BCMG_OK;
-        } else if (!isfinite(tot) || (c >= 2 && tot > 1e6 * S.refsq)) {
+        } else if (c >= 2 && tot > 1e6 * S.refsq) {
             S.active = 0;
             S.status = BCMG_ERR_DIVERGED;
         } else if (c >= S.max_cycles) {

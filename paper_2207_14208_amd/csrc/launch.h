@@ -52,8 +52,9 @@ void launch_classify(int d, int n, const double *phi, uint8_t *cls, hipStream_t 
 //   kind 0: cls[p] == value;  kind 1: mark[p] != 0 (mark passed as cls)
 // counts/offsets: scratch of compact_blocks(nn) ints each; total written to *total_dev
 int compact_blocks(long long nn);
-void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
-                    int *total_dev, hipStream_t s);
+// (fails only if its scan's temporary cannot be allocated; nothing is written then)
+hipError_t launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
+                          int *total_dev, hipStream_t s);
 void launch_ghost_geometry(int d, int N, int level, double h, const double *phi, const uint8_t *cls, const int *gidx,
                            int ng, int dtau_mode, double dtau_const, int bc, int *gcode, double *gtau, double *gdtau,
                            double *geta, double *gn, double *gq, int *gfb, double *gnd, hipStream_t s);
@@ -67,7 +68,7 @@ void launch_erow(int d, int N, const uint8_t *cls, const int *gidx, int ng, cons
 void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_t *cls_f, const int *gidx_f, int ngf,
                  const int *bidx_f, int nbf, const int *eptr_f, const int *eidx_f, const double *ecf_f,
                  int restrict_mode, const int *optr, int *counts, int *oidx, double *ocf, hipStream_t s);
-void launch_scan(const int *counts, int n, int *ptr, hipStream_t s);
+hipError_t launch_scan(const int *counts, int n, int *ptr, hipStream_t s);
 void launch_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c, uint8_t *mark_c, long long nnf,
                       hipStream_t s);
 void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag, hipStream_t s);

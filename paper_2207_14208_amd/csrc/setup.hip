@@ -11,6 +11,7 @@
 
 #include "bcmg_internal.h"
 #include "launch.h"
+#include "mem.h"
 
 namespace bcmg {
 
@@ -187,26 +188,30 @@ __global__ void k_scan_apply(const int *in, int n, const int *boff, int *out) {
         }
 }
 
-void scan_exclusive(const int *in, int n, int *out, int *total, hipStream_t s) {
+hipError_t scan_exclusive(const int *in, int n, int *out, int *total, hipStream_t s) {
     const int nb = (n + kTile - 1) / kTile;
     if (nb <= 1) {
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kBlock), 0, s, in, n, out, total);
-        return;
+        return hipSuccess;
     }
     int *tmp = nullptr;
-    if (hipMallocAsync((void **)&tmp, sizeof(int) * 2 * (size_t)nb, s) != hipSuccess) return;
+    hipError_t e = scratch_alloc((void **)&tmp, sizeof(int) * 2 * (size_t)nb, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, tmp);
-    scan_exclusive(tmp, nb, tmp + nb, total, s);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, n, tmp + nb, out);
-    hipFreeAsync(tmp, s);
+    e = scan_exclusive(tmp, nb, tmp + nb, total, s);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, n, tmp + nb, out);
+    scratch_free(tmp, s);
+    return e;
 }
 
-void launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
-                    int *total_dev, hipStream_t s) {
+hipError_t launch_compact(const uint8_t *cls, long long nn, uint8_t value, int *counts, int *offsets, int *out,
+                          int *total_dev, hipStream_t s) {
     const int nb = compact_blocks(nn);
     hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, counts);
-    scan_exclusive(counts, nb, offsets, total_dev, s);
+    const hipError_t e = scan_exclusive(counts, nb, offsets, total_dev, s);
+    if (e != hipSuccess) return e;
     if (out) hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, s, cls, nn, value, offsets, out);
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------- ghost geometry
@@ -917,7 +922,7 @@ void launch_rrow(int d, int Nc, const int *gidx_c, int ngc, int Nf, const uint8_
 }
 
 // Exclusive prefix sum of n counts into ptr[0..n-1], total into ptr[n].
-void launch_scan(const int *counts, int n, int *ptr, hipStream_t s) { scan_exclusive(counts, n, ptr, ptr + n, s); }
+hipError_t launch_scan(const int *counts, int n, int *ptr, hipStream_t s) { return scan_exclusive(counts, n, ptr, ptr + n, s); }
 
 // Coarse OUTSIDE nodes that the prolongation reads: the corners of the
 // coarse cells holding fine INSIDE / GHOST nodes.  Only these band nodes

@@ -143,7 +143,11 @@ class Server:
                 continue
             slot = self.backend.add(handle)
             self.resident[slot] = req
-            self.bytes_of[slot] = need
+            # the reservation was an estimate (an upper bound); from now on the
+            # problem counts with the bytes it actually holds
+            real = self.backend.bytes(handle) if hasattr(self.backend, "bytes") else need
+            self.used_bytes += real - need
+            self.bytes_of[slot] = real
             self.stats.peak_slots = max(self.stats.peak_slots, len(self.resident))
 
     def step(self, now_fn) -> None:
@@ -272,6 +276,12 @@ class GPUBackend:
         info = G.level_info(0)
         return (req.rid, G, u, info["n_inside"] + info["n_ghost"])
 
+    def bytes(self, handle) -> int:
+        """Device bytes the prepared problem holds (bcmg_problem_bytes), plus
+        its solution array."""
+        _, G, u, _ = handle
+        return G.device_bytes() + u.numel() * u.element_size()
+
     def add(self, handle) -> int:
         _, G, u, _ = handle
         slot = self.batch.add(G, u, self.tol)
@@ -352,6 +362,7 @@ def bench(args) -> dict:
         "converged": len(ok), "failed": len(meas) - len(ok), "rejected": len(st.rejected),
         "retried_with_const_dtau": sum(1 for r in meas if r.attempts > 1),
         "peak_slots": st.peak_slots, "peak_bytes": st.peak_bytes,
+        "peak_torch_allocated_bytes": int(be.torch.cuda.max_memory_allocated()),
         "wall_s": {"span": span, "steps": st.t_step, "join": st.t_join, "retire": st.t_retire,
                    "prepare_worker": st.t_prepare, "batch_steps": st.steps},
     }

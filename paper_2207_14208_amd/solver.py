@@ -30,6 +30,61 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+# ---------------------------------------------------------------- device memory
+# In a torch process the library's device memory comes from torch's caching
+# allocator (bcmg_set_allocator), so one pool owns HBM and torch's memory
+# statistics include the solver's hierarchies.
+_alloc_cbs = None
+_exiting = False
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None  # the library reports BCMG_ERR_OOM
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device allocations through torch's caching
+    allocator (enable) or back to its private pool.  Handles keep the source
+    they were created with."""
+    global _alloc_cbs
+    if enable:
+        if _alloc_cbs is None:
+            _alloc_cbs = (N.ALLOC_FN(_torch_alloc), N.FREE_FN(_torch_free))
+        check(lib().bcmg_set_allocator(C.cast(_alloc_cbs[0], C.c_void_p), C.cast(_alloc_cbs[1], C.c_void_p), None))
+    else:
+        check(lib().bcmg_set_allocator(None, None, None))
+
+
+def _mark_exit():
+    # handles still alive at interpreter exit are not destroyed: their frees
+    # would call back into a torch that is shutting down
+    global _exiting
+    _exiting = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_mark_exit)
+_torch_allocator_on = False
+
+
+def _ensure_torch_allocator():
+    global _torch_allocator_on
+    if not _torch_allocator_on:
+        use_torch_allocator(True)
+        _torch_allocator_on = True
+
+
 @dataclass
 class SolveStats:
     cycles: int
@@ -61,6 +116,7 @@ class Problem:
         if phi_d.numel() != (N_ + 1) ** dim:
             raise ValueError("phi has the wrong size")
         h = C.c_void_p()
+        _ensure_torch_allocator()
         check(lib().bcmg_setup(dim, N_, _ptr(phi_d), C.byref(self.opts), _stream_handle(stream), C.byref(h)))
         self.h = h
         n = C.c_int32()
@@ -70,7 +126,8 @@ class Problem:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().bcmg_destroy(self.h)
+            if not _exiting:
+                lib().bcmg_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -185,6 +242,7 @@ class Batch:
 
     def __init__(self, capacity: int, stream=None):
         h = C.c_void_p()
+        _ensure_torch_allocator()
         check(lib().bcmg_batch_create(capacity, _stream_handle(stream), C.byref(h)))
         self.h = h
         self.capacity = capacity
@@ -223,7 +281,8 @@ class Batch:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().bcmg_batch_destroy(self.h)
+            if not _exiting:
+                lib().bcmg_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

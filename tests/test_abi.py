@@ -39,3 +39,16 @@ def test_host_only_calls():
 def test_unknown_option_rejected():
     with pytest.raises(TypeError):
         N.default_options(bogus=1)
+
+
+def test_set_allocator_arguments():
+    """bcmg_set_allocator takes both callbacks or neither (host-only call)."""
+    L = N.lib()
+    cb_a = N.ALLOC_FN(lambda n, s, c: None)
+    cb_f = N.FREE_FN(lambda p, n, s, c: None)
+    a = C.cast(cb_a, C.c_void_p)
+    f = C.cast(cb_f, C.c_void_p)
+    assert L.bcmg_set_allocator(a, None, None) == N.ERR_INVALID
+    assert L.bcmg_set_allocator(None, f, None) == N.ERR_INVALID
+    assert L.bcmg_set_allocator(a, f, None) == N.OK
+    assert L.bcmg_set_allocator(None, None, None) == N.OK

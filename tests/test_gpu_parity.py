@@ -410,3 +410,33 @@ def test_empty_and_non_finite_level_sets_are_rejected():
         with pytest.raises(NAT.BcmgError) as e:
             Problem(2, 16, phi)
         assert e.value.status == NAT.ERR_INVALID
+
+
+@pytest.mark.parametrize("where", ["f", "gq", "inf_f"])
+def test_non_finite_data_reported_as_divergence(where):
+    """A NaN (or Inf) in f at an INSIDE node or in g(Q) makes the initial
+    residual non-finite: the oracle and the GPU both end the solve before
+    any cycle with a divergence, and the caller's u is left as it was."""
+    Problem = _gpu()
+    from paper_2207_14208_amd import _native as NAT
+    c = W.circle_65()
+    O = oracle.Problem(c.d, c.N, c.phi)
+    G = Problem(c.d, c.N, c.phi)
+    cls = O.classes(0)
+    f = c.f.copy()
+    gq = W.points_eval(c.g, O.ghosts(0)["q"], c.d)
+    bad = np.inf if where == "inf_f" else np.nan
+    if where == "gq":
+        gq[len(gq) // 2] = bad
+    else:
+        f[np.nonzero(cls == oracle.INSIDE)[0][100]] = bad
+    O.set_rhs(f, gq)
+    G.set_data(f, gq)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    it, ho = O.solve(uo, 1e-10)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    before = ug.cpu().numpy().copy()
+    st, hg = G.solve(ug, 1e-10)
+    assert it == -1 and len(ho) == 1
+    assert st.status == NAT.ERR_DIVERGED and st.cycles == 0, st
+    assert np.array_equal(ug.cpu().numpy(), before)

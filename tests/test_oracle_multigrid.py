@@ -322,3 +322,17 @@ def test_circle_optimal_beats_constant():
     assert abs(c128 - GOLD["rho_const_2d_dirichlet"]["value"]) <= 0.1
     assert o64 < c64 and o128 < c128
     assert o128 < 0.25
+
+
+def test_non_finite_initial_residual_is_divergence():
+    """A NaN in the data makes the initial residual non-finite: the solve
+    reports divergence before any cycle and leaves u unchanged."""
+    c = W.circle_65()
+    P = oracle.Problem(c.d, c.N, c.phi)
+    f = c.f.copy()
+    f[np.nonzero(P.classes(0) == oracle.INSIDE)[0][10]] = np.nan
+    P.set_rhs(f, W.points_eval(c.g, P.ghosts(0)["q"], c.d))
+    u = np.zeros(P.nodes(0))
+    it, hist = P.solve(u, 1e-10)
+    assert it == -1 and len(hist) == 1 and np.isnan(hist[0])
+    assert np.all(u == 0.0)
