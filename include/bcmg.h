@@ -211,6 +211,22 @@ bcmg_status bcmg_vcycle(bcmg_problem *prob, double *u_dev);
 /* ||f - A u||_2 over INSIDE and GHOST rows of the finest level (host result). */
 bcmg_status bcmg_residual_norm(bcmg_problem *prob, const double *u_dev, double *norm_host);
 
+/*
+ * bcmg_residual_norm for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, hosts that forbid allocation):
+ * the same kernels and summation order, so the same result, but the norm's
+ * partial sums, range record and result live in a static device array of the
+ * library (4 MiB plus 32 bytes per device, held until the process ends); the
+ * call allocates nothing.  It writes the residual into the problem's own
+ * finest-level scratch, as bcmg_residual_norm does, and synchronises the
+ * problem's stream.  Limit: at most 524287 row segments plus ghost chunks on
+ * the finest level (bcmg_level_info; a 513^3 flower has about 8e4), else
+ * BCMG_ERR_INVALID.  Every call on one device shares that device's array:
+ * calls that overlap on one device (other threads or streams) race and must
+ * be serialised by the caller.  BCMG_ERR_STATE if the device current at the
+ * call is not the one the problem was set up on.
+ */
+bcmg_status bcmg_residual_norm_noalloc(bcmg_problem *prob, const double *u_dev, double *norm_host);
 
 /*
  * Solve in place from the given u_dev until ||r^m|| <= rel_tol ||r^0||

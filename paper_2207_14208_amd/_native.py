@@ -59,6 +59,7 @@ PROTOTYPES = {
     "bcmg_fill_boundary": (i32, [vp, vp, vp]),
     "bcmg_vcycle": (i32, [vp, vp]),
     "bcmg_residual_norm": (i32, [vp, vp, P(dbl)]),
+    "bcmg_residual_norm_noalloc": (i32, [vp, vp, P(dbl)]),
     "bcmg_solve": (i32, [vp, vp, dbl, P(bcmg_solve_stats), vp]),
     "bcmg_level_smooth": (i32, [vp, i32, vp, vp, i32]),
     "bcmg_level_residual": (i32, [vp, i32, vp, vp, vp, P(dbl)]),

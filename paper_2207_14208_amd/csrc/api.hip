@@ -87,6 +87,7 @@ struct bcmg_problem {
     bcmg_options opt{};
     hipStream_t stream = nullptr;
     MemSource mem;            // where its device memory comes from (fixed at setup)
+    int device = 0;           // device current at setup
     int fp32 = 0;
     LevelH lev[kMaxLevels];
     double *rhs64 = nullptr;  // finest FP64 right-hand side (f on INSIDE, g(Q) on GHOST)
@@ -645,6 +646,38 @@ bcmg_status upload_step_descs(bcmg_problem *P, int l0, int cnt, void *const *u, 
     return BCMG_OK;
 }
 
+// Scratch of bcmg_residual_norm_noalloc: the norm's partial sums, its range
+// record and its result, in a static device array (each device that runs the
+// library holds one copy until the process ends).  Host code uses the address
+// hipGetSymbolAddress gives on each device, never the array's name.
+constexpr long long kNoAllocPartials = 1 << 19;
+constexpr long long kNoAllocWords = kNoAllocPartials + 4;  // + NormRange (2 words) + result + pad
+static __device__ __align__(256) double scratch[kNoAllocWords];
+
+struct NoAllocScratch {
+    std::mutex mu;
+    double *ptr[64] = {};
+} g_noalloc;
+
+// Look up (once per device, with that device current) the device address of
+// the scratch array.
+bcmg_status noalloc_scratch_init(int dev) {
+    if (dev < 0 || dev >= 64) return fail(BCMG_ERR_DEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc.mu);
+    if (g_noalloc.ptr[dev]) return BCMG_OK;
+    double *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(BCMG_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_noalloc.ptr[dev] = p;
+    return BCMG_OK;
+}
+
+double *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc.mu);
+    return g_noalloc.ptr[dev];
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -734,7 +767,12 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
     P->opt = o;
     P->stream = (hipStream_t)stream;
     P->mem = mem_current();
+    P->device = P->mem.device;
     MemScope mem_scope(P->mem);  // setup temporaries come from the same source
+    if ((st = noalloc_scratch_init(P->device))) {
+        delete P;
+        return st;
+    }
     PhaseTimer timer(P->stream);
     t_phase = &timer;
     struct ClearPhase {
@@ -1798,6 +1836,40 @@ bcmg_status bcmg_residual_norm(bcmg_problem *P, const double *u, double *norm_ho
     HIPCHK(hipMemcpyAsync(&v, P->d_out, sizeof v, hipMemcpyDeviceToHost, P->stream));
     HIPCHK(hipStreamSynchronize(P->stream));
     (void)st;
+    *norm_host = std::sqrt(v);
+    return BCMG_OK;
+}
+
+bcmg_status bcmg_residual_norm_noalloc(bcmg_problem *P, const double *u, double *norm_host) {
+    if (!P || !u || !norm_host) return fail(BCMG_ERR_INVALID, "null argument");
+    const long long need = (long long)P->n_seg[0] + P->n_gch[0] + 1;
+    if (need > kNoAllocPartials)
+        return fail(BCMG_ERR_INVALID,
+                    "finest level has %lld row segments and ghost chunks; bcmg_residual_norm_noalloc holds at most %lld "
+                    "(use bcmg_residual_norm)",
+                    need - 1, kNoAllocPartials - 1);
+    double *base = noalloc_scratch(P->device);
+    if (!base) return fail(BCMG_ERR_STATE, "scratch address not set up on device %d", P->device);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(BCMG_ERR_STATE, "device %d is current, the problem lives on %d", dev, P->device);
+    double *partials = base;
+    NormRange *range = (NormRange *)(base + kNoAllocPartials);
+    double *result = base + kNoAllocPartials + 2;
+    // the descriptor goes to the problem's own step table, the range record to
+    // the scratch, both from host stack memory (no staging buffer)
+    const Desc D = make_desc(P, 0, (void *)u, P->rhs64, P->r64, 0);
+    const NormRange R{0, P->n_seg[0], 0, P->n_gch[0]};
+    HIPCHK(hipMemcpyAsync(P->d_step, &D, sizeof D, hipMemcpyHostToDevice, P->stream));
+    HIPCHK(hipMemcpyAsync(range, &R, sizeof R, hipMemcpyHostToDevice, P->stream));
+    launch_residual(P->d, 0, 0, 1, P->d_step, P->d_stepitems + P->off_seg[0], P->n_seg[0],
+                    P->d_stepitems + P->off_gch[0], P->n_gch[0], P->d_stepst, partials, P->stream,
+                    P->opt.bc == BCMG_BC_NEUMANN);
+    launch_norm_finish(range, 1, partials, P->n_seg[0], P->d_stepst, nullptr, nullptr, 0, 2, result, P->stream);
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, result, sizeof v, hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipStreamSynchronize(P->stream));
+    HIPCHK(hipGetLastError());
     *norm_host = std::sqrt(v);
     return BCMG_OK;
 }
