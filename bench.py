@@ -1,22 +1,26 @@
 """Benchmark: unknowns solved per second to a relative residual of 1e-10.
 
-Workload (one GPU): 3D Poisson on the flower domain
+Default workload (one GPU): 3D Poisson on the flower domain
 phi = r - (0.5 + 0.1 sin(3 theta) sin(4 varphi)) about (0.01, 0.01, 0.01) in
-[-1,1]^3 with 257^3 nodes, exact solution exp(x+y+z) (f and the Dirichlet
-data from it), FP64, V(2,1) red-black Gauss-Seidel cycles with distance-
-dependent ghost relaxation down to a 5^3 grid, solved from u = 0 to
-||r|| <= 1e-10 ||r0||.  Synthetic input generated on the host, copied to HBM
-before the timed region; setup (classification, ghost geometry, extension
-band, coarse inverse) is done once and reported separately.
+[-1,1]^3 with 513^3 nodes, exact solution exp(x+y+z) (f and the Dirichlet
+data from it), V(2,1) red-black Gauss-Seidel cycles with distance-dependent
+ghost relaxation down to a 5^3 grid, solved from u = 0 to
+||r|| <= 1e-10 ||r0||, once in FP64 and once in mixed precision (FP32 cycle
+on the correction, FP64 residual, update and coarse solve).  The headline
+value is the mixed-precision rate; the FP64 rate is reported beside it.
+Synthetic input generated on the host, copied to HBM before the timed
+region; setup (classification, ghost geometry, extension band, coarse
+inverse) is done once per problem and reported separately.
+--workload flower257 runs the 257^3 FP64 solve alone.
 
 A step is one full solve (V-cycles replayed from a captured hipGraph).  After
 the timed steps, HIP events on the solver's stream time the finest-level
-red-black sweep for the roofline line: around a burst of 100 back-to-back
-red + black sweeps on a copy of the solution (the roofline figure), and
+red-black sweep of the headline problem for the roofline line: around a
+burst of 100 back-to-back red + black sweeps (the roofline figure), and
 around every finest-level colour launch of solves run as direct launches
 (events recorded inside a graph cannot be timed; reported beside it).  The
-oracle (plain C, FP64) is timed on a bounded sample of the same workload for
-the CPU baseline.
+oracle (plain C, FP64, one thread) is timed on a bounded sample of the same
+problem for the CPU baseline.
 
 Prints one JSON line.
 """
@@ -32,8 +36,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rb_sweep_flower257_fp64_traffic.json")
+# HBM traffic of the finest sweep per workload, from committed counter runs
+TRAFFIC_FILES = {
+    (512, "mixed"): os.path.join(ROOT, "profiles", "k_rb_sweep_flower513_mixed_traffic.json"),
+    (256, "fp64"): os.path.join(ROOT, "profiles", "k_rb_sweep_flower257_fp64_traffic.json"),
+}
 KERNEL_SRC = [os.path.join(ROOT, "paper_2207_14208_amd", "csrc", f) for f in ("seg.h", "rb_sweep.h")]
+METRIC = "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms"
 
 
 def kernel_fingerprint(paths=KERNEL_SRC) -> str:
@@ -50,18 +59,21 @@ def kernel_fingerprint(paths=KERNEL_SRC) -> str:
     return hashlib.sha256(re.sub(r"\s+", "", src).encode()).hexdigest()
 
 
-def stored_traffic(N: int, fp64: bool):
+def stored_traffic(N: int, precision: str):
     """HBM bytes per finest-level red-black launch, from the committed
     FETCH_SIZE and WRITE_SIZE counter runs (scaled by the same counters on a
-    plain copy kernel of known size); None when the workload differs or the
-    kernel source has changed since the counters were taken."""
+    plain copy kernel of known size); None when no record exists for the
+    workload or the kernel source has changed since the counters were taken."""
+    path = TRAFFIC_FILES.get((N, precision))
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
         fp = kernel_fingerprint()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_fingerprint") != fp or rec.get("N") != N or not fp64:
+    if rec.get("kernel_source_fingerprint") != fp or rec.get("N") != N or rec.get("precision") != precision:
         return None
     return rec["bytes_per_launch"]
 
@@ -71,17 +83,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--N", type=int, default=256, help="intervals per axis (257^3 nodes by default)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--N", type=int, default=0, help="intervals per axis (default: 512 for flower513, 256 for flower257)")
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle V-cycles in the CPU sample")
-    ap.add_argument("--workload", choices=["flower257", "mixed513", "batched", "served", "rho_sweep", "neumann"],
-                    default="flower257",
-                    help="flower257: the headline single solve; mixed513: 513^3 FP64 against mixed precision; "
-                         "batched: 512 2D star problems; served: the continuous-batching request loop; "
-                         "rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: the "
-                         "257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
+    ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle V-cycles in the CPU sample (default: 1 at "
+                                                                "513^3, 2 below)")
+    ap.add_argument("--workload", choices=["flower513", "flower257", "batched", "served", "rho_sweep", "neumann"],
+                    default="flower513",
+                    help="flower513: the 513^3 flower, FP64 against mixed precision (the headline); flower257: "
+                         "the 257^3 FP64 solve; batched: 512 2D star problems; served: the continuous-batching "
+                         "request loop; rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: "
+                         "the 257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     ap.add_argument("--prepare-workers", type=int, default=2,
@@ -100,14 +113,18 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
-    if args.workload == "mixed513":
-        return bench_mixed(args)
     if args.workload == "rho_sweep":
         return bench_rho_sweep(args)
     if args.workload == "served":
         return bench_served(args)
     if args.workload == "neumann":
         return bench_neumann(args)
+    return bench_flower(args)
+
+
+def bench_flower(args):
+    """The flower solves: 513^3 FP64 against mixed precision (headline:
+    mixed), or 257^3 in one precision."""
     import numpy as np
     import torch
 
@@ -125,130 +142,154 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    N = args.N
-    prec = NAT.MIXED if args.precision == "mixed" else NAT.FP64
+    big = args.workload == "flower513"
+    N = args.N or (512 if big else 256)
+    names = ["fp64", "mixed"] if big else [args.precision]
+    head = names[-1]
+    prec_of = {"fp64": NAT.FP64, "mixed": NAT.MIXED}
 
     case = W.flower3d(N)
     phi = torch.from_numpy(case.phi).to(dev)
     f = torch.from_numpy(case.f).to(dev)
+    ue = torch.from_numpy(W.sample(3, N, case.u_exact)).to(dev)
     torch.cuda.synchronize()
 
-    def make_problem():
+    def make_problem(prec):
         G = Problem(3, N, phi, precision=prec, max_cycles=args.max_cycles)
         q = G.ghost_info(0)["q"]
         gq = torch.exp(q[:, 0] + q[:, 1] + q[:, 2])  # Dirichlet data g = exp(x+y+z) at the projections Q
         G.set_data(f, gq)
         return G
 
-    # the first setup in a process also loads the kernels (the library's and
-    # torch's): time a second one
-    make_problem().close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    G = make_problem()
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    info = G.level_info(0)
-    unknowns = info["n_inside"] + info["n_ghost"]
-    u = torch.zeros(G.nodes, dtype=torch.float64, device=dev)
-
-    def step():
-        u.zero_()
-        st, hist = G.solve(u, 1e-10)
-        return st, hist
-
-    for _ in range(args.warmup):
-        st, hist = step()
-    torch.cuda.synchronize()
-    times = []
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        st, hist = step()
+    res, sols = {}, {}
+    G_head = u_head = None
+    for name in names:
+        prec = prec_of[name]
+        # the first setup in a process also loads the kernels (the library's
+        # and torch's): time a second one
+        make_problem(prec).close()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_all
-    # a reduced --max-cycles (counter collection) may stop before the tolerance
-    assert st.status == 0 or (st.status == NAT.ERR_NOT_CONVERGED and st.cycles == args.max_cycles), \
-        f"solve failed: {st}"
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = unknowns * args.steps / elapsed
+        t0 = time.perf_counter()
+        G = make_problem(prec)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        info = G.level_info(0)
+        unknowns = info["n_inside"] + info["n_ghost"]
+        u = torch.zeros(G.nodes, dtype=torch.float64, device=dev)
 
-    # error against the exact solution (sanity: second-order discretisation)
-    ue = torch.from_numpy(W.sample(3, N, case.u_exact)).to(dev)
-    cls = G.classes(0)
-    inside = cls == NAT.INSIDE
-    err_inf = (u[inside] - ue[inside]).abs().max().item()
+        def step():
+            u.zero_()
+            return G.solve(u, 1e-10)
 
-    # roofline of the finest-level red-black sweep (one colour).  HIP events on
-    # the solver's stream: (1) around a burst of back-to-back sweeps on a copy
-    # of the solution (the kernel's own cadence, used for the roofline), and
-    # (2) around every finest-level colour launch of full solves run as direct
-    # launches (includes the launch gaps between the cycle's kernels)
+        for _ in range(args.warmup):
+            st, hist = step()
+        torch.cuda.synchronize()
+        times = []
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            st, hist = step()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_all
+        # a reduced --max-cycles (counter collection) may stop before the tolerance
+        assert st.status == 0 or (st.status == NAT.ERR_NOT_CONVERGED and st.cycles == args.max_cycles), \
+            f"{name} solve failed: {st}"
+        cls = G.classes(0)
+        inside = cls == NAT.INSIDE
+        unk = inside | (cls == NAT.GHOST)
+        res[name] = {
+            "unknowns_per_s": unknowns * args.steps / elapsed, "ms_per_solve": elapsed * 1e3 / args.steps,
+            "solve_ms_median": float(np.median(times) * 1e3), "solve_ms_device": st.solve_ms,
+            "cycles": st.cycles, "rel_residual": st.r_final / st.r0,
+            "rho_last": float(hist[-1] / hist[-2]) if len(hist) > 2 else None,
+            "setup_ms": setup_ms, "max_err_vs_exact": (u[inside] - ue[inside]).abs().max().item(),
+            "unknowns": unknowns, "n_inside": info["n_inside"], "n_ghost": info["n_ghost"], "levels": G.levels,
+        }
+        sols[name] = u[unk].clone()
+        if name == head:
+            G_head, u_head = G, u
+        else:
+            G.close()
+            del G
+            torch.cuda.empty_cache()
+    if big:
+        res["mixed"]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
+                                                sols["fp64"].abs().max()).item()
+    del sols
+
+    # roofline of the headline problem's finest-level red-black sweep (one
+    # colour).  HIP events on the solver's stream: (1) around a burst of
+    # back-to-back sweeps (the kernel's own cadence, used for the roofline),
+    # and (2) around every finest-level colour launch of full solves run as
+    # direct launches (includes the launch gaps between the cycle's kernels)
+    G, u = G_head, u_head
     timing_enable(True)
-    n_rep = max(2, min(args.steps, 5))
-    for _ in range(n_rep):
-        step()
+    for _ in range(max(2, min(args.steps, 5))):
+        u.zero_()
+        G.solve(u, 1e-10)
     torch.cuda.synchronize()
     launches, tot_ms, nodes = timing_read()
     timing_enable(False)
     in_solve_us = tot_ms / max(launches, 1) * 1e3
-    esz = 8 if prec == NAT.FP64 else 4
+    esz = 8 if head == "fp64" else 4
     alg_bytes = 1.5 * esz * nodes  # per colour launch: read f and write u at its nodes, read u of the other colour
     reps = 100
-    if prec == NAT.FP64:
-        burst_ms = G.timing_sweeps(u, reps)
-        avg_s = burst_ms / (2 * reps) / 1e3
-    else:
-        avg_s = in_solve_us / 1e6
+    burst_ms = G.timing_sweeps(u, reps)
+    avg_s = burst_ms / (2 * reps) / 1e3
     achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-
+    r = res[head]
     out = {
-        "metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
-        "value": value,
+        "metric": METRIC,
+        "value": r["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == NAT.FP64 else "f32+f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic (analytic level set and manufactured solution)",
         "config": {
-            "workload": f"3D flower, {N + 1}^3 nodes, u=exp(x+y+z), {args.precision.upper()} V(2,1) RB-GS to rel. residual 1e-10",
+            "workload": (f"3D flower, {N + 1}^3 nodes, u=exp(x+y+z), FP64 vs mixed-precision V(2,1) RB-GS to rel. "
+                         f"residual 1e-10 (value: mixed)") if big else
+                        f"3D flower, {N + 1}^3 nodes, u=exp(x+y+z), {head.upper()} V(2,1) RB-GS to rel. residual 1e-10",
             "nodes_per_axis": N + 1,
-            "unknowns": unknowns,
-            "n_inside": info["n_inside"],
-            "n_ghost": info["n_ghost"],
-            "levels": G.levels,
-            "cycles": st.cycles,
-            "rho_last": float(hist[-1] / hist[-2]) if len(hist) > 2 else None,
-            "setup_ms": setup_ms,
-            "solve_ms_median": float(np.median(times) * 1e3),
-            "solve_ms_device": st.solve_ms,
-            "max_err_vs_exact": err_inf,
+            "unknowns": r["unknowns"],
+            "n_inside": r["n_inside"],
+            "n_ghost": r["n_ghost"],
+            "levels": r["levels"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rb_sweep (finest level, one colour)",
+            "kernel": f"k_rb_sweep<3, {'double' if head == 'fp64' else 'float'}> (finest level, one colour)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": stored_traffic(N, prec == NAT.FP64),
+            "traffic": stored_traffic(N, head),
             "avg_launch_us": avg_s * 1e6,
-            "launches_timed": 2 * reps if prec == NAT.FP64 else launches,
+            "launches_timed": 2 * reps,
             "avg_launch_us_in_solve": in_solve_us,
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    for name in names:
+        out[name] = res[name]
+    if big:
+        out["speedup_mixed_vs_fp64"] = res["mixed"]["unknowns_per_s"] / res["fp64"]["unknowns_per_s"]
+    G.close()
+    del G, u
+    torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
+        cpu_cycles = args.cpu_cycles or (1 if N >= 512 else 2)
+        ref_cycles = res["fp64"]["cycles"] if "fp64" in res else r["cycles"]
         cpu_t0 = time.perf_counter()
         O = oracle.Problem(3, N, case.phi)
         og = O.ghosts(0)
@@ -257,90 +298,21 @@ def main():
         uo = np.zeros(O.nodes(0))
         r0 = O.norm(0, O.residual(0, uo))
         tc = time.perf_counter()
-        for _ in range(args.cpu_cycles):
+        for _ in range(cpu_cycles):
             O.vcycle(uo)
             O.norm(0, O.residual(0, uo))
-        per_cycle = (time.perf_counter() - tc) / args.cpu_cycles
-        cpu_solve = per_cycle * st.cycles
+        per_cycle = (time.perf_counter() - tc) / cpu_cycles
+        cpu_solve = per_cycle * ref_cycles
         out["cpu_baseline"] = {
-            "value": unknowns / cpu_solve,
+            "value": r["unknowns"] / cpu_solve,
             "unit": "unknowns/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": (f"oracle (plain C, FP64, 1 thread) on the same {N + 1}^3 problem: setup ({cpu_setup:.1f} s, "
-                       f"excluded like on the GPU) then {args.cpu_cycles} V-cycles with residual norms "
-                       f"({per_cycle:.2f} s each), scaled to the {st.cycles} cycles of the full solve"),
+            "sample": (f"oracle (plain C, FP64, 1 thread: it has no threading) on the same {N + 1}^3 problem: setup "
+                       f"({cpu_setup:.1f} s, excluded like on the GPU) then {cpu_cycles} V-cycle(s) with residual "
+                       f"norms ({per_cycle:.2f} s each), scaled to the {ref_cycles} cycles of the FP64 solve"),
             "r0": r0,
         }
-    print(json.dumps(out))
-
-
-def _flower_problem(N, prec, max_cycles):
-    import torch
-
-    from paper_2207_14208_amd import workloads as W
-    from paper_2207_14208_amd.solver import Problem
-    case = W.flower3d(N)
-    G = Problem(3, N, torch.from_numpy(case.phi).cuda(), precision=prec, max_cycles=max_cycles)
-    q = G.ghost_info(0)["q"]
-    G.set_data(torch.from_numpy(case.f).cuda(), torch.exp(q[:, 0] + q[:, 1] + q[:, 2]))
-    return case, G
-
-
-def bench_mixed(args):
-    """513^3 flower: the plain FP64 solve against the mixed-precision solve
-    (FP32 cycle on the correction, FP64 residual, update and coarse solve),
-    both to ||r|| <= 1e-10 ||r0||; error of the mixed result against the FP64
-    result and against the exact solution."""
-    import numpy as np
-    import torch
-
-    from paper_2207_14208_amd import _native as NAT
-    from paper_2207_14208_amd import workloads as W
-    N = 512 if args.N == 256 else args.N
-    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
-           "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,
-           "warmup": args.warmup}
-    res = {}
-    sols = {}
-    for name, prec in (("fp64", NAT.FP64), ("mixed", NAT.MIXED)):
-        case, G = _flower_problem(N, prec, args.max_cycles)
-        info = G.level_info(0)
-        unknowns = info["n_inside"] + info["n_ghost"]
-        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
-        for _ in range(args.warmup):
-            u.zero_()
-            G.solve(u, 1e-10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            u.zero_()
-            st, hist = G.solve(u, 1e-10)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / args.steps
-        res[name] = {"unknowns_per_s": unknowns / el, "ms_per_solve": el * 1e3, "cycles": st.cycles,
-                     "status": st.status, "rel_residual": st.r_final / st.r0}
-        cls = G.classes(0)
-        m = (cls == NAT.INSIDE) | (cls == NAT.GHOST)
-        sols[name] = u[m].clone()
-        if name == "mixed":
-            ue = torch.from_numpy(W.sample(3, N, case.u_exact)).cuda()[m]
-            res[name]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
-                                                 sols["fp64"].abs().max()).item()
-            res[name]["max_err_vs_exact"] = (sols["mixed"] - ue).abs().max().item()
-            res["fp64"]["max_err_vs_exact"] = (sols["fp64"] - ue).abs().max().item()
-        out["config"] = {"workload": f"3D flower, {N + 1}^3 nodes, u=exp(x+y+z), FP64 vs mixed V(2,1) to 1e-10",
-                         "unknowns": unknowns, "levels": G.levels}
-        G.close()
-        del G
-        torch.cuda.empty_cache()
-    out["value"] = res["mixed"]["unknowns_per_s"]
-    out["ms_per_step"] = res["mixed"]["ms_per_solve"]
-    out["dtype"] = "f32+f64"
-    out["fp64"] = res["fp64"]
-    out["mixed"] = res["mixed"]
-    out["speedup_mixed_vs_fp64"] = res["mixed"]["unknowns_per_s"] / res["fp64"]["unknowns_per_s"]
     print(json.dumps(out))
 
 
@@ -356,7 +328,7 @@ def bench_neumann(args):
     from paper_2207_14208_amd import workloads as W
     from paper_2207_14208_amd.solver import Problem
     N = args.N
-    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
+    out = {"metric": METRIC,
            "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,
            "warmup": args.warmup, "dtype": "f64"}
@@ -508,7 +480,7 @@ def bench_batched(args):
         plain_el += time.perf_counter() - ts
         plain_cycles.append(st.cycles)
         G.close()
-    out = {"metric": "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); served p50/p99 ms",
+    out = {"metric": METRIC,
            "value": r.unknowns / el, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64", "data": "synthetic (seeded star domains and manufactured solution)",

@@ -331,10 +331,12 @@ bcmg_status bcmg_problem_bytes(const bcmg_problem *prob, int64_t *bytes);
 bcmg_status bcmg_timing_enable(int32_t on);
 bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *inside_nodes_per_launch);
 
-/* Back-to-back finest-level red-black sweeps (reps red + black pairs, FP64
- * problems) on a scratch copy of u_dev, launched directly between one HIP
- * event pair on the problem's stream: *ms_host is the elapsed time, so the
- * time per colour launch is *ms_host / (2 reps).  u_dev is not modified. */
+/* Back-to-back finest-level red-black sweeps (reps red + black pairs),
+ * launched directly between one HIP event pair on the problem's stream:
+ * *ms_host is the elapsed time, so the time per colour launch is
+ * *ms_host / (2 reps).  FP64 problems sweep a scratch copy of u_dev (u_dev
+ * is not modified); mixed-precision problems sweep the FP32 arrays of their
+ * correction cycle (u_dev may be NULL; a later solve starts them afresh). */
 bcmg_status bcmg_timing_sweeps(bcmg_problem *prob, const double *u_dev, int32_t reps, double *ms_host);
 
 #ifdef __cplusplus

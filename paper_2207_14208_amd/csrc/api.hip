@@ -1890,13 +1890,20 @@ bcmg_status bcmg_timing_read(int64_t *launches, double *total_ms, int64_t *nodes
 }
 
 bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, double *ms) {
-    bcmg_status st = check_fp64_step(P, 0);
-    if (st) return st;
-    if (!u || !ms || reps < 1) return fail(BCMG_ERR_INVALID, "bad argument");
+    if (!valid_level(P, 0)) return fail(BCMG_ERR_INVALID, "bad problem");
+    if (!ms || reps < 1 || (!P->fp32 && !u)) return fail(BCMG_ERR_INVALID, "bad argument");
+    bcmg_status st;
     const LevelH &V = P->lev[0];
-    double *scratch = (double *)V.r;  // residual scratch of the finest level
-    HIPCHK(hipMemcpyAsync(scratch, u, sizeof(double) * V.nn, hipMemcpyDeviceToDevice, P->stream));
-    void *pu[1] = {scratch}, *pr[1] = {P->rhs64}, *px[1] = {V.r};
+    void *pu[1], *pr[1], *px[1] = {V.r};
+    if (P->fp32) {  // the FP32 correction cycle's own finest arrays (overwritten)
+        pu[0] = V.u;
+        pr[0] = V.rhs;
+    } else {  // a copy of u in the residual scratch of the finest level
+        double *work = (double *)V.r;
+        HIPCHK(hipMemcpyAsync(work, u, sizeof(double) * V.nn, hipMemcpyDeviceToDevice, P->stream));
+        pu[0] = work;
+        pr[0] = P->rhs64;
+    }
     if ((st = upload_step_descs(P, 0, 1, pu, pr, px))) return st;
     const Item *segs = P->d_stepitems + P->off_seg[0];
     struct Events {  // destroyed on every return path
@@ -1909,11 +1916,11 @@ bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, d
     HIPCHK(hipEventCreate(&ev.e0));
     HIPCHK(hipEventCreate(&ev.e1));
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
-    launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);  // warm
+    launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);  // warm
     HIPCHK(hipEventRecord(e0, P->stream));
     for (int i = 0; i < reps; i++) {
-        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);
-        launch_rb_sweep(P->d, 0, P->d_step, segs, P->n_seg[0], 1, P->d_stepst, P->stream);
+        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);
+        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 1, P->d_stepst, P->stream);
     }
     HIPCHK(hipEventRecord(e1, P->stream));
     HIPCHK(hipEventSynchronize(e1));

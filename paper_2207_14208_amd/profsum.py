@@ -71,28 +71,33 @@ def trace_table(d: str, top: int = 30) -> tuple[list, float]:
 
 
 def counter_rows(d: str, counter: str):
-    """(short name, grid, value) per dispatch of one counter."""
+    """(short name, grid, value, dispatch id) per dispatch of one counter."""
     for path in _find(d, "*counter_collection.csv"):
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") != counter:
                     continue
                 g = int(_col(r, "Grid_Size", "Grid_Size_X", default=0))
-                yield _short(r["Kernel_Name"]), g, float(r["Counter_Value"])
+                yield _short(r["Kernel_Name"]), g, float(r["Counter_Value"]), int(_col(r, "Dispatch_Id", default=0))
 
 
 def traffic(fetch_dir: str, write_dir: str, kernel: str, grid: int, copy_bytes: int) -> dict:
     def per_dispatch(d, counter):
         vals = collections.defaultdict(list)
-        for name, g, v in counter_rows(d, counter):
+        copies = []
+        for name, g, v, did in counter_rows(d, counter):
             vals[(name, g)].append(v)
+            if "copy" in name.lower() and v * 1024.0 > 0.1 * copy_bytes:
+                copies.append((did, v))
         g_use = grid if grid else max((g for (n, g) in vals if n == kernel), default=0)
         mine = [v for (n, g), vs in vals.items() if n == kernel and g == g_use for v in vs]
-        # the copy probe: the largest elementwise copy dispatch
-        copies = [max(vs) for (n, g), vs in vals.items() if "copy" in n.lower() or "elementwise" in n.lower()]
         if not mine:
             raise SystemExit(f"no {counter} rows for {kernel} grid {grid} in {d}")
-        return sum(mine) / len(mine), (max(copies) if copies else None), len(mine), g_use
+        # the copy probe: the program's first large copy dispatch (bench.py
+        # runs it before anything else; later copies, such as uploads of the
+        # inputs, can be larger)
+        probe = min(copies)[1] if copies else None
+        return sum(mine) / len(mine), probe, len(mine), g_use
 
     f_k, f_copy, nf, grid = per_dispatch(fetch_dir, "FETCH_SIZE")
     w_k, w_copy, nw, _ = per_dispatch(write_dir, "WRITE_SIZE")

@@ -57,3 +57,27 @@ def test_traffic_scales_counters_by_the_copy_probe(tmp_path):
     assert t["grid"] == 2048 and t["dispatches"] == [2, 1]
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     assert t["bytes_per_launch"] == pytest.approx(230.0 * 1024)
+
+
+def test_copy_probe_is_the_first_large_copy(tmp_path):
+    # the probe copy (dispatch 2) comes before a larger upload of the inputs
+    # (dispatch 9, same copy kernel): the factors come from the probe
+    hdr = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    fd, wd = tmp_path / "f", tmp_path / "w"
+    fd.mkdir()
+    wd.mkdir()
+    _write(fd / "c_counter_collection.csv", hdr, [
+        [1, "fill_kernel(int)", 4096, "FETCH_SIZE", 0.0],
+        [2, "__amd_rocclr_copyBuffer", 4096, "FETCH_SIZE", 512.0],
+        [5, "void k_rb_sweep<3, float>(int)", 2048, "FETCH_SIZE", 100.0],
+        [9, "__amd_rocclr_copyBuffer", 4096, "FETCH_SIZE", 2048.0],
+        [12, "__amd_rocclr_copyBuffer", 4096, "FETCH_SIZE", 1.5],
+    ])
+    _write(wd / "c_counter_collection.csv", hdr, [
+        [2, "__amd_rocclr_copyBuffer", 4096, "WRITE_SIZE", 1024.0],
+        [5, "void k_rb_sweep<3, float>(int)", 2048, "WRITE_SIZE", 30.0],
+        [9, "__amd_rocclr_copyBuffer", 4096, "WRITE_SIZE", 4096.0],
+    ])
+    t = profsum.traffic(str(fd), str(wd), "k_rb_sweep<3, float>", 0, 1 << 20)
+    assert t["copy_fetch_kib"] == 512.0 and t["copy_write_kib"] == 1024.0
+    assert t["bytes_per_launch"] == pytest.approx(230.0 * 1024)
