@@ -88,10 +88,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle V-cycles in the CPU sample (default: 1 at "
                                                                 "513^3, 2 below)")
-    ap.add_argument("--workload", choices=["flower513", "flower257", "batched", "served", "rho_sweep", "neumann"],
+    ap.add_argument("--workload", choices=["flower513", "flower257", "probe513", "batched", "served", "rho_sweep",
+                                           "neumann"],
                     default="flower513",
                     help="flower513: the 513^3 flower, FP64 against mixed precision (the headline); flower257: "
-                         "the 257^3 FP64 solve; batched: 512 2D star problems; served: the continuous-batching "
+                         "the 257^3 FP64 solve; probe513: the finest red-black sweep on the full 513^3 box (the "
+                         "roofline probe); batched: 512 2D star problems; served: the continuous-batching "
                          "request loop; rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: "
                          "the 257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
@@ -119,7 +121,65 @@ def main():
         return bench_served(args)
     if args.workload == "neumann":
         return bench_neumann(args)
+    if args.workload == "probe513":
+        return bench_probe(args)
     return bench_flower(args)
+
+
+def bench_probe(args):
+    """Roofline probe: the red-black sweep of the finest level on the whole
+    513^3 box (phi = -1 everywhere: 511^3 INSIDE nodes, rows of 511 nodes),
+    timed by HIP events around 100 back-to-back red + black sweeps, for the
+    FP32 sweep of a mixed-precision problem in the split and natural storage
+    orders and for the FP64 sweep.  Algorithmic bytes per colour launch:
+    1.5 esz per INSIDE node (f and the written u at the colour's nodes, u of
+    the other colour), as for the solve's sweep."""
+    import torch
+
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd.solver import Problem
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    N = args.N or 512
+    phi = -torch.ones((N + 1) ** 3, dtype=torch.float64, device="cuda")
+    reps = 100
+    res = {}
+    for name, prec, layout in (("fp32_split", NAT.MIXED, NAT.LAYOUT_SPLIT), ("fp32_natural", NAT.MIXED, NAT.LAYOUT_NATURAL),
+                               ("fp64_natural", NAT.FP64, NAT.LAYOUT_NATURAL)):
+        G = Problem(3, N, phi, precision=prec, layout=layout)
+        info = G.level_info(0)
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        G.timing_sweeps(u, 5)
+        ms = G.timing_sweeps(u, reps)
+        avg_s = ms / (2 * reps) / 1e3
+        esz = 4 if prec == NAT.MIXED else 8
+        alg = 1.5 * esz * info["n_inside"]
+        res[name] = {"avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg, "achieved_GBps": alg / avg_s / 1e9,
+                     "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS, "n_inside": info["n_inside"],
+                     "n_segments": info["n_segments"]}
+        G.close()
+        del G, u
+        torch.cuda.empty_cache()
+    best = res["fp32_split"]
+    out = {"metric": "finest red-black sweep bandwidth on the full 513^3 box (roofline probe)",
+           "value": best["achieved_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 5,
+           "ms_per_step": 2 * best["avg_launch_us"] / 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic (phi = -1 on the whole box)",
+           "config": {"workload": f"roofline probe: red-black sweep of the full {N + 1}^3 box, FP32 split layout "
+                                  f"(FP32 natural and FP64 beside it)", "nodes_per_axis": N + 1},
+           "roofline": {"bound": "hbm", "kernel": "k_rb_sweep_multi<3, float, 2> (split layout, one colour)",
+                        "achieved": best["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": best["frac"], "traffic": None, "avg_launch_us": best["avg_launch_us"],
+                        "alg_bytes_per_launch": best["alg_bytes_per_launch"]},
+           "variants": res}
+    print(json.dumps(out))
 
 
 def bench_flower(args):

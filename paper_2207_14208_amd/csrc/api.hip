@@ -74,6 +74,7 @@ struct LevelH {
     int *rptr = nullptr, *ridx = nullptr;  // restriction rows of this level's ghosts (levels >= 1)
     double *rcoef = nullptr;
     void *u = nullptr, *rhs = nullptr, *r = nullptr;
+    long long half = 0;  // u, rhs and r stored split by node parity (see NodeArr): (nn + 1) / 2, else 0
     double *gnew = nullptr;
     std::vector<Item> segs;  // desc field 0; patched when copied into a table
     // coarsest level
@@ -128,6 +129,7 @@ struct Lists {
     // restriction into the level has done it)
     Item *rsegs = nullptr;
     int nrseg = 0;
+    bool split = false;  // every problem's level here has split storage (paired sweeps pay there)
 };
 
 struct bcmg_batch {
@@ -166,6 +168,7 @@ struct bcmg_batch {
     int nfseg = 0, nfgch = 0;
     int Ac = 0;                    // aligned levels 0..Ac run in the per-problem coarse workgroup
     long long coarse_nodes = kCoarseNodes;
+    int pair_segs = kSweepPairSegs;  // FP32 sweeps over this many segments pair them per wavefront
     CoarseProg *d_progs = nullptr;
     int nprog = 0;
     LdsProg *d_lprogs = nullptr;   // the same programs with their levels staged in LDS
@@ -316,6 +319,10 @@ Desc make_desc(const bcmg_problem *P, int l, void *u, void *rhs, void *r, int sl
     D.u = u;
     D.rhs = rhs;
     D.r = r;
+    // the level's own arrays carry its storage order; other arrays (the
+    // caller's u, the FP64 right-hand side) are in the natural order
+    D.half_u = V.half && (u == V.u || u == V.rhs || u == V.r) ? V.half : 0;
+    D.half_r = V.half && (r == V.u || r == V.rhs || r == V.r) ? V.half : 0;
     D.gnew = V.gnew;
     D.nc = V.nc;
     D.singular = V.singular;
@@ -560,6 +567,7 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     }
     // level arrays (cycle precision); the finest FP64 level uses caller memory for u
     const size_t esz = P->fp32 ? 4 : 8;
+    if (l == 0 && P->fp32 && P->opt.layout == BCMG_LAYOUT_SPLIT && V.nn > kSplitMinNodes) V.half = (V.nn + 1) / 2;
     if (l > 0 || P->fp32) {
         if ((st = dalloc(P, &V.u, V.nn * esz))) return st;
     }
@@ -701,6 +709,7 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->seg_len = kSegLen;
     o->bc = BCMG_BC_DIRICHLET;
     o->reaction = 0.0;
+    o->layout = BCMG_LAYOUT_NATURAL;
     return BCMG_OK;
 }
 
@@ -723,6 +732,7 @@ static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
     if (o->seg_len != 64 && o->seg_len != 128) return fail(BCMG_ERR_INVALID, "seg_len must be 64 or 128");
     if (o->bc != BCMG_BC_DIRICHLET && o->bc != BCMG_BC_NEUMANN) return fail(BCMG_ERR_INVALID, "bad bc");
     if (!(o->reaction >= 0.0 && std::isfinite(o->reaction))) return fail(BCMG_ERR_INVALID, "reaction must be >= 0");
+    if (o->layout != BCMG_LAYOUT_NATURAL && o->layout != BCMG_LAYOUT_SPLIT) return fail(BCMG_ERR_INVALID, "bad layout");
     return BCMG_OK;
 }
 
@@ -1296,6 +1306,11 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         long long nn = 1;
         for (int k = 0; k < b->d; k++) nn *= (4LL << a2) + 1;
         if (nn > b->coarse_nodes) break;
+        // the workgroup cycles natural-order arrays only
+        bool split = false;
+        for (int s = 0; s < b->cap; s++)
+            if (b->prob[s] && b->prob[s]->L - 1 == a2 && b->prob[s]->lev[0].half) split = true;
+        if (split) break;
         Ac = a2;
     }
     // with LDS enabled, lower the threshold until every problem's coarse
@@ -1432,6 +1447,14 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         L.ncgch = o.ncgch;
         L.rsegs = b->d_items + o.rseg;
         L.nrseg = o.nrseg;
+        bool any = false, all = true;
+        for (int s2 = 0; s2 < b->cap; s2++) {
+            const bcmg_problem *Q = b->prob[s2];
+            if (!Q || Q->L <= a) continue;
+            any = true;
+            all = all && Q->lev[Q->L - 1 - a].half != 0;
+        }
+        L.split = any && all;
     }
     b->fsegs = b->d_items + fseg0;
     b->nfseg = nfseg;
@@ -1453,7 +1476,7 @@ static void timed_sweep(bcmg_batch *b, int a, int colour, bool first = false) {
         hipEventRecord(e0, b->stream);
     }
     launch_rb_sweep(b->d, b->fp32, b->d_desc, first ? L.rsegs : L.segs, first ? L.nrseg : L.nseg, colour, b->d_state,
-                    b->stream);
+                    b->stream, L.split ? b->pair_segs : INT32_MAX);
     if (fine) {
         hipEventRecord(e1, b->stream);
         b->tev.push_back({e0, e1});
@@ -1612,6 +1635,13 @@ bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value) {
         HIPCHK(hipStreamSynchronize(b->stream));
         b->coarse_nodes = value;
         b->dirty = true;
+        return BCMG_OK;
+    }
+    if (param == BCMG_PARAM_SWEEP_PAIR_SEGS) {
+        if (value < 1 || value > INT32_MAX) return fail(BCMG_ERR_INVALID, "sweep pair threshold out of range");
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->pair_segs = (int)value;
+        drop_graph(b);
         return BCMG_OK;
     }
     if (param == BCMG_PARAM_LDS_BYTES) {
@@ -1916,11 +1946,12 @@ bcmg_status bcmg_timing_sweeps(bcmg_problem *P, const double *u, int32_t reps, d
     HIPCHK(hipEventCreate(&ev.e0));
     HIPCHK(hipEventCreate(&ev.e1));
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
-    launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);  // warm
+    const int pair = V.half ? kSweepPairSegs : INT32_MAX;  // as a batch launches it
+    launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream, pair);  // warm
     HIPCHK(hipEventRecord(e0, P->stream));
     for (int i = 0; i < reps; i++) {
-        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream);
-        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 1, P->d_stepst, P->stream);
+        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 0, P->d_stepst, P->stream, pair);
+        launch_rb_sweep(P->d, P->fp32, P->d_step, segs, P->n_seg[0], 1, P->d_stepst, P->stream, pair);
     }
     HIPCHK(hipEventRecord(e1, P->stream));
     HIPCHK(hipEventSynchronize(e1));

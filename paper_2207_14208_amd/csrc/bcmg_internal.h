@@ -1,6 +1,9 @@
 // Internal declarations shared by the HIP translation units of libbcmg.
 // Device data layout:
 //   * every level keeps dense node arrays (x fastest): class (uint8), u, rhs, r;
+//     with BCMG_LAYOUT_SPLIT the finest FP32 arrays of a large mixed-precision
+//     problem store the two parities of the node index one after the other
+//     (NodeArr in seg.h);
 //   * the work of a launch is a list of items: row segments of <= 128 nodes
 //     (one wavefront each) or chunks of <= 256 ghost / band entries (one
 //     workgroup each); each item names a level descriptor, so one launch can
@@ -32,6 +35,12 @@ constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
 constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
 // levels with at most this many nodes are cycled by one workgroup per problem
 constexpr long long kCoarseNodes = 5000;
+// FP32 red-black launches over at least this many row segments give each
+// wavefront two of them (BCMG_PARAM_SWEEP_PAIR_SEGS)
+constexpr int kSweepPairSegs = 32768;
+// the finest FP32 arrays of a mixed-precision problem with more nodes than
+// this are stored split by node parity under BCMG_LAYOUT_SPLIT
+constexpr long long kSplitMinNodes = 1 << 17;
 // levels with at most this many nodes keep a colour-sorted list of their
 // INSIDE nodes (used when they are cycled in LDS)
 constexpr long long kListNodes = 1 << 15;
@@ -66,6 +75,8 @@ struct alignas(16) Desc {
     const int *ilist;         // INSIDE nodes, even i+j+k first (small levels only, else null)
     int ni, nred;             //   their count and the count of the first colour
     void *u, *rhs, *r;        // level arrays, element type = cycle precision
+    long long half_u, half_r; // storage order of u and rhs / of r: 0 natural (x fastest), else split by the
+                              //   parity of the node index, even first, half = (nn + 1) / 2 (see NodeArr)
     double *gnew;             // [ng] new ghost values of a Jacobi ghost step
     // coarsest level: dense inverse over INSIDE then GHOST unknowns
     int nc, singular;

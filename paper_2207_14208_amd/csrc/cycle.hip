@@ -120,7 +120,7 @@ __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, PD gn
 }
 
 template <int D, typename T, bool NEU>
-__device__ __forceinline__ double ghost_row(const Desc &L, int g, gcp<T> __restrict__ u) {
+__device__ __forceinline__ double ghost_row(const Desc &L, int g, const NodeArr<const T> &u) {
     return ghost_row_at<D, NEU>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, (gcp<double>)L.gnd,
                                 L.gnd != nullptr, L.sy, L.sz, g, u);
 }
@@ -134,19 +134,21 @@ template <int D, typename Tu, typename Tr>
 __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, int lane, bool live, bool store = true) {
     const Seg s = seg_of(it);
     double r2 = 0.0;
-    gcp<Tu> __restrict__ u = (gcp<Tu>)L.u;
-    gcp<Tu> __restrict__ f = (gcp<Tu>)L.rhs;
+    const NodeArr<const Tu> u = node_u<const Tu>(L);
+    const NodeArr<const Tu> f = node_rhs<const Tu>(L);
     gcp<uint8_t> cls = (gcp<uint8_t>)L.cls;
-    gp<Tr> __restrict__ r = (gp<Tr>)L.r;
+    const NodeArr<Tr> r = node_r<Tr>(L);
     const long long nn = L.nn;
     // both nodes of the lane are loaded and computed before either store,
     // so that their loads are in flight together
     double rv[2];
     int cc[2];
     long long pp[2];
+    int qs[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int q = lane + 64 * h;
+        const int q = seg_lane_node(lane, h, L.half_u);
+        qs[h] = q;
         const long long p = s.p0 + (q < s.len ? q : 0);
         cc[h] = cls[p];
         pp[h] = p;
@@ -175,7 +177,7 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
     }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        if (lane + 64 * h < s.len && cc[h] == C_INSIDE && live) {
+        if (qs[h] < s.len && cc[h] == C_INSIDE && live) {
             if (store) r[pp[h]] = (Tr)rv[h];
             r2 += rv[h] * rv[h];
         }
@@ -256,7 +258,7 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
                                               bool red, T &fv, T &uv, int &cc) {
-    const double out = restrict_inside_at<D>((gcp<T>)F.r, (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
+    const double out = restrict_inside_at<D>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
                                              C.restrict_mode);
     cc = ((gcp<uint8_t>)C.cls)[pc];
     fv = (T)out;
@@ -333,15 +335,15 @@ __device__ __forceinline__ double row_dot_group(gcp<int> idx, gcp<double> coef, 
 // extension folded in); zeroes the coarse unknown.
 template <typename T>
 __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int g, bool live) {
-    gcp<T> __restrict__ r = (gcp<T>)F.r;
+    const NodeArr<const T> r = node_r<const T>(F);
     gcp<int> rptr = (gcp<int>)C.rptr, ridx = (gcp<int>)C.ridx;
     gcp<double> rcoef = (gcp<double>)C.rcoef;
     const int beg = rptr[g], end = rptr[g + 1];
     const long long pc = ((gcp<int>)C.gidx)[g];
     const double acc = row_dot(ridx, rcoef, beg, end, [&](int q) { return (double)r[q]; });
     if (!live) return;
-    ((gp<T>)C.rhs)[pc] = (T)acc;
-    ((gp<T>)C.u)[pc] = (T)0;
+    node_rhs<T>(C)[pc] = (T)acc;
+    node_u<T>(C)[pc] = (T)0;
 }
 
 // The restriction of coarse node q of a segment (one node per lane: its 3^d
@@ -358,21 +360,21 @@ __device__ __forceinline__ void seg_restrict_one(const Desc &C, const Desc &F, c
     pin(uv);
     pin(cc);
     if (!live || q >= s.len || cc != C_INSIDE) return;
-    ((gp<T>)C.u)[s.p0 + q] = uv;
-    ((gp<T>)C.rhs)[s.p0 + q] = fv;
+    node_u<T>(C)[s.p0 + q] = uv;
+    node_rhs<T>(C)[s.p0 + q] = fv;
 }
 
 // restrict_ghost by the eight lanes sub of a group (one coarse ghost each group)
 template <typename T>
 __device__ __forceinline__ void restrict_ghost_group(const Desc &C, const Desc &F, int g, int sub, bool live) {
-    gcp<T> __restrict__ r = (gcp<T>)F.r;
+    const NodeArr<const T> r = node_r<const T>(F);
     const int beg = ((gcp<int>)C.rptr)[g], end = ((gcp<int>)C.rptr)[g + 1];
     const long long pc = ((gcp<int>)C.gidx)[g];
     const double acc =
         row_dot_group((gcp<int>)C.ridx, (gcp<double>)C.rcoef, beg, end, sub, [&](int q) { return (double)r[q]; });
     if (!live || sub != 0) return;
-    ((gp<T>)C.rhs)[pc] = (T)acc;
-    ((gp<T>)C.u)[pc] = (T)0;
+    node_rhs<T>(C)[pc] = (T)acc;
+    node_u<T>(C)[pc] = (T)0;
 }
 
 template <int D, typename T>
@@ -398,8 +400,8 @@ __device__ __forceinline__ void seg_restrict(const Desc &C, const Desc &F, const
         const int q = lane + 64 * h;
         if (!live || q >= s.len || cc[h] != C_INSIDE) continue;
         const long long pc = s.p0 + q;
-        ((gp<T>)C.u)[pc] = uv[h];
-        ((gp<T>)C.rhs)[pc] = fv[h];
+        node_u<T>(C)[pc] = uv[h];
+        node_rhs<T>(C)[pc] = fv[h];
     }
 }
 
@@ -447,9 +449,9 @@ __device__ __forceinline__ double prolong_at(PE ec, long long csy, long long csz
 template <int D, typename T>
 __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long long p, int I0, int I1, int I2, T &v,
                                              int &fc) {
-    const double e = prolong_at<D>((gcp<T>)C.u, C.sy, C.sz, I0, I1, I2);
+    const double e = prolong_at<D>(node_u<const T>(C), C.sy, C.sz, I0, I1, I2);
     fc = ((gcp<uint8_t>)F.cls)[p];
-    v = (T)((double)((gcp<T>)F.u)[p] + e);
+    v = (T)((double)node_u<const T>(F)[p] + e);
 }
 
 template <int D, typename T>
@@ -459,7 +461,7 @@ __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const 
     int fc[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {  // both nodes computed before either store
-        const int q = lane + 64 * h;
+        const int q = seg_lane_node(lane, h, F.half_u);
         const int qq = q < s.len ? q : 0;
         prolong_node<D, T>(F, C, s.p0 + qq, s.x0 + qq, s.yj, s.zk, v[h], fc[h]);
     }
@@ -470,9 +472,9 @@ __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const 
     }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int q = lane + 64 * h;
+        const int q = seg_lane_node(lane, h, F.half_u);
         if (!live || q >= s.len || (fc[h] != C_INSIDE && fc[h] != C_GHOST)) continue;
-        ((gp<T>)F.u)[s.p0 + q] = v[h];
+        node_u<T>(F)[s.p0 + q] = v[h];
     }
 }
 
@@ -480,8 +482,8 @@ __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const 
 // values): increment, then u_G += increment in a second pass.
 template <int D, typename T, bool NEU>
 __device__ __forceinline__ void ghost_delta(const Desc &L, int g, bool live) {
-    gcp<T> u = (gcp<T>)L.u;
-    gcp<T> rhs = (gcp<T>)L.rhs;
+    const NodeArr<const T> u = node_u<const T>(L);
+    const NodeArr<const T> rhs = node_rhs<const T>(L);
     const long long p = ((gcp<int>)L.gidx)[g];
     const double rg = (double)rhs[p];
     const double up = (double)u[p];
@@ -498,17 +500,17 @@ __device__ __forceinline__ void ghost_apply(const Desc &L, int g, bool live) {
     const T v = (T)((gcp<double>)L.gnew)[g];
     pin(v);
     if (!live) return;
-    ((gp<T>)L.u)[p] = v;
+    node_u<T>(L)[p] = v;
 }
 
 template <int D, typename Tu, typename Tr, bool NEU>
 __device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live, bool store = true) {
     const long long pg = ((gcp<int>)L.gidx)[g];
-    const double rg = (double)((gcp<Tu>)L.rhs)[pg];
-    const double r = rg - ghost_row<D, Tu, NEU>(L, g, (gcp<Tu>)L.u);
+    const double rg = (double)node_rhs<const Tu>(L)[pg];
+    const double r = rg - ghost_row<D, Tu, NEU>(L, g, node_u<const Tu>(L));
     pin(r);
     if (!live) return 0.0;
-    if (store) ((gp<Tr>)L.r)[pg] = (Tr)r;
+    if (store) node_r<Tr>(L)[pg] = (Tr)r;
     return r * r;
 }
 
@@ -518,7 +520,7 @@ __device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live
 // ghost step), or null to read them from the field.
 template <typename T>
 __device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *gsrc, bool live) {
-    gp<T> field = (gp<T>)L.u;
+    const NodeArr<T> field = node_u<T>(L);
     gcp<int> gidx = (gcp<int>)L.gidx;
     gcp<double> src = (gcp<double>)gsrc;
     const int beg = ((gcp<int>)L.eptr)[b], end = ((gcp<int>)L.eptr)[b + 1];
@@ -533,7 +535,7 @@ __device__ __forceinline__ void ext_gather(const Desc &L, int b, const double *g
 // ext_gather by the eight lanes sub of a group (one band entry each group)
 template <typename T>
 __device__ __forceinline__ void ext_gather_group(const Desc &L, int b, const double *gsrc, int sub, bool live) {
-    gp<T> field = (gp<T>)L.u;
+    const NodeArr<T> field = node_u<T>(L);
     gcp<int> gidx = (gcp<int>)L.gidx;
     gcp<double> src = (gcp<double>)gsrc;
     const int beg = ((gcp<int>)L.eptr)[b], end = ((gcp<int>)L.eptr)[b + 1];
@@ -826,8 +828,10 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(const Desc *__restrict__ d
                                                       float *const *__restrict__ eptr) {
     SEG_ITEM
     const Seg s = seg_of(it);
-    gp<float> ev = (gp<float>)eptr[it.x];
-    gp<double> u = (gp<double>)L.u;
+    // the correction has the layout of the finest FP32 arrays, which the
+    // outer descriptor's r (the correction's right-hand side) shares
+    const NodeArr<float> ev{(gp<float>)eptr[it.x], L.half_r};
+    const NodeArr<double> u = node_u<double>(L);
     double v[2];
     int c[2];
 #pragma unroll
@@ -1297,10 +1301,23 @@ static inline int blocks_for_segs(int nseg) { return (nseg + kWavesPerBlock - 1)
             DISPATCH_DB(d, KERNEL, T, false, __VA_ARGS__);                     \
     } while (0)
 
+#define DISPATCH_DS(d, KERNEL, T, S, ...)                                      \
+    do {                                                                       \
+        if ((d) == 1) hipLaunchKernelGGL((KERNEL<1, T, S>), __VA_ARGS__);      \
+        if ((d) == 2) hipLaunchKernelGGL((KERNEL<2, T, S>), __VA_ARGS__);      \
+        if ((d) == 3) hipLaunchKernelGGL((KERNEL<3, T, S>), __VA_ARGS__);      \
+    } while (0)
+
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
-                     const SlotState *st, hipStream_t s) {
+                     const SlotState *st, hipStream_t s, int pair_min) {
     if (nseg <= 0) return;
-    dim3 g(blocks_for_segs(nseg)), b(kBlock);
+    dim3 b(kBlock);
+    if (fp32 && nseg >= pair_min) {  // two segments per wavefront
+        dim3 g(blocks_for_segs((nseg + 1) / 2));
+        DISPATCH_DS(d, k_rb_sweep_multi, float, 2, g, b, 0, s, descs, items, nseg, colour, st);
+        return;
+    }
+    dim3 g(blocks_for_segs(nseg));
     if (fp32)
         DISPATCH_D(d, k_rb_sweep, float, g, b, 0, s, descs, items, nseg, colour, st);
     else

@@ -6,8 +6,10 @@
 namespace bcmg {
 
 // ---- cycle kernels (cycle.hip); fp32 selects the element type of u/rhs/r ----
+// FP32 launches with at least pair_min segments take two segments per wavefront (callers pass
+// kSweepPairSegs for split-layout levels, INT32_MAX elsewhere)
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
-                     const SlotState *st, hipStream_t s);
+                     const SlotState *st, hipStream_t s, int pair_min = INT32_MAX);
 // Jacobi ghost step (new values into gnew, then applied); with bch, the
 // applying launch also extends the new field into the band chunks bch.
 // neu: some problem of the launch has Neumann ghost rows (selects the kernels

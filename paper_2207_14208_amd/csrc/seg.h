@@ -15,6 +15,37 @@ using gp = __attribute__((address_space(1))) T *;
 template <typename T>
 using gcp = const __attribute__((address_space(1))) T *;
 
+// A level's node array, indexed by the x-fastest node index p.  A split
+// array stores the nodes of even p first, then those of odd p: with n = N + 1
+// odd, the parity of p is the colour (i + j + k) mod 2 of red-black ordering,
+// and every axis neighbour has the other parity, so a colour pass reads one
+// half contiguously and writes the other.  half = the number of even indices
+// ((nn + 1) / 2) for a split array, 0 for the natural order.
+template <typename T>
+struct NodeArr {
+    gp<T> a;
+    long long half;
+    __device__ __forceinline__ long long at(long long p) const {
+        return half ? (p >> 1) + ((p & 1) ? half : 0LL) : p;
+    }
+    __device__ __forceinline__ __attribute__((address_space(1))) T &operator[](long long p) const { return a[at(p)]; }
+};
+
+// the descriptor's u and rhs (one layout) and r (its own layout)
+template <typename T>
+__device__ __forceinline__ NodeArr<T> node_u(const Desc &L) { return NodeArr<T>{(gp<T>)L.u, L.half_u}; }
+template <typename T>
+__device__ __forceinline__ NodeArr<T> node_rhs(const Desc &L) { return NodeArr<T>{(gp<T>)L.rhs, L.half_u}; }
+template <typename T>
+__device__ __forceinline__ NodeArr<T> node_r(const Desc &L) { return NodeArr<T>{(gp<T>)L.r, L.half_r}; }
+
+// Node q of a row segment that lane takes as its h-th node (two per lane):
+// lane + 64 h keeps each load of a natural-order array contiguous across the
+// wavefront; 2 lane + h does so for a split array (each h is one parity).
+__device__ __forceinline__ int seg_lane_node(int lane, int h, long long half) {
+    return half ? 2 * lane + h : lane + 64 * h;
+}
+
 struct Seg {
     long long p0;  // first node
     int len, x0, yj, zk;

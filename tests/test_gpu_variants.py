@@ -164,3 +164,66 @@ def test_mixed_precision_at_full_size():
     em = np.abs(um[m] - c.gB[m]).max()
     ed = np.abs(ud[m] - c.gB[m]).max()
     assert em <= 0.02 and abs(em - ed) <= 1e-8, (em, ed)
+
+
+@pytest.mark.parametrize("name", ["flower3d65", "star1025"])
+def test_split_layout_same_bits_as_natural(name):
+    """With BCMG_LAYOUT_SPLIT the finest FP32 arrays of a large
+    mixed-precision problem are stored split by node parity: the same
+    arithmetic in another storage order, so the solve gives the same cycle
+    count, history and u bits as with BCMG_LAYOUT_NATURAL, alone and in a
+    batch with a problem too small to be split."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Batch
+    c = {"flower3d65": lambda: W.flower3d(64), "star1025": lambda: W.star_case(0, 1025, 0.45, 0.08, 5)}[name]()
+    small = W.star_case(1, 65, 0.35, 0.05, 3) if c.d == 2 else W.ellipsoid(32)
+    out = []
+    for layout in (N.LAYOUT_SPLIT, N.LAYOUT_NATURAL):
+        G = gpu_problem(c, precision=N.MIXED, layout=layout)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        st, h = G.solve(u, 1e-10)
+        assert st.status == 0, st
+        out.append((st.cycles, h, u.cpu().numpy()))
+        # in a batch beside a small problem (natural order)
+        G2 = gpu_problem(c, precision=N.MIXED, layout=layout)
+        u2 = G2.initial_guess(torch.from_numpy(c.gB).cuda())
+        S = gpu_problem(small, precision=N.MIXED)
+        us = S.initial_guess(torch.from_numpy(small.gB).cuda())
+        B = Batch(2)
+        s1 = B.add(G2, u2, 1e-10)
+        B.add(S, us, 1e-10)
+        B.run(1, 300)
+        stb, hb = B.stats(s1)
+        assert stb.cycles == st.cycles and np.array_equal(hb, h)
+        assert np.array_equal(u2.cpu().numpy(), out[-1][2])
+        B.close()
+        for P in (G, G2, S):
+            P.close()
+    (c1, h1, u1), (c2, h2, u2) = out
+    assert c1 == c2 and np.array_equal(h1, h2) and np.array_equal(u1, u2)
+
+
+def test_paired_segment_sweep_same_bits():
+    """FP32 sweeps with two row segments per wavefront (forced on every
+    launched level here; by default only launches over 32768 segments take
+    it) give the same bits as one segment per wavefront."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Batch
+    c = W.flower3d(128)
+    out = []
+    for pair_min in (1, 1 << 30):
+        G = gpu_problem(c, precision=N.MIXED, layout=N.LAYOUT_SPLIT)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        B = Batch(1)
+        B.set_param(N.PARAM_SWEEP_PAIR_SEGS, pair_min)
+        s = B.add(G, u, 1e-10)
+        B.run(1, 300)
+        st, h = B.stats(s)
+        assert st.status == 0, st
+        out.append((st.cycles, h, u.cpu().numpy()))
+        B.close()
+        G.close()
+    (c1, h1, u1), (c2, h2, u2) = out
+    assert c1 == c2 and np.array_equal(h1, h2) and np.array_equal(u1, u2)
