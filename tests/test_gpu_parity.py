@@ -440,3 +440,40 @@ def test_non_finite_data_reported_as_divergence(where):
     assert it == -1 and len(ho) == 1
     assert st.status == NAT.ERR_DIVERGED and st.cycles == 0, st
     assert np.array_equal(ug.cpu().numpy(), before)
+
+
+def test_headline_solve_against_stored_oracle_solve():
+    """The 257^3 flower solved to 1e-10 in FP64 from u = 0, against the
+    oracle's whole solve of the same problem stored in
+    tests/golden/flower257_fp64_solve.json (written by
+    make_flower257_solve.py, which calls only the oracle): the same cycle
+    count (one apart only at the threshold), every cycle's residual norm
+    within 1e-8 relative plus the rounding floor, and the final u within
+    1e-12 relative at 4096 stored sample nodes and in its checksums."""
+    import json
+    import os
+    Problem = _gpu()
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "flower257_fp64_solve.json")) as fh:
+        gold = json.load(fh)
+    c = W.flower3d(gold["N"])
+    G = Problem(c.d, c.N, c.phi)
+    gq = W.points_eval(c.g, G.ghost_info(0)["q"].cpu().numpy(), c.d)
+    G.set_data(c.f, gq)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hg = G.solve(ug, gold["tol"])
+    assert st.status == 0, st
+    u = ug.cpu().numpy()
+    cls = G.classes(0).cpu().numpy()
+    rhs = np.where(cls == oracle.INSIDE, c.f, 0.0)
+    rhs[G.ghost_info(0)["idx"].cpu().numpy().astype(np.int64)] = gq
+    ho = np.asarray(gold["history"])
+    floor = residual_floor(c.d, c.N, cls, u, rhs)
+    assert cycles_agree(st.cycles, gold["cycles"], ho, gold["tol"], floor), (st.cycles, gold["cycles"])
+    assert histories_agree(hg, ho, floor)
+    if st.cycles == gold["cycles"]:
+        m = unknowns(cls)
+        assert int(m.sum()) == gold["n_unknowns"]
+        idx = np.asarray(gold["sample_idx"])
+        assert np.abs(u[idx] - np.asarray(gold["sample_u"])).max() <= 1e-12 * gold["u_max"]
+        assert abs(u[m].sum() - gold["u_sum"]) <= 1e-12 * gold["u_abs_sum"]
+        assert abs(np.abs(u[m]).max() - gold["u_max"]) <= 1e-12 * gold["u_max"]

@@ -227,3 +227,36 @@ def test_paired_segment_sweep_same_bits():
         G.close()
     (c1, h1, u1), (c2, h2, u2) = out
     assert c1 == c2 and np.array_equal(h1, h2) and np.array_equal(u1, u2)
+
+
+def test_stars512_batch_equals_solo_and_oracle():
+    """The batched workload's own draw: 512 star problems (seed 2207, sides
+    65..1025, mixed precision, tol 1e-10) solved in one batch with the
+    workload's settings give every problem the same status, cycle count and
+    u bits as its solve alone; one problem of each of three sides is within
+    1e-8 of the oracle's FP64 solution."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.batching import BatchConfig, BatchSolver, make_problem
+    params = W.star_params(512, seed=2207)
+    cases = [W.star_case(i, *p) for i, p in enumerate(params)]
+    cfg = BatchConfig(seg_len=128, coarse_nodes=5000, cycles_per_step=4, precision=N.MIXED)
+    bs = BatchSolver(cases, cfg)
+    r = bs.run()
+    assert all(s == 0 for s in r.status), [s for s in r.status if s]
+    batch_u = [u.cpu().numpy() for _, u, _ in bs.items]
+    bs.close()
+    checked = set()
+    for i, c in enumerate(cases):
+        G, u, _ = make_problem(c, cfg)
+        st, _ = G.solve(u, cfg.tol)
+        assert st.status == 0 and st.cycles == r.cycles[i], (i, st, r.cycles[i])
+        ua = u.cpu().numpy()
+        assert np.array_equal(ua, batch_u[i]), i
+        G.close()
+        if c.N in (64, 128, 256) and c.N not in checked:
+            checked.add(c.N)
+            O, ustar, cls, it, _ = oracle_solution(c)
+            m = (cls == oracle.INSIDE) | (cls == oracle.GHOST)
+            assert np.abs(ua[m] - ustar[m]).max() <= 1e-8 * np.abs(ustar[m]).max(), i
+    assert checked == {64, 128, 256}

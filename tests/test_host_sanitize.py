@@ -1,0 +1,33 @@
+"""The library's host code under AddressSanitizer and
+UndefinedBehaviorSanitizer (host side only; device code is built as usual):
+tests/host_sanitize_driver.cpp calls the entry points that validate
+arguments and manage state without a device."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2207_14208_amd", "csrc")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def test_host_code_clean_under_asan_and_ubsan(tmp_path):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = tmp_path / "host_sanitize"
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all"]
+    cmd = [HIPCC, "-O1", "-g", "-std=c++17", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *san,
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(HERE, "host_sanitize_driver.cpp"),
+           *[os.path.join(CSRC, f) for f in ("api.hip", "mem.hip", "cycle.hip", "setup.hip")],
+           "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=900)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "ok" in r.stdout
