@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
+    ap.add_argument("--served-dtau", choices=["exp", "poly"], default="exp",
+                    help="served: the optimal dtau form (exponential, Remark exptheta2D; or polynomial, Prop. opt3D)")
     ap.add_argument("--prepare-workers", type=int, default=2,
                     help="served: host threads that sample and set up admitted requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

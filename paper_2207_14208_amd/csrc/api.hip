@@ -1357,24 +1357,35 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         }
         progs.push_back(cp);
     }
-    // the same programs with their levels staged in LDS, when they all fit
+    // the same programs with their levels staged in LDS, when the LDS path is
+    // on, every level has its colour-sorted INSIDE list (levels of at most
+    // kListNodes nodes) and they all fit; otherwise no program or image is
+    // built (the HBM workgroup needs neither)
     std::vector<LdsProg> lprogs;
     size_t lds_max = 0;
+    bool lists = true;
     for (const CoarseProg &cp : progs) {
         const bcmg_problem *P = b->prob[cp.slot];
-        LdsProg lp;
-        memset(&lp, 0, sizeof lp);
-        lp.slot = cp.slot;
-        lp.top = cp.top;
-        lp.ext_top = cp.ext_top;
-        lp.finest = cp.top == P->L - 1 ? 1 : 0;
-        lds_max = std::max(lds_max, lds_plan(P, cp.top, &lp));
-        for (int a2 = 0; a2 <= cp.top; a2++) lp.lev[a2].desc = cp.lev[a2].desc;
-        lprogs.push_back(lp);
+        for (int a2 = 0; a2 <= cp.top; a2++) lists = lists && P->lev[P->L - 1 - a2].ilist != nullptr;
     }
+    if (b->lds_budget > 0 && lists) {
+        for (const CoarseProg &cp : progs) {
+            const bcmg_problem *P = b->prob[cp.slot];
+            LdsProg lp;
+            memset(&lp, 0, sizeof lp);
+            lp.slot = cp.slot;
+            lp.top = cp.top;
+            lp.ext_top = cp.ext_top;
+            lp.finest = cp.top == P->L - 1 ? 1 : 0;
+            lds_max = std::max(lds_max, lds_plan(P, cp.top, &lp));
+            for (int a2 = 0; a2 <= cp.top; a2++) lp.lev[a2].desc = cp.lev[a2].desc;
+            lprogs.push_back(lp);
+        }
+    }
+    b->lds_bytes = !lprogs.empty() && lds_max <= b->lds_budget ? std::max<size_t>(lds_max, 16) : 0;
+    if (!b->lds_bytes) lprogs.clear();
     size_t image_words = 0;
     for (const LdsProg &lp : lprogs) image_words += (size_t)lp.static_words;
-    b->lds_bytes = !lprogs.empty() && lds_max <= b->lds_budget ? std::max<size_t>(lds_max, 16) : 0;
     // upload
     hipStream_t st = b->stream;
     if (descs.size() > b->desc_cap) {

@@ -320,7 +320,7 @@ def bench(args) -> dict:
     from . import _native as N
     budget = 16 << 30
     slots = 64
-    dtau = N.DTAU_OPT_POLY
+    dtau = {"exp": N.DTAU_OPT_EXP, "poly": N.DTAU_OPT_POLY}[getattr(args, "served_dtau", "exp")]
     n_meas = getattr(args, "requests", 400)
     workers = getattr(args, "prepare_workers", 2)
     n_warm = max(20, n_meas // 8)
@@ -353,7 +353,7 @@ def bench(args) -> dict:
         "data": "synthetic (seeded sphere unions, random smooth f)",
         "config": {"workload": "served 3D sphere unions, sides {33,65,129,257}, 4-64 spheres, g=0, tol 1e-8, "
                                "Poisson arrivals at 70% of measured capacity",
-                   "slots": slots, "hbm_budget_bytes": budget, "dtau": "OPT_POLY", "capacity_req_per_s": mu,
+                   "slots": slots, "hbm_budget_bytes": budget, "dtau": {N.DTAU_OPT_EXP: "OPT_EXP", N.DTAU_OPT_POLY: "OPT_POLY"}[dtau], "capacity_req_per_s": mu,
                    "prepare_workers": workers,
                    "arrival_rate": lam},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),

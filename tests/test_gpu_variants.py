@@ -260,3 +260,33 @@ def test_stars512_batch_equals_solo_and_oracle():
             m = (cls == oracle.INSIDE) | (cls == oracle.GHOST)
             assert np.abs(ua[m] - ustar[m]).max() <= 1e-8 * np.abs(ustar[m]).max(), i
     assert checked == {64, 128, 256}
+
+
+def test_coarse_workgroup_in_hbm_over_a_large_level():
+    """The per-problem coarse workgroup in HBM (LDS off) over levels larger
+    than those that keep an INSIDE list (the 65^3 flower's 33^3 level,
+    35937 nodes): the batch builds no LDS programs or images then (the image
+    copy once read the missing list), and the solve matches the oracle after
+    the same cycles."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    from paper_2207_14208_amd.solver import Batch
+    c = W.flower3d(64)
+    G = gpu_problem(c)
+    u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    B = Batch(1)
+    B.set_param(N.PARAM_COARSE_NODES, 40000)
+    B.set_param(N.PARAM_LDS_BYTES, 0)
+    s = B.add(G, u, 1e-10)
+    B.run(1, 300)
+    st, _ = B.stats(s)
+    assert st.status == 0, st
+    O = oracle.Problem(c.d, c.N, c.phi)
+    og = O.ghosts(0)
+    O.set_rhs(c.f, W.points_eval(c.g, og["q"], c.d))
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    O.solve(uo, 0.0, st.cycles)
+    assert np.abs(uo - u.cpu().numpy()).max() <= 1e-12 * np.abs(uo).max()
+    B.close()
+    G.close()
