@@ -88,12 +88,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle V-cycles in the CPU sample (default: 1 at "
                                                                 "513^3, 2 below)")
-    ap.add_argument("--workload", choices=["flower513", "flower257", "probe513", "batched", "served", "rho_sweep",
-                                           "neumann"],
+    ap.add_argument("--workload", choices=["flower513", "flower257", "probe513", "cycle_options", "batched", "served",
+                                           "rho_sweep", "neumann"],
                     default="flower513",
                     help="flower513: the 513^3 flower, FP64 against mixed precision (the headline); flower257: "
                          "the 257^3 FP64 solve; probe513: the finest red-black sweep on the full 513^3 box (the "
-                         "roofline probe); batched: 512 2D star problems; served: the continuous-batching "
+                         "roofline probe); cycle_options: the 257^3 flower with the V- and W-cycle and the "
+                         "red-black and weighted-Jacobi smoothers; batched: 512 2D star problems; served: the "
+                         "continuous-batching "
                          "request loop; rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: "
                          "the 257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
@@ -125,7 +127,63 @@ def main():
         return bench_neumann(args)
     if args.workload == "probe513":
         return bench_probe(args)
+    if args.workload == "cycle_options":
+        return bench_cycle_options(args)
     return bench_flower(args)
+
+
+def bench_cycle_options(args):
+    """The flower (257^3 by default), FP64 to 1e-10, with each cycle shape
+    (V, W) and interior smoother (red-black Gauss-Seidel, weighted Jacobi):
+    cycles and time per solve.  value: unknowns/s of the default V-cycle with
+    red-black smoothing."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14208_amd import _native as NAT
+    from paper_2207_14208_amd import workloads as W
+    from paper_2207_14208_amd.solver import Problem
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    N = args.N or 256
+    case = W.flower3d(N)
+    phi = torch.from_numpy(case.phi).cuda()
+    f = torch.from_numpy(case.f).cuda()
+    res = {}
+    for name, cyc, sm in (("V_rb", NAT.CYCLE_V, NAT.SMOOTH_RB), ("W_rb", NAT.CYCLE_W, NAT.SMOOTH_RB),
+                          ("V_jacobi", NAT.CYCLE_V, NAT.SMOOTH_JACOBI), ("W_jacobi", NAT.CYCLE_W, NAT.SMOOTH_JACOBI)):
+        G = Problem(3, N, phi, cycle=cyc, smoother=sm, max_cycles=args.max_cycles)
+        q = G.ghost_info(0)["q"]
+        G.set_data(f, torch.exp(q[:, 0] + q[:, 1] + q[:, 2]))
+        info = G.level_info(0)
+        u = torch.zeros(G.nodes, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            u.zero_()
+            G.solve(u, 1e-10)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, hist = G.solve(u, 1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times) * 1e3)
+        res[name] = {"status": NAT.STATUS_NAMES.get(st.status), "cycles": st.cycles, "ms_per_solve": ms,
+                     "us_per_cycle": ms * 1e3 / max(st.cycles, 1),
+                     "unknowns_per_s": (info["n_inside"] + info["n_ghost"]) / (ms / 1e3)}
+        G.close()
+        del G, u
+        torch.cuda.empty_cache()
+    out = {"metric": METRIC, "value": res["V_rb"]["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["V_rb"]["ms_per_solve"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (analytic level set and manufactured solution)",
+           "config": {"workload": f"3D flower, {N + 1}^3 nodes, FP64 to 1e-10: V/W cycle x red-black/weighted-Jacobi "
+                                  f"smoothing (value: V, red-black)", "nodes_per_axis": N + 1},
+           "variants": res}
+    print(json.dumps(out))
 
 
 def bench_probe(args):

@@ -92,7 +92,26 @@ typedef struct {
     double reaction;       /* c >= 0 of c u - Laplace u = f (default 0: Poisson; 1: the reaction-diffusion
                               tests of Sec. 3.3 / Sec. 4.2 with Neumann rows) */
     int32_t layout;        /* BCMG_LAYOUT_*: storage order of the library's own finest-level arrays */
+    int32_t cycle;         /* BCMG_CYCLE_V (default) or BCMG_CYCLE_W */
+    int32_t smoother;      /* BCMG_SMOOTH_RB (red-black Gauss-Seidel, default) or BCMG_SMOOTH_JACOBI */
 } bcmg_options;
+
+/* Cycle shape (Sec. 2.1: the two-grid scheme applied recursively, gamma
+ * times on each coarse level): V (gamma = 1) or W (gamma = 2 on every level
+ * but the one above the coarsest, whose coarse problem is solved exactly
+ * once).  A W-cycle runs every level by launches (no per-problem coarse
+ * workgroup), and a batch of W-cycle problems needs them all to have the
+ * same number of levels. */
+#define BCMG_CYCLE_V 0
+#define BCMG_CYCLE_W 1
+/* Interior smoother of each smoothing step (the ghost relaxation follows
+ * either): red-black Gauss-Seidel, or weighted Jacobi (Sec. 2.1: omega D +
+ * (1 - omega) I with omega = 2d / (2d + 1), 2/3 in 1D), whose new values go
+ * through the level's residual array (two launches).  Weighted Jacobi runs
+ * every level but the coarsest by launches and needs a nonsingular coarsest
+ * level. */
+#define BCMG_SMOOTH_RB 0
+#define BCMG_SMOOTH_JACOBI 1
 
 /* Storage order of the finest level's FP32 arrays of a mixed-precision
  * problem (the caller's arrays are always x fastest).  NATURAL (default):
@@ -216,9 +235,10 @@ bcmg_status bcmg_set_data(bcmg_problem *prob, const double *f_dev, const double 
 /* u_dev[BOXDIR nodes] = gbox_dev (nodes; NULL means 0).  Other entries untouched. */
 bcmg_status bcmg_fill_boundary(bcmg_problem *prob, const double *gbox_dev, double *u_dev);
 
-/* One V(nu1,nu2) cycle on u_dev (finest level, FP64, in place).  INSIDE and
- * GHOST entries are the unknowns, BOXDIR entries must hold g_B, other entries
- * are never read or written.  Sec. 2.1 (TGCS and its gamma = 1 recursion). */
+/* One (nu1,nu2) cycle of the problem's shape (V or W) on u_dev (finest
+ * level, FP64, in place).  INSIDE and GHOST entries are the unknowns, BOXDIR
+ * entries must hold g_B, other entries are never read or written.  Sec. 2.1
+ * (TGCS and its recursion with gamma = 1 or 2). */
 bcmg_status bcmg_vcycle(bcmg_problem *prob, double *u_dev);
 
 /* ||f - A u||_2 over INSIDE and GHOST rows of the finest level (host result). */

@@ -20,6 +20,8 @@ DTAU_OPT_EXP, DTAU_OPT_POLY, DTAU_CONST = 0, 1, 2
 RESTRICT_RENORM_FW, RESTRICT_PLAIN_MEAN = 0, 1
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 LAYOUT_NATURAL, LAYOUT_SPLIT = 0, 1
+CYCLE_V, CYCLE_W = 0, 1
+SMOOTH_RB, SMOOTH_JACOBI = 0, 1
 PARAM_COARSE_NODES = 1
 PARAM_LDS_BYTES = 2
 PARAM_SWEEP_PAIR_SEGS = 3
@@ -30,7 +32,8 @@ class bcmg_options(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("coarsest_N", C.c_int32), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("dtau_mode", C.c_int32), ("dtau_const", C.c_double),
                 ("ext_iters", C.c_int32), ("restrict_mode", C.c_int32), ("seg_len", C.c_int32),
-                ("bc", C.c_int32), ("reaction", C.c_double), ("layout", C.c_int32)]
+                ("bc", C.c_int32), ("reaction", C.c_double), ("layout", C.c_int32), ("cycle", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class bcmg_solve_stats(C.Structure):

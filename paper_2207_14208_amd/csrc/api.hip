@@ -140,6 +140,7 @@ struct bcmg_batch {
     hipEvent_t join = nullptr;
     long long fine_inside = 0;          // INSIDE nodes on the finest aligned level
     int d = 0, fp32 = 0, nu1 = 2, nu2 = 1, K = 4, max_hist = 0;
+    int wcycle = 0, jacobi = 0;         // cycle shape and interior smoother shared by the slots
     int neu = 0;                        // some slot has Neumann ghost rows (set at rebuild)
     std::vector<bcmg_problem *> prob;
     std::vector<double *> u;
@@ -710,6 +711,8 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->bc = BCMG_BC_DIRICHLET;
     o->reaction = 0.0;
     o->layout = BCMG_LAYOUT_NATURAL;
+    o->cycle = BCMG_CYCLE_V;
+    o->smoother = BCMG_SMOOTH_RB;
     return BCMG_OK;
 }
 
@@ -733,6 +736,8 @@ static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
     if (o->bc != BCMG_BC_DIRICHLET && o->bc != BCMG_BC_NEUMANN) return fail(BCMG_ERR_INVALID, "bad bc");
     if (!(o->reaction >= 0.0 && std::isfinite(o->reaction))) return fail(BCMG_ERR_INVALID, "reaction must be >= 0");
     if (o->layout != BCMG_LAYOUT_NATURAL && o->layout != BCMG_LAYOUT_SPLIT) return fail(BCMG_ERR_INVALID, "bad layout");
+    if (o->cycle != BCMG_CYCLE_V && o->cycle != BCMG_CYCLE_W) return fail(BCMG_ERR_INVALID, "bad cycle");
+    if (o->smoother != BCMG_SMOOTH_RB && o->smoother != BCMG_SMOOTH_JACOBI) return fail(BCMG_ERR_INVALID, "bad smoother");
     return BCMG_OK;
 }
 
@@ -1302,7 +1307,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     // aligned level a has N = 4 * 2^a on every problem: levels with at most
     // coarse_nodes nodes are cycled by one workgroup per problem
     int Ac = 0;
-    for (int a2 = 0; a2 < kMaxLevels; a2++) {
+    for (int a2 = 0; a2 < kMaxLevels && !b->wcycle && !b->jacobi; a2++) {
         long long nn = 1;
         for (int k = 0; k < b->d; k++) nn *= (4LL << a2) + 1;
         if (nn > b->coarse_nodes) break;
@@ -1499,9 +1504,13 @@ static void timed_sweep(bcmg_batch *b, int a, int colour, bool first = false) {
 // first: the first step of the pre-smoothing (its red half-sweep covers the
 // problems whose finest level this is only)
 static void smooth(bcmg_batch *b, int a, const Item *ext = nullptr, int next = 0, bool first = false) {
-    timed_sweep(b, a, 0, first);
-    timed_sweep(b, a, 1);
     const Lists &L = b->lv[a];
+    if (b->jacobi) {
+        launch_jacobi(b->d, b->fp32, b->d_desc, L.segs, L.nseg, b->d_state, b->stream);
+    } else {
+        timed_sweep(b, a, 0, first);
+        timed_sweep(b, a, 1);
+    }
     launch_ghost_relax(b->d, b->fp32, b->d_desc, L.gch, L.ngch, b->d_state, b->stream, ext, next, b->neu);
 }
 
@@ -1520,7 +1529,7 @@ static void launch_vcycle(bcmg_batch *b) {
         launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu);
         // a coarse level cycled by launches gets its first red half-sweep here
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
-                        b->nu1 > 0 && a - 1 > b->Ac);
+                        !b->jacobi && b->nu1 > 0 && a - 1 > b->Ac);
     }
     if (b->lds_bytes)
         launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s,
@@ -1541,6 +1550,43 @@ static void launch_vcycle(bcmg_batch *b) {
     }
 }
 
+// One W-cycle visit of aligned level a > Ac (Sec. 2.1: the two-grid step
+// applied recursively, gamma = 2 on every coarse level but the one above the
+// coarsest).  restricted: the level's correction starts from zero and the
+// restriction into it has done its first red half-sweep (the first visit;
+// the second starts from the first one's result, so its red half-sweep runs
+// in full).
+static void wcycle_level(bcmg_batch *b, int a, bool restricted) {
+    const int d = b->d, f = b->fp32;
+    hipStream_t s = b->stream;
+    const Lists &L = b->lv[a];
+    const bool work = L.nseg > 0 || L.ngch > 0;
+    if (work) {
+        for (int i = 0; i < b->nu1; i++) smooth(b, a, nullptr, 0, restricted && i == 0);
+        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu);
+        launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
+                        !b->jacobi && b->nu1 > 0 && a - 1 > b->Ac);
+    }
+    if (a - 1 == b->Ac) {
+        if (b->lds_bytes)
+            launch_coarse_lds(d, f, b->d_desc, b->d_lprogs, b->nprog, b->lds_bytes, b->d_state, b->nu1, b->nu2, s,
+                              b->neu);
+        else
+            launch_coarse_cycle(d, f, b->d_desc, b->d_items, b->d_progs, b->nprog, b->d_state, b->nu1, b->nu2, s,
+                                b->neu);
+    } else {
+        for (int g = 0; g < 2; g++) wcycle_level(b, a - 1, g == 0);
+    }
+    if (!work) return;
+    launch_prolong(d, f, b->d_desc, L.segs, L.nseg, b->d_state, s);
+    const Lists *U = a + 1 < b->A ? &b->lv[a + 1] : nullptr;  // extension for the next prolongation
+    for (int i = 0; i < b->nu2; i++) {
+        const bool last = i == b->nu2 - 1;
+        smooth(b, a, last && U ? U->cbch : nullptr, last && U ? U->ncbch : 0);
+    }
+    if (b->nu2 == 0 && U) launch_ext_gather(f, b->d_desc, U->cbch, U->ncbch, 1, b->d_state, s);
+}
+
 // finest FP64 residual (into the FP32 right-hand side of the correction
 // cycle; an FP64 batch keeps only its norm, since the next cycle recomputes
 // r before the restriction reads it) plus per-slot norm and convergence
@@ -1552,8 +1598,16 @@ static void launch_outer_residual(bcmg_batch *b, int mode) {
                        b->hist_stride, mode, nullptr, b->stream);
 }
 
+// one multigrid cycle of the batch's shape on the correction equations
+static void launch_mg_cycle(bcmg_batch *b) {
+    if (b->wcycle && b->A - 1 > b->Ac)
+        wcycle_level(b, b->A - 1, true);
+    else
+        launch_vcycle(b);
+}
+
 static void launch_cycle(bcmg_batch *b) {
-    launch_vcycle(b);
+    launch_mg_cycle(b);
     if (b->fp32) launch_ir_update(b->d_outer, b->fsegs, b->nfseg, b->d_state, b->d_eptr, b->stream);
     launch_outer_residual(b, 1);
 }
@@ -1581,15 +1635,25 @@ bcmg_status bcmg_batch_add(bcmg_batch *b, bcmg_problem *P, double *u, double rto
     for (int s = 0; s < b->cap; s++) n_used += b->prob[s] != nullptr;
     if (n_used > 0) {
         if (P->d != b->d || P->fp32 != b->fp32 || P->opt.nu1 != b->nu1 || P->opt.nu2 != b->nu2 ||
-            P->opt.ext_iters != b->K)
-            return fail(BCMG_ERR_INVALID, "problem does not match the batch (dim, precision, nu1, nu2, ext_iters)");
+            P->opt.ext_iters != b->K || (P->opt.cycle == BCMG_CYCLE_W) != (b->wcycle != 0) ||
+            (P->opt.smoother == BCMG_SMOOTH_JACOBI) != (b->jacobi != 0))
+            return fail(BCMG_ERR_INVALID,
+                        "problem does not match the batch (dim, precision, nu1, nu2, ext_iters, cycle, smoother)");
+        if (b->wcycle)
+            for (int s2 = 0; s2 < b->cap; s2++)
+                if (b->prob[s2] && b->prob[s2]->L != P->L)
+                    return fail(BCMG_ERR_INVALID, "W-cycle problems of a batch must have the same number of levels");
     } else {
         b->d = P->d;
         b->fp32 = P->fp32;
         b->nu1 = P->opt.nu1;
         b->nu2 = P->opt.nu2;
         b->K = P->opt.ext_iters;
+        b->wcycle = P->opt.cycle == BCMG_CYCLE_W;
+        b->jacobi = P->opt.smoother == BCMG_SMOOTH_JACOBI;
     }
+    if (b->jacobi && P->lev[P->L - 1].singular)
+        return fail(BCMG_ERR_INVALID, "weighted Jacobi needs a nonsingular coarsest level");
     int s = -1;
     for (int i = 0; i < b->cap; i++)
         if (!b->prob[i]) {
@@ -1854,7 +1918,7 @@ bcmg_status bcmg_vcycle(bcmg_problem *P, double *u) {
     s1.active = 1;
     s1.max_cycles = 1 << 30;
     HIPCHK(hipMemcpyAsync(b->d_state, &s1, sizeof s1, hipMemcpyHostToDevice, b->stream));
-    launch_vcycle(b);
+    launch_mg_cycle(b);
     if (b->fp32) launch_ir_update(b->d_outer, b->fsegs, b->nfseg, b->d_state, b->d_eptr, b->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(b->stream));

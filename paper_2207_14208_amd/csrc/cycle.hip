@@ -683,6 +683,64 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     }
 }
 
+// Weighted Jacobi on the INSIDE rows (Sec. 2.1: the smoother omega D + (1 -
+// omega) I, with omega = 2d / (2d + 1) in d dimensions, 2/3 in 1D).  Pass 0
+// computes u + omega ((h^2 f + sum of the 2d neighbours) / (2d + c h^2) - u)
+// from the old field into r; pass 1 copies r back into u.  Two nodes per
+// lane, both loaded before either store.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(const Desc *__restrict__ descs, const Item *__restrict__ items,
+                                                   int nseg, int pass, const SlotState *__restrict__ st) {
+    SEG_ITEM
+    const Seg s = seg_of(it);
+    const NodeArr<T> u = node_u<T>(L);
+    const NodeArr<const T> f = node_rhs<const T>(L);
+    const NodeArr<T> r = node_r<T>(L);
+    const long long nn = L.nn;
+    T v[2];
+    int cc[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = seg_lane_node(lane, h, L.half_u);
+        const long long p = s.p0 + (q < s.len ? q : 0);
+        cc[h] = ((gcp<uint8_t>)L.cls)[p];
+        if (pass == 1) {
+            v[h] = r[p];
+            continue;
+        }
+        const T up = u[p], fp = f[p];
+        const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
+        T ym = 0, yp = 0, zm = 0, zp = 0;
+        if (D >= 2) {
+            ym = u[clampi(p - L.sy, nn)];
+            yp = u[clampi(p + L.sy, nn)];
+        }
+        if (D >= 3) {
+            zm = u[clampi(p - L.sz, nn)];
+            zp = u[clampi(p + L.sz, nn)];
+        }
+        T sum = xp + xm;
+        if (D >= 2) sum += yp + ym;
+        if (D >= 3) sum += zp + zm;
+        const T omega = (T)(2.0 * D / (2.0 * D + 1.0));
+        v[h] = up + omega * (((T)L.h2 * fp + sum) / (T)(2.0 * D + L.reaction * L.h2) - up);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(v[h]);
+        pin(cc[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = seg_lane_node(lane, h, L.half_u);
+        if (!live || q >= s.len || cc[h] != C_INSIDE) continue;
+        if (pass == 0)
+            r[s.p0 + q] = v[h];
+        else
+            u[s.p0 + q] = v[h];
+    }
+}
+
 // Per-slot sum of the partials in a fixed order (thread t adds entries t,
 // t + 1024, ..., then a tree), then the convergence test.  mode 0: ||r^0|| of slots
 // waiting for it; mode 1: after a cycle; mode 2: only store the norm.
@@ -1322,6 +1380,18 @@ void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int 
         DISPATCH_D(d, k_rb_sweep, float, g, b, 0, s, descs, items, nseg, colour, st);
     else
         DISPATCH_D(d, k_rb_sweep, double, g, b, 0, s, descs, items, nseg, colour, st);
+}
+
+void launch_jacobi(int d, int fp32, const Desc *descs, const Item *items, int nseg, const SlotState *st,
+                   hipStream_t s) {
+    if (nseg <= 0) return;
+    dim3 g(blocks_for_segs(nseg)), b(kBlock);
+    for (int pass = 0; pass < 2; pass++) {
+        if (fp32)
+            DISPATCH_D(d, k_jacobi, float, g, b, 0, s, descs, items, nseg, pass, st);
+        else
+            DISPATCH_D(d, k_jacobi, double, g, b, 0, s, descs, items, nseg, pass, st);
+    }
 }
 
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,

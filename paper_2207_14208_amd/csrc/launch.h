@@ -10,6 +10,10 @@ namespace bcmg {
 // kSweepPairSegs for split-layout levels, INT32_MAX elsewhere)
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s, int pair_min = INT32_MAX);
+// weighted Jacobi on the INSIDE rows: new values into r from the old field,
+// then copied into u (two launches)
+void launch_jacobi(int d, int fp32, const Desc *descs, const Item *items, int nseg, const SlotState *st,
+                   hipStream_t s);
 // Jacobi ghost step (new values into gnew, then applied); with bch, the
 // applying launch also extends the new field into the band chunks bch.
 // neu: some problem of the launch has Neumann ghost rows (selects the kernels

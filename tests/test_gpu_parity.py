@@ -477,3 +477,39 @@ def test_headline_solve_against_stored_oracle_solve():
         assert np.abs(u[idx] - np.asarray(gold["sample_u"])).max() <= 1e-12 * gold["u_max"]
         assert abs(u[m].sum() - gold["u_sum"]) <= 1e-12 * gold["u_abs_sum"]
         assert abs(np.abs(u[m]).max() - gold["u_max"]) <= 1e-12 * gold["u_max"]
+
+
+@pytest.mark.parametrize("name", ["circle65", "flower3d_65", "spheres_65"])
+@pytest.mark.parametrize("variant", ["wcycle", "jacobi", "wcycle_jacobi"])
+def test_solve_parity_cycle_and_smoother_options(name, variant):
+    """The W-cycle (gamma = 2 on every level but the one above the coarsest)
+    and the weighted-Jacobi interior smoother (omega = 2d/(2d+1)), Sec. 2.1,
+    against the oracle's modes: the same cycle count, per-cycle norms and u
+    after the GPU's cycles, as for the V-cycle."""
+    from paper_2207_14208_amd import _native as NAT
+    Problem = _gpu()
+    c = CASES[name]()
+    gpu_opt, o_opt = {}, {}
+    if "wcycle" in variant:
+        gpu_opt["cycle"], o_opt["cycle"] = NAT.CYCLE_W, oracle.CYCLE_W
+    if "jacobi" in variant:
+        gpu_opt["smoother"], o_opt["smoother"] = NAT.SMOOTH_JACOBI, oracle.SMOOTH_JAC
+    O = oracle.Problem(c.d, c.N, c.phi, oracle.Options(**o_opt))
+    G = Problem(c.d, c.N, c.phi, **gpu_opt)
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    it, ho = O.solve(uo, 1e-10)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hg = G.solve(ug, 1e-10)
+    if it < 0:  # the W-cycle diverges on the 30-sphere union: both sides, at the same cycle
+        assert "wcycle" in variant and name == "spheres_65"
+        assert st.status == NAT.ERR_DIVERGED and st.cycles == len(ho) - 1, (st, len(ho))
+        return
+    assert it > 0 and st.status == 0, (it, st)
+    floor = residual_floor(c.d, c.N, cls, uo, O.rhs(0))
+    assert cycles_agree(st.cycles, it, ho, 1e-10, floor), (st.cycles, it)
+    assert histories_agree(hg, ho, floor)
+    u_after = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    O.solve(u_after, 0.0, st.cycles)
+    assert _close(u_after, ug.cpu().numpy(), 1e-12)
