@@ -99,6 +99,9 @@ def parse():
                          "request loop; rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: "
                          "the 257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
+    ap.add_argument("--check-interval", type=int, default=8,
+                    help="flower513, flower257: at most this many cycles per convergence check of the solve "
+                         "(bcmg_options.check_interval; 1 checks after every cycle)")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     ap.add_argument("--served-dtau", choices=["exp", "poly"], default="exp",
@@ -109,6 +112,16 @@ def parse():
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel of "
                          "known size, for scaling hardware traffic counters)")
     return ap.parse_args()
+
+
+def rho_last(hist):
+    """Per-cycle residual ratio between the last two checked cycles (cycles
+    without a check have NaN in the history)."""
+    idx = np.flatnonzero(~np.isnan(hist))
+    if len(idx) < 3:
+        return None
+    a, b = idx[-2], idx[-1]
+    return float((hist[b] / hist[a]) ** (1.0 / (b - a)))
 
 
 def main():
@@ -275,7 +288,7 @@ def bench_flower(args):
     torch.cuda.synchronize()
 
     def make_problem(prec):
-        G = Problem(3, N, phi, precision=prec, max_cycles=args.max_cycles)
+        G = Problem(3, N, phi, precision=prec, max_cycles=args.max_cycles, check_interval=args.check_interval)
         q = G.ghost_info(0)["q"]
         gq = torch.exp(q[:, 0] + q[:, 1] + q[:, 2])  # Dirichlet data g = exp(x+y+z) at the projections Q
         G.set_data(f, gq)
@@ -323,7 +336,8 @@ def bench_flower(args):
             "unknowns_per_s": unknowns * args.steps / elapsed, "ms_per_solve": elapsed * 1e3 / args.steps,
             "solve_ms_median": float(np.median(times) * 1e3), "solve_ms_device": st.solve_ms,
             "cycles": st.cycles, "rel_residual": st.r_final / st.r0,
-            "rho_last": float(hist[-1] / hist[-2]) if len(hist) > 2 else None,
+            "rho_last": rho_last(hist),
+            "checks": int(np.count_nonzero(~np.isnan(hist))) - 1,
             "setup_ms": setup_ms, "max_err_vs_exact": (u[inside] - ue[inside]).abs().max().item(),
             "unknowns": unknowns, "n_inside": info["n_inside"], "n_ghost": info["n_ghost"], "levels": G.levels,
         }
@@ -382,6 +396,7 @@ def bench_flower(args):
             "n_inside": r["n_inside"],
             "n_ghost": r["n_ghost"],
             "levels": r["levels"],
+            "check_interval": args.check_interval,
         },
         "roofline": {
             "bound": "hbm",

@@ -94,6 +94,8 @@ typedef struct {
     int32_t layout;        /* BCMG_LAYOUT_*: storage order of the library's own finest-level arrays */
     int32_t cycle;         /* BCMG_CYCLE_V (default) or BCMG_CYCLE_W */
     int32_t smoother;      /* BCMG_SMOOTH_RB (red-black Gauss-Seidel, default) or BCMG_SMOOTH_JACOBI */
+    int32_t check_interval; /* bcmg_solve: at most this many cycles per convergence check (1..8, default 1:
+                               a check after every cycle); see bcmg_solve */
 } bcmg_options;
 
 /* Cycle shape (Sec. 2.1: the two-grid scheme applied recursively, gamma
@@ -130,7 +132,9 @@ typedef struct {
     bcmg_status status;    /* BCMG_OK, _NOT_CONVERGED or _DIVERGED */
     double r0;             /* ||r^0||_2 over INSIDE and GHOST rows */
     double r_final;        /* ||r^m||_2 at exit */
-    double rho_mean;       /* mean of ||r^(m+1)||/||r^(m)|| over m = 11..15 (0 if fewer cycles) */
+    double rho_mean;       /* mean of ||r^(m+1)||/||r^(m)|| over m = 11..15 (0 if fewer cycles; if some of
+                              those cycles were not checked, the per-cycle rate between the nearest
+                              checked cycles around them) */
     double solve_ms;       /* device time of the solve (HIP events on the stream) */
 } bcmg_solve_stats;
 
@@ -268,6 +272,20 @@ bcmg_status bcmg_residual_norm_noalloc(bcmg_problem *prob, const double *u_dev, 
  * correction with an FP64 coarse solve, and an FP64 update (iterative
  * refinement).  hist_host (max_cycles+1 doubles, may be NULL) receives
  * ||r^m|| for m = 0..cycles.  Returns the solve status.
+ *
+ * Convergence checks.  A check is the residual norm over the finest level
+ * (in BCMG_MIXED mode also the update and the FP32 right-hand side of the
+ * next correction cycle).  With check_interval k > 1 the solve runs blocks
+ * of up to k cycles per check (in BCMG_MIXED mode: the block's FP32 cycles
+ * iterate on one correction equation) while the rate observed between the
+ * last two host-read checks predicts at least two more cycles after the
+ * block; the first two cycles and the last two predicted are checked one by
+ * one.  A
+ * cycle not followed by a check
+ * leaves NaN in hist_host.  Unchecked cycles count in cycles and max_cycles.
+ * The solve can run past the cycle where a per-cycle check would have
+ * stopped (by at most k - 1 cycles) only when the rate improves by more than
+ * the prediction allows.
  */
 bcmg_status bcmg_solve(bcmg_problem *prob, double *u_dev, double rel_tol, bcmg_solve_stats *stats_host,
                        double *hist_host);

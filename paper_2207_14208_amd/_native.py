@@ -33,7 +33,7 @@ class bcmg_options(C.Structure):
                 ("precision", C.c_int32), ("dtau_mode", C.c_int32), ("dtau_const", C.c_double),
                 ("ext_iters", C.c_int32), ("restrict_mode", C.c_int32), ("seg_len", C.c_int32),
                 ("bc", C.c_int32), ("reaction", C.c_double), ("layout", C.c_int32), ("cycle", C.c_int32),
-                ("smoother", C.c_int32)]
+                ("smoother", C.c_int32), ("check_interval", C.c_int32)]
 
 
 class bcmg_solve_stats(C.Structure):

@@ -181,6 +181,9 @@ struct bcmg_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_cycles = 0;
+    // bcmg_solve's blocks of j cycles with one check after them (j = 2..)
+    hipGraph_t bgraph[kMaxCheckInterval + 1] = {};
+    hipGraphExec_t bexec[kMaxCheckInterval + 1] = {};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // timing events of direct launches
 };
 
@@ -713,6 +716,7 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->layout = BCMG_LAYOUT_NATURAL;
     o->cycle = BCMG_CYCLE_V;
     o->smoother = BCMG_SMOOTH_RB;
+    o->check_interval = 1;
     return BCMG_OK;
 }
 
@@ -738,6 +742,8 @@ static bcmg_status check_options(int dim, int N, const bcmg_options *o) {
     if (o->layout != BCMG_LAYOUT_NATURAL && o->layout != BCMG_LAYOUT_SPLIT) return fail(BCMG_ERR_INVALID, "bad layout");
     if (o->cycle != BCMG_CYCLE_V && o->cycle != BCMG_CYCLE_W) return fail(BCMG_ERR_INVALID, "bad cycle");
     if (o->smoother != BCMG_SMOOTH_RB && o->smoother != BCMG_SMOOTH_JACOBI) return fail(BCMG_ERR_INVALID, "bad smoother");
+    if (o->check_interval < 1 || o->check_interval > kMaxCheckInterval)
+        return fail(BCMG_ERR_INVALID, "check_interval must be in 1..%d", kMaxCheckInterval);
     return BCMG_OK;
 }
 
@@ -1110,6 +1116,12 @@ static void drop_graph(bcmg_batch *b) {
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_cycles = 0;
+    for (int j = 0; j <= kMaxCheckInterval; j++) {
+        if (b->bexec[j]) hipGraphExecDestroy(b->bexec[j]);
+        if (b->bgraph[j]) hipGraphDestroy(b->bgraph[j]);
+        b->bexec[j] = nullptr;
+        b->bgraph[j] = nullptr;
+    }
     for (auto &pr : b->tev) {
         hipEventDestroy(pr.first);
         hipEventDestroy(pr.second);
@@ -1591,11 +1603,11 @@ static void wcycle_level(bcmg_batch *b, int a, bool restricted) {
 // cycle; an FP64 batch keeps only its norm, since the next cycle recomputes
 // r before the restriction reads it) plus per-slot norm and convergence
 // bookkeeping
-static void launch_outer_residual(bcmg_batch *b, int mode) {
+static void launch_outer_residual(bcmg_batch *b, int mode, int ncyc = 1) {
     launch_residual(b->d, 0, b->fp32, 1, b->d_outer, b->fsegs, b->nfseg, b->fgch, b->nfgch, b->d_state, b->d_partials,
                     b->stream, b->neu, b->fp32 ? 1 : 0);
     launch_norm_finish(b->d_ranges, b->cap, b->d_partials, b->nfseg, b->d_state, b->d_rtol2, b->d_hist,
-                       b->hist_stride, mode, nullptr, b->stream);
+                       b->hist_stride, mode, nullptr, b->stream, ncyc);
 }
 
 // one multigrid cycle of the batch's shape on the correction equations
@@ -1606,10 +1618,12 @@ static void launch_mg_cycle(bcmg_batch *b) {
         launch_vcycle(b);
 }
 
-static void launch_cycle(bcmg_batch *b) {
-    launch_mg_cycle(b);
+// ncyc cycles and one convergence check after them; in mixed precision the
+// ncyc FP32 cycles iterate on one correction equation before the update
+static void launch_cycle(bcmg_batch *b, int ncyc = 1) {
+    for (int c = 0; c < ncyc; c++) launch_mg_cycle(b);
     if (b->fp32) launch_ir_update(b->d_outer, b->fsegs, b->nfseg, b->d_state, b->d_eptr, b->stream);
-    launch_outer_residual(b, 1);
+    launch_outer_residual(b, 1, ncyc);
 }
 
 static bcmg_status batch_init_slot(bcmg_batch *b, int slot, double rtol) {
@@ -1765,6 +1779,30 @@ static bcmg_status batch_launch_cycles(bcmg_batch *b, int cycles) {
     return BCMG_OK;
 }
 
+// ncyc cycles with one check after them (bcmg_solve's blocks); one graph per
+// block length, captured on first use
+static bcmg_status batch_launch_block(bcmg_batch *b, int ncyc) {
+    if (ncyc <= 1) return batch_launch_cycles(b, 1);
+    if (b->dirty) {
+        bcmg_status st = batch_rebuild(b);
+        if (st) return st;
+    }
+    if (g_timing.on) {
+        launch_cycle(b, ncyc);
+        HIPCHK(hipGetLastError());
+        return BCMG_OK;
+    }
+    if (!b->bexec[ncyc]) {
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        launch_cycle(b, ncyc);
+        hipError_t e = hipStreamEndCapture(b->stream, &b->bgraph[ncyc]);
+        if (e != hipSuccess) return fail(BCMG_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        HIPCHK(hipGraphInstantiate(&b->bexec[ncyc], b->bgraph[ncyc], nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(b->bexec[ncyc], b->stream));
+    return BCMG_OK;
+}
+
 // after a synchronisation: add the timed launches to the process-wide counters
 static void drain_timing(bcmg_batch *b) {
     if (b->tev.empty()) return;
@@ -1824,8 +1862,18 @@ bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stat
         stats->r_final = std::sqrt(S.lastsq);
         double rho = 0.0;
         if (c >= 16) {
-            for (int m = 11; m <= 15; m++) rho += h[m + 1] / h[m];
-            rho /= 5.0;
+            bool all = true;
+            for (int m = 11; m <= 16; m++) all = all && !std::isnan(h[m]);
+            if (all) {
+                for (int m = 11; m <= 15; m++) rho += h[m + 1] / h[m];
+                rho /= 5.0;
+            } else {  // unchecked cycles: the per-cycle rate between the checks around the window
+                int ma = 11, mb = 16;
+                while (ma > 0 && std::isnan(h[ma])) ma--;
+                while (mb < c && std::isnan(h[mb])) mb++;
+                if (!std::isnan(h[ma]) && !std::isnan(h[mb]) && h[ma] > 0.0)
+                    rho = std::pow(h[mb] / h[ma], 1.0 / (mb - ma));
+            }
         }
         stats->rho_mean = rho;
         stats->solve_ms = 0.0;
@@ -1872,27 +1920,40 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     if ((st = batch_join(b))) return st;
-    // The one-cycle graph is replayed k times between host checks, with k
-    // the number of cycles the observed convergence rate still needs (at
-    // least 1, at most 16): the host waits on the device once per check
-    // rather than once per cycle.  Cycles replayed after convergence find
-    // the slot inactive and change nothing.
-    int k = 1, checked_cycles = 0;
+    // The host waits on the device once per k cycles, with k the number of
+    // cycles the observed convergence rate still needs (at least 1, at most
+    // 16).  Cycles launched after convergence find the slot inactive and
+    // change nothing.  Those k cycles run in blocks of up to check_interval
+    // cycles with a device-side check after each block, as long as at least
+    // two predicted cycles remain after the block; the rest are checked one
+    // by one.
+    const int J = P->opt.check_interval;
+    int k = 1, tail = 1, checked_cycles = 0;
     double checked_sq = -1.0;
     while (b->h_state[0].active) {
-        for (int i = 0; i < k; i++)
+        int left = k;
+        while (left > tail && J > 1) {
+            const int j = std::min(J, left - tail);
+            if ((st = batch_launch_block(b, j))) return st;
+            left -= j;
+        }
+        for (int i = 0; i < left; i++)
             if ((st = batch_launch_cycles(b, 1))) return st;
         HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(SlotState), hipMemcpyDeviceToHost, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));
         drain_timing(b);
         const SlotState &S = b->h_state[0];
         k = 1;
+        tail = 1;
         const int dc = S.cycles - checked_cycles;
         if (S.active && checked_sq > 0.0 && dc > 0 && S.lastsq > 0.0 && S.lastsq < checked_sq && S.tolsq > 0.0) {
             const double rate = std::log(S.lastsq / checked_sq) / dc;  // log of rho^2 per cycle, < 0
             const double need = std::log(S.tolsq / S.lastsq) / rate;   // cycles still needed
-            if (need > 1.0) k = (int)std::min(16.0, std::floor(need));
+            const double nc = std::min(1e6, std::floor(need));
+            if (need > 1.0) k = (int)std::min(16.0, nc);
             k = std::max(1, std::min(k, S.max_cycles - S.cycles));
+            // the cycles predicted to be the last two are checked one by one
+            tail = (int)std::max(0.0, 2.0 - (nc - k));
         }
         checked_cycles = S.cycles;
         checked_sq = S.lastsq;

@@ -38,6 +38,8 @@ constexpr long long kCoarseNodes = 5000;
 // FP32 red-black launches over at least this many row segments give each
 // wavefront two of them (BCMG_PARAM_SWEEP_PAIR_SEGS)
 constexpr int kSweepPairSegs = 32768;
+// largest check_interval (cycles per convergence check of bcmg_solve)
+constexpr int kMaxCheckInterval = 8;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than
 // this are stored split by node parity under BCMG_LAYOUT_SPLIT
 constexpr long long kSplitMinNodes = 1 << 17;

@@ -743,14 +743,16 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const Desc *__restrict__ desc
 
 // Per-slot sum of the partials in a fixed order (thread t adds entries t,
 // t + 1024, ..., then a tree), then the convergence test.  mode 0: ||r^0|| of slots
-// waiting for it; mode 1: after a cycle; mode 2: only store the norm.
+// waiting for it; mode 1: after ncyc cycles (the first ncyc - 1 of them were
+// not followed by a check; their history entries are NaN); mode 2: only store
+// the norm.
 constexpr int kNormThreads = 1024;
 __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
                                                               const double *__restrict__ partials, int nseg_total,
                                                               SlotState *__restrict__ st,
                                                               const double *__restrict__ rtol2,
                                                               double *__restrict__ hist, int hist_stride, int mode,
-                                                              double *__restrict__ out) {
+                                                              int ncyc, double *__restrict__ out) {
     const int s = blockIdx.x;
     if (s >= nslots) return;
     if (mode == 1 && st[s].active != 1) return;
@@ -799,11 +801,14 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
         S.active = finite && tot > 0.0 ? 1 : 0;
         if (hist) hist[(long long)s * hist_stride] = sqrt(tot);
     } else if (mode == 1) {
-        const int c = S.cycles + 1;
+        const int c0 = S.cycles, c = c0 + ncyc;
         S.cycles = c;
         S.lastsq = tot;
-        if (hist && c < hist_stride) hist[(long long)s * hist_stride + c] = sqrt(tot);
-        if (c == 1) S.refsq = fmax(S.r0sq, tot);
+        if (hist) {
+            for (int k = c0 + 1; k < c && k < hist_stride; k++) hist[(long long)s * hist_stride + k] = __builtin_nan("");
+            if (c < hist_stride) hist[(long long)s * hist_stride + c] = sqrt(tot);
+        }
+        if (c0 == 0) S.refsq = fmax(S.r0sq, tot);
         if (!isfinite(tot)) {
             S.active = 0;
             S.status = BCMG_ERR_DIVERGED;
@@ -1452,10 +1457,11 @@ void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, con
 }
 
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
-                        const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s) {
+                        const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s,
+                        int ncyc) {
     if (nslots <= 0) return;
     hipLaunchKernelGGL(k_norm_finish, dim3(nslots), dim3(kNormThreads), 0, s, ranges, nslots, partials, nseg_total,
-                       st, rtol2, hist, hist_stride, mode, out);
+                       st, rtol2, hist, hist_stride, mode, ncyc, out);
 }
 
 void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,

@@ -25,8 +25,10 @@ void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
                      const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu = 0,
                      int store = 1);
+// mode 1: the check after ncyc cycles (ncyc - 1 of them unchecked)
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
-                        const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s);
+                        const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s,
+                        int ncyc = 1);
 // extension of u into the band chunks bch (ghost values read from u)
 // via_need: the chunks run over the needed band entries (bneed) instead of all of them
 void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,

@@ -513,3 +513,60 @@ def test_solve_parity_cycle_and_smoother_options(name, variant):
     u_after = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
     O.solve(u_after, 0.0, st.cycles)
     assert _close(u_after, ug.cpu().numpy(), 1e-12)
+
+
+@pytest.mark.parametrize("name", ["circle65", "flower3d_65", "star_257"])
+@pytest.mark.parametrize("interval", [3, 8])
+def test_solve_with_deferred_checks(name, interval):
+    """check_interval > 1: blocks of cycles with one convergence check each
+    while the observed rate predicts at least two more cycles.  The cycle
+    count may only exceed the per-cycle count by what a block can overrun
+    (interval - 1), the checked norms agree with the oracle's, unchecked
+    cycles leave NaN, and u equals the oracle's after the GPU's cycle count."""
+    Problem = _gpu()
+    c = CASES[name]()
+    O = oracle.Problem(c.d, c.N, c.phi)
+    G = Problem(c.d, c.N, c.phi, check_interval=interval)
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    it, ho = O.solve(uo, 1e-10)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hg = G.solve(ug, 1e-10)
+    assert it > 0 and st.status == 0, (it, st)
+    floor = residual_floor(c.d, c.N, cls, uo, O.rhs(0))
+    assert it - 1 <= st.cycles <= it + interval - 1, (st.cycles, it)
+    checked = ~np.isnan(hg)
+    assert checked[0] and checked[1] and checked[2] and checked[st.cycles]
+    assert (~checked).sum() > 0, "no check was deferred"
+    n = min(len(hg), len(ho))
+    m = checked[:n]
+    assert np.all(np.abs(hg[:n][m] - ho[:n][m]) <= 1e-8 * ho[:n][m] + floor)
+    assert hg[st.cycles] <= 1e-10 * hg[0] * (1 + 1e-8) + floor
+    assert _close(oracle_after(c, O, st.cycles), ug.cpu().numpy(), 1e-12)
+
+
+@pytest.mark.parametrize("name", ["flower3d_65", "star_257"])
+def test_mixed_precision_with_deferred_checks(name):
+    """Mixed precision with check_interval 4: the FP32 cycles of a block
+    iterate on one correction equation before the FP64 update.  The final u
+    meets the FP64 residual tolerance (by the oracle's residual) and lies
+    within 1e-8 of the oracle's FP64 solution."""
+    from paper_2207_14208_amd import _native as NAT
+    Problem = _gpu()
+    c = CASES[name]()
+    O = oracle.Problem(c.d, c.N, c.phi)
+    G = Problem(c.d, c.N, c.phi, precision=NAT.MIXED, check_interval=4)
+    _rhs_pair(c, O, G)
+    cls = O.classes(0)
+    uo = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    O.solve(uo, 1e-12)
+    ug = G.initial_guess(torch.from_numpy(c.gB).cuda())
+    st, hg = G.solve(ug, 1e-10)
+    assert st.status == 0, st
+    assert np.isnan(hg).sum() > 0, "no check was deferred"
+    u = ug.cpu().numpy()
+    r0 = O.norm(0, O.residual(0, np.where(cls == oracle.BOXDIR, c.gB, 0.0)))
+    assert O.norm(0, O.residual(0, u)) <= 1e-10 * r0 * 1.001
+    m = unknowns(cls)
+    assert np.max(np.abs(u[m] - uo[m])) <= 1e-8 * np.max(np.abs(uo[m]))
