@@ -117,6 +117,7 @@ def parse():
 def rho_last(hist):
     """Per-cycle residual ratio between the last two checked cycles (cycles
     without a check have NaN in the history)."""
+    import numpy as np
     idx = np.flatnonzero(~np.isnan(hist))
     if len(idx) < 3:
         return None

@@ -17,3 +17,16 @@ def test_more_than_one_gpu_is_refused():
     assert len(lines) == 1
     msg = json.loads(lines[0])
     assert "error" in msg and "one GPU" in msg["error"]
+
+
+def test_rho_last_skips_unchecked_cycles():
+    # cycles without a check carry NaN in the history; the rate is taken
+    # per cycle between the last two checked entries
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    nan = float("nan")
+    h = np.array([1.0, 0.5, 0.25, nan, nan, 0.25 * 0.125, nan, 0.25 * 0.125 * 0.25])
+    assert abs(bench.rho_last(h) - 0.5) < 1e-15
+    assert abs(bench.rho_last(np.array([1.0, 0.5, 0.2])) - 0.4) < 1e-15
+    assert bench.rho_last(np.array([1.0, 0.5])) is None
