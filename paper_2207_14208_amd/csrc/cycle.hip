@@ -46,8 +46,11 @@ __device__ __forceinline__ double lagrange_dt(int w, int m, double t) {  // d/dt
 // the ghost's derivative coefficients nd = gnd[3g..3g+2].  The 3^d candidate
 // nodes are loaded first (nodes outside the stencil read G itself), then
 // accumulated in lexicographic order of m.  Kernels without NEU keep the
-// register footprint of the Dirichlet row.
-template <int D, bool NEU, typename PI, typename PD, typename PU>
+// register footprint of the Dirichlet row.  PLANES (Dirichlet rows): load and
+// accumulate one plane of m2 at a time (the same terms in the same order, so
+// the same result) - three memory round trips instead of one, but a third
+// of the registers, for kernels whose other work needs the occupancy.
+template <int D, bool NEU, bool PLANES = false, typename PI, typename PD, typename PU>
 __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, PD gnd, bool neu, long long sy, long long sz,
                                                int g, PU u) {
     const long long p = gidx[g];
@@ -65,6 +68,35 @@ __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, PD gn
         for (int m = 0; m < 3; m++) la[k][m] = lagrange(w[k], m, t);
     }
     constexpr int M1 = D >= 2 ? 3 : 1, M2 = D >= 3 ? 3 : 1;
+    if constexpr (PLANES && !NEU) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 < M2; m2++) {
+            double pv[M1][3];
+#pragma unroll
+            for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+                for (int m0 = 0; m0 < 3; m0++) {
+                    const bool in = m0 < w[0] && m1 < w[1] && m2 < w[2];
+                    const long long q = in ? p - m0 * step[0] - m1 * step[1] - m2 * step[2] : p;
+                    pv[m1][m0] = (double)u[q];
+                }
+#pragma unroll
+            for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+                for (int m0 = 0; m0 < 3; m0++) {
+                    if (!(m0 < w[0] && m1 < w[1] && m2 < w[2])) continue;
+                    double wgt = 1.0;
+                    wgt *= la[0][m0];
+                    wgt *= la[1][m1];
+                    wgt *= la[2][m2];
+                    acc += wgt * pv[m1][m0];
+                }
+            // the next plane's loads stay below this point
+            asm volatile("" ::"v"(acc) : "memory");
+        }
+        return acc;
+    }
     double val[M2][M1][3];
 #pragma unroll
     for (int m2 = 0; m2 < M2; m2++)
@@ -119,10 +151,10 @@ __device__ __forceinline__ double ghost_row_at(PI gidx, PI gcode, PD gtau, PD gn
     return acc;
 }
 
-template <int D, typename T, bool NEU>
+template <int D, typename T, bool NEU, bool PLANES = false>
 __device__ __forceinline__ double ghost_row(const Desc &L, int g, const NodeArr<const T> &u) {
-    return ghost_row_at<D, NEU>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, (gcp<double>)L.gnd,
-                                L.gnd != nullptr, L.sy, L.sz, g, u);
+    return ghost_row_at<D, NEU, PLANES>((gcp<int>)L.gidx, (gcp<int>)L.gcode, (gcp<double>)L.gtau, (gcp<double>)L.gnd,
+                                        L.gnd != nullptr, L.sy, L.sz, g, u);
 }
 
 // ------------------------------------------------------------ node updates
@@ -193,55 +225,66 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
 // FW of the fine residual r over the 3^d box around fine node X for a
 // coarse INSIDE row: all of the box INSIDE and in the grid, else the FW
 // weights of its INSIDE nodes renormalised (or their plain mean).
-template <int D, typename PR, typename PC>
+// PLANES: load and accumulate one plane of m2 at a time (the same terms in
+// the same order), a third of the registers for three memory round trips.
+template <int D, bool PLANES = false, typename PR, typename PC>
 __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long long fsy, long long fsz, int X0,
                                                      int X1, int X2, int mode) {
     constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
-    uint8_t fc[2 * R2 + 1][2 * R1 + 1][3];
-    double rv[2 * R2 + 1][2 * R1 + 1][3];
-    bool inb[2 * R2 + 1][2 * R1 + 1][3];
+    constexpr int NP = PLANES ? 2 * R2 + 1 : 1;  // planes loaded together
+    constexpr int NL = PLANES ? 1 : 2 * R2 + 1;  // planes per load group
     const long long pf = X0 + X1 * fsy + X2 * fsz;
-#pragma unroll
-    for (int m2 = -R2; m2 <= R2; m2++)
-#pragma unroll
-        for (int m1 = -R1; m1 <= R1; m1++)
-#pragma unroll
-            for (int m0 = -1; m0 <= 1; m0++) {
-                const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
-                const bool in = J0 >= 0 && J0 <= FN && (D < 2 || (J1 >= 0 && J1 <= FN)) &&
-                                (D < 3 || (J2 >= 0 && J2 <= FN));
-                const long long q = in ? pf + m0 + m1 * fsy + m2 * fsz : pf;
-                inb[m2 + R2][m1 + R1][m0 + 1] = in;
-                fc[m2 + R2][m1 + R1][m0 + 1] = fcls[q];
-                rv[m2 + R2][m1 + R1][m0 + 1] = (double)r[q];
-            }
     double full = 0.0, sel = 0.0, selw = 0.0, msum = 0.0, mcnt = 0.0;
     bool all_ok = true;
 #pragma unroll
-    for (int m2 = -R2; m2 <= R2; m2++)
+    for (int g = 0; g < NP; g++) {
+        uint8_t fc[NL][2 * R1 + 1][3];
+        double rv[NL][2 * R1 + 1][3];
+        bool inb[NL][2 * R1 + 1][3];
 #pragma unroll
-        for (int m1 = -R1; m1 <= R1; m1++)
+        for (int i2 = 0; i2 < NL; i2++)
 #pragma unroll
-            for (int m0 = -1; m0 <= 1; m0++) {
-                double wgt = 1.0;
-                wgt *= (m0 == 0 ? 0.5 : 0.25);
-                if (D >= 2) wgt *= (m1 == 0 ? 0.5 : 0.25);
-                if (D >= 3) wgt *= (m2 == 0 ? 0.5 : 0.25);
-                if (!inb[m2 + R2][m1 + R1][m0 + 1]) {
-                    all_ok = false;
-                    continue;
+            for (int m1 = -R1; m1 <= R1; m1++)
+#pragma unroll
+                for (int m0 = -1; m0 <= 1; m0++) {
+                    const int m2 = g + i2 - R2;
+                    const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
+                    const bool in = J0 >= 0 && J0 <= FN && (D < 2 || (J1 >= 0 && J1 <= FN)) &&
+                                    (D < 3 || (J2 >= 0 && J2 <= FN));
+                    const long long q = in ? pf + m0 + m1 * fsy + m2 * fsz : pf;
+                    inb[i2][m1 + R1][m0 + 1] = in;
+                    fc[i2][m1 + R1][m0 + 1] = fcls[q];
+                    rv[i2][m1 + R1][m0 + 1] = (double)r[q];
                 }
-                const bool take = fc[m2 + R2][m1 + R1][m0 + 1] == C_INSIDE;
-                if (!take) all_ok = false;
-                const double v = rv[m2 + R2][m1 + R1][m0 + 1];
-                full += wgt * v;
-                if (take) {
-                    sel += wgt * v;
-                    selw += wgt;
-                    msum += v;
-                    mcnt += 1.0;
+#pragma unroll
+        for (int i2 = 0; i2 < NL; i2++)
+#pragma unroll
+            for (int m1 = -R1; m1 <= R1; m1++)
+#pragma unroll
+                for (int m0 = -1; m0 <= 1; m0++) {
+                    const int m2 = g + i2 - R2;
+                    double wgt = 1.0;
+                    wgt *= (m0 == 0 ? 0.5 : 0.25);
+                    if (D >= 2) wgt *= (m1 == 0 ? 0.5 : 0.25);
+                    if (D >= 3) wgt *= (m2 == 0 ? 0.5 : 0.25);
+                    if (!inb[i2][m1 + R1][m0 + 1]) {
+                        all_ok = false;
+                        continue;
+                    }
+                    const bool take = fc[i2][m1 + R1][m0 + 1] == C_INSIDE;
+                    if (!take) all_ok = false;
+                    const double v = rv[i2][m1 + R1][m0 + 1];
+                    full += wgt * v;
+                    if (take) {
+                        sel += wgt * v;
+                        selw += wgt;
+                        msum += v;
+                        mcnt += 1.0;
+                    }
                 }
-            }
+        // the next plane's loads stay below this point
+        if (PLANES) asm volatile("" ::"v"(full), "v"(sel), "v"(selw), "v"(msum) : "memory");
+    }
     if (all_ok) return full;
     if (mode == BCMG_RESTRICT_PLAIN_MEAN) return mcnt > 0.0 ? msum / mcnt : 0.0;
     return selw > 0.0 ? sel / selw : 0.0;
@@ -258,8 +301,8 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
                                               bool red, T &fv, T &uv, int &cc) {
-    const double out = restrict_inside_at<D>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
-                                             C.restrict_mode);
+    const double out = restrict_inside_at<D, true>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1,
+                                                   X2, C.restrict_mode);
     cc = ((gcp<uint8_t>)C.cls)[pc];
     fv = (T)out;
     uv = (T)0;
@@ -507,7 +550,7 @@ template <int D, typename Tu, typename Tr, bool NEU>
 __device__ __forceinline__ double ghost_residual(const Desc &L, int g, bool live, bool store = true) {
     const long long pg = ((gcp<int>)L.gidx)[g];
     const double rg = (double)node_rhs<const Tu>(L)[pg];
-    const double r = rg - ghost_row<D, Tu, NEU>(L, g, node_u<const Tu>(L));
+    const double r = rg - ghost_row<D, Tu, NEU, true>(L, g, node_u<const Tu>(L));
     pin(r);
     if (!live) return 0.0;
     if (store) node_r<Tr>(L)[pg] = (Tr)r;
