@@ -497,16 +497,76 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
     v = (T)((double)node_u<const T>(F)[p] + e);
 }
 
+// Prolongation at two x-adjacent fine nodes I0 and I0 + 1 of one row: both
+// read coarse x-positions B and B + 1 only (B = floor(I0 / 2)), so the coarse
+// values are loaded once for the pair; each node then sums its corners as
+// prolong_at does (the same terms in the same order).  bvalid: node I0 + 1 is
+// wanted (else x = B + 1 is read only if node I0 needs it: with I0 even on
+// the box face, B + 1 lies beyond the row).
+template <int D, typename PE>
+__device__ __forceinline__ void prolong_pair(PE ec, long long csy, long long csz, int I0, int I1, int I2,
+                                             bool bvalid, double &ea, double &eb) {
+    const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
+    const int B0 = (I0 - h0) / 2, B1 = (I1 - h1) / 2, B2 = (I2 - h2) / 2;
+    constexpr int M1 = D >= 2 ? 2 : 1, M2 = D >= 3 ? 2 : 1;
+    double ev[M2][M1][2];  // coarse values at x = B0, B0 + 1
+    const long long b = B0 + B1 * csy + B2 * csz;
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                const bool in = m1 <= h1 && m2 <= h2 && (c == 0 || h0 == 1 || bvalid);
+                ev[m2][m1][c] = (double)ec[in ? b + c + m1 * csy + m2 * csz : b];
+            }
+    // node a = I0 (corners x = B0 .. B0 + h0); node b = I0 + 1: with I0 even
+    // it is odd over B0, B0 + 1, with I0 odd it is even at B0 + 1 alone
+    double a = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+        for (int m1 = 0; m1 < M1; m1++) {
+            if (!(m1 <= h1 && m2 <= h2)) continue;
+#pragma unroll
+            for (int m0 = 0; m0 < 2; m0++) {
+                if (m0 <= h0) {  // node a, corner x = B0 + m0
+                    double wgt = 1.0;
+                    if (h0) wgt *= 0.5;
+                    if (h1) wgt *= 0.5;
+                    if (h2) wgt *= 0.5;
+                    a += wgt * ev[m2][m1][m0];
+                }
+                if (m0 <= 1 - h0) {  // node b, corner x = (B0 + h0) + m0
+                    double wgt = 1.0;
+                    if (!h0) wgt *= 0.5;
+                    if (h1) wgt *= 0.5;
+                    if (h2) wgt *= 0.5;
+                    e2 += wgt * ev[m2][m1][h0 + m0];
+                }
+            }
+        }
+    ea = a;
+    eb = e2;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
+    // lane takes the adjacent nodes q0 = 2 lane and q0 + 1 (for a split
+    // array, one of each parity: both loads stay contiguous per half)
+    const int q0 = 2 * lane;
+    const int qa = q0 < s.len ? q0 : 0;
+    double e[2];
+    prolong_pair<D>(node_u<const T>(C), C.sy, C.sz, s.x0 + qa, s.yj, s.zk, q0 + 1 < s.len, e[0], e[1]);
     T v[2];
     int fc[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {  // both nodes computed before either store
-        const int q = seg_lane_node(lane, h, F.half_u);
-        const int qq = q < s.len ? q : 0;
-        prolong_node<D, T>(F, C, s.p0 + qq, s.x0 + qq, s.yj, s.zk, v[h], fc[h]);
+        const int q = q0 + h;
+        const long long p = s.p0 + (q < s.len ? q : qa);
+        fc[h] = ((gcp<uint8_t>)F.cls)[p];
+        v[h] = (T)((double)node_u<const T>(F)[p] + e[h]);
     }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
@@ -515,7 +575,7 @@ __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const 
     }
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int q = seg_lane_node(lane, h, F.half_u);
+        const int q = q0 + h;
         if (!live || q >= s.len || (fc[h] != C_INSIDE && fc[h] != C_GHOST)) continue;
         node_u<T>(F)[s.p0 + q] = v[h];
     }
