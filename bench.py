@@ -571,7 +571,8 @@ def bench_batched(args):
     mixed precision, solved together by the batched engine (hipGraph-replayed
     cycles, per-problem coarse workgroups, autotuned row tile, coarse
     threshold and cycles per replay), against the same problems solved one
-    after another by the plain FP64 solver."""
+    after another by the single-problem solver, in FP64 and in mixed
+    precision."""
     import numpy as np
     import torch
 
@@ -603,19 +604,25 @@ def bench_batched(args):
         times.append(r.elapsed_s)
     el = float(np.median(times))
     ok = sum(1 for s in r.status if s == 0)
-    print(f"batched: {el * 1e3:.1f} ms per batch solve; plain solves next", file=sys.stderr, flush=True)
-    # plain FP64 solver, one problem after another (same problems, same tolerance)
-    plain_el = 0.0
-    plain_cycles = []
-    for c in cases:
-        G, u, _ = make_problem(c, BatchConfig(seg_len=128, precision=NAT.FP64, max_cycles=args.max_cycles))
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        st, _ = G.solve(u, 1e-10)
-        torch.cuda.synchronize()
-        plain_el += time.perf_counter() - ts
-        plain_cycles.append(st.cycles)
-        G.close()
+    print(f"batched: {el * 1e3:.1f} ms per batch solve; one-by-one solves next", file=sys.stderr, flush=True)
+    # the single-problem solver, one problem after another (same problems,
+    # same tolerance), in FP64 and in mixed precision: the first comparison
+    # is batching and precision together, the second batching alone
+    one_by_one = {}
+    for pname, prec in (("fp64", NAT.FP64), ("mixed", NAT.MIXED)):
+        el1, cyc1 = 0.0, []
+        for c in cases:
+            G, u, _ = make_problem(c, BatchConfig(seg_len=128, precision=prec, max_cycles=args.max_cycles))
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st, _ = G.solve(u, 1e-10)
+            torch.cuda.synchronize()
+            el1 += time.perf_counter() - ts
+            cyc1.append(st.cycles)
+            G.close()
+        one_by_one[pname] = (el1, cyc1)
+    plain_el, plain_cycles = one_by_one["fp64"]
+    mixed_el, mixed_cycles = one_by_one["mixed"]
     out = {"metric": METRIC,
            "value": r.unknowns / el, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -630,7 +637,10 @@ def bench_batched(args):
                              "frac_of_8TBps": r.alg_bytes / el / 8e12},
            "plain_fp64_one_by_one": {"unknowns_per_s": r.unknowns / plain_el, "seconds": plain_el,
                                      "cycles_median": int(np.median(plain_cycles))},
-           "speedup_vs_plain": (r.unknowns / el) / (r.unknowns / plain_el)}
+           "mixed_one_by_one": {"unknowns_per_s": r.unknowns / mixed_el, "seconds": mixed_el,
+                                "cycles_median": int(np.median(mixed_cycles))},
+           "speedup_vs_plain": (r.unknowns / el) / (r.unknowns / plain_el),
+           "speedup_of_batching": (r.unknowns / el) / (r.unknowns / mixed_el)}
     print(json.dumps(out))
     bs.close()
 

@@ -229,6 +229,18 @@ bcmg_status bcmg_ghost_info(const bcmg_problem *prob, int32_t level, int32_t *id
                             int32_t *fallback_dev);
 
 /*
+ * Stencil statistics of a level's ghost rows (Sec. 3.3, the widths of R8 and
+ * the fallbacks above), counted on the host from the level's codes and
+ * flags.  counts_host (27 int64, may be NULL): counts_host[k] is the number of
+ * rows whose widths, sorted in decreasing order with missing axes taken as 1,
+ * are (a, b, c) with k = 9 (3 - a) + 3 (3 - b) + (3 - c): k = 0 is (3,3,3),
+ * 13 is (2,2,2), 26 is (1,1,1).  root_fallback_host / row_fallback_host (may
+ * be NULL): rows with fallback bit 0 / bit 1 set.
+ */
+bcmg_status bcmg_ghost_stats(const bcmg_problem *prob, int32_t level, int64_t *counts_host,
+                             int64_t *root_fallback_host, int64_t *row_fallback_host);
+
+/*
  * Right-hand side of the finest level: f_dev (nodes; used on INSIDE nodes) and
  * gq_dev (n_ghost values g(Q) in ghost-list order, the boundary data at the
  * projections returned by bcmg_ghost_info; for Neumann rows the normal

@@ -60,6 +60,7 @@ PROTOTYPES = {
     "bcmg_level_info": (i32, [vp, i32, P(i32), P(i64), P(i64), P(i64), P(i64)]),
     "bcmg_classes": (i32, [vp, i32, vp]),
     "bcmg_ghost_info": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+    "bcmg_ghost_stats": (i32, [vp, i32, P(i64), P(i64), P(i64)]),
     "bcmg_set_data": (i32, [vp, vp, vp]),
     "bcmg_fill_boundary": (i32, [vp, vp, vp]),
     "bcmg_vcycle": (i32, [vp, vp]),

@@ -935,6 +935,32 @@ bcmg_status bcmg_ghost_info(const bcmg_problem *P, int32_t l, int32_t *idx, int3
     return BCMG_OK;
 }
 
+bcmg_status bcmg_ghost_stats(const bcmg_problem *P, int32_t l, int64_t *counts, int64_t *root_fallback,
+                             int64_t *row_fallback) {
+    if (!valid_level(P, l)) return fail(BCMG_ERR_INVALID, "bad problem or level");
+    const LevelH &V = P->lev[l];
+    const size_t ng = (size_t)V.ng;
+    std::vector<int32_t> code(ng), fb(ng);
+    if (ng) {
+        HIPCHK(hipMemcpyAsync(code.data(), V.gcode, ng * 4, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(fb.data(), V.gfb, ng * 4, hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+    }
+    int64_t c[27] = {0}, nroot = 0, nrow = 0;
+    for (size_t g = 0; g < ng; g++) {
+        int w[3] = {1, 1, 1};
+        for (int k = 0; k < P->d; k++) w[k] = code_w(code[g], k);
+        std::sort(w, w + 3, [](int a, int b) { return a > b; });
+        c[(3 - w[0]) * 9 + (3 - w[1]) * 3 + (3 - w[2])]++;
+        nroot += fb[g] & 1;
+        nrow += (fb[g] >> 1) & 1;
+    }
+    if (counts) std::copy(c, c + 27, counts);
+    if (root_fallback) *root_fallback = nroot;
+    if (row_fallback) *row_fallback = nrow;
+    return BCMG_OK;
+}
+
 bcmg_status bcmg_set_data(bcmg_problem *P, const double *f, const double *gq) {
     if (!P) return fail(BCMG_ERR_INVALID, "null problem");
     if (!gq && P->lev[0].ng > 0) return fail(BCMG_ERR_INVALID, "null ghost data");

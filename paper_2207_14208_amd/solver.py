@@ -162,6 +162,15 @@ class Problem:
             check(lib().bcmg_ghost_info(self.h, level, *[_ptr(g[k]) for k in ("idx", "code", "eta", "n", "q", "tau", "dtau", "fb")]))
         return g
 
+    def ghost_stats(self, level: int = 0) -> dict:
+        """bcmg_ghost_stats: {"widths": {(a, b, c): rows, ...} (sorted widths,
+        nonzero classes only), "root_fallback": n, "row_fallback": n}."""
+        counts = (C.c_int64 * 27)()
+        root, row = C.c_int64(), C.c_int64()
+        check(lib().bcmg_ghost_stats(self.h, level, counts, C.byref(root), C.byref(row)))
+        widths = {(3 - k // 9, 3 - (k // 3) % 3, 3 - k % 3): int(counts[k]) for k in range(27) if counts[k]}
+        return {"widths": widths, "root_fallback": root.value, "row_fallback": row.value}
+
     # ---------------------------------------------------------------- data
     def set_data(self, f, gq):
         f_d = _dev_f64(f) if f is not None else None

@@ -570,3 +570,38 @@ def test_mixed_precision_with_deferred_checks(name):
     assert O.norm(0, O.residual(0, u)) <= 1e-10 * r0 * 1.001
     m = unknowns(cls)
     assert np.max(np.abs(u[m] - uo[m])) <= 1e-8 * np.max(np.abs(uo[m]))
+
+
+@pytest.mark.parametrize("name", ["circle65", "flower3d_65", "spheres_65", "line1d_129"])
+def test_ghost_stats_match_oracle(name):
+    """bcmg_ghost_stats on every level: the histogram of sorted stencil widths
+    and the fallback counts equal those of the oracle's ghost rows."""
+    from collections import Counter
+    c, O, G = build_pair(name)
+    for l in range(G.levels):
+        g = O.ghosts(l)
+        w = np.array(g["w"], dtype=np.int64).reshape(-1, 3)
+        w[:, c.d:] = 1
+        expect = Counter(tuple(int(v) for v in sorted(row, reverse=True)) for row in w)
+        got = G.ghost_stats(l)
+        assert got["widths"] == dict(expect), (l, got["widths"], expect)
+        assert got["root_fallback"] == int(np.count_nonzero(g["fb"] & 1))
+        assert got["row_fallback"] == int(np.count_nonzero(g["fb"] & 2))
+
+
+def test_ghost_stats_count_neumann_row_fallbacks():
+    """The 30-sphere union with Neumann rows has coarse levels whose rows fall
+    back to the one-sided difference (bit 1 of the flags): counted alike."""
+    from paper_2207_14208_amd import _native as NAT
+    Problem = _gpu()
+    c = spheres_case(64)
+    O = oracle.Problem(c.d, c.N, c.phi, oracle.Options(bc=oracle.BC_NEUMANN, reaction=1.0))
+    G = Problem(c.d, c.N, c.phi, bc=NAT.BC_NEUMANN, reaction=1.0)
+    total = 0
+    for l in range(G.levels):
+        fb = O.ghosts(l)["fb"]
+        got = G.ghost_stats(l)
+        assert got["row_fallback"] == int(np.count_nonzero(fb & 2))
+        assert got["root_fallback"] == int(np.count_nonzero(fb & 1))
+        total += got["row_fallback"]
+    assert total > 0
