@@ -103,6 +103,11 @@ def parse():
                     help="flower513, flower257: at most this many cycles per convergence check of the solve "
                          "(bcmg_options.check_interval; 1 checks after every cycle)")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")
+    ap.add_argument("--tuned", default="",
+                    help="batched: SEG_LEN,COARSE_NODES,CYCLES_PER_STEP instead of the autotuner's choice (for "
+                         "counter runs, which need the same launches in every pass)")
+    ap.add_argument("--no-one-by-one", action="store_true",
+                    help="batched: skip the one-problem-at-a-time comparison solves (for counter runs)")
     ap.add_argument("--requests", type=int, default=400, help="served: measured requests")
     ap.add_argument("--served-dtau", choices=["exp", "poly"], default="exp",
                     help="served: the optimal dtau form (exponential, Remark exptheta2D; or polynomial, Prop. opt3D)")
@@ -112,6 +117,18 @@ def parse():
                     help="before the workload, copy a device buffer of this size once (a plain copy kernel of "
                          "known size, for scaling hardware traffic counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """One device-to-device copy of mib MiB before the workload: a plain copy
+    kernel of known size, against which the traffic counters are scaled."""
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def rho_last(hist):
@@ -131,6 +148,8 @@ def main():
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding the grid "
                                    "across GPUs is not implemented)"}))
         sys.exit(2)
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "rho_sweep":
@@ -214,13 +233,6 @@ def bench_probe(args):
     from paper_2207_14208_amd.solver import Problem
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
-    if args.copy_probe_mib > 0:
-        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     N = args.N or 512
     phi = -torch.ones((N + 1) ** 3, dtype=torch.float64, device="cuda")
     reps = 100
@@ -269,13 +281,6 @@ def bench_flower(args):
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     dev = "cuda"
-    if args.copy_probe_mib > 0:
-        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     big = args.workload == "flower513"
     N = args.N or (512 if big else 256)
     names = ["fp64", "mixed"] if big else [args.precision]
@@ -583,7 +588,11 @@ def bench_batched(args):
 
     t0 = time.perf_counter()
     sample = [W.star_case(i, *p) for i, p in enumerate(W.star_params(24, seed=1))]
-    tuned = autotune.tune(sample, NAT.MIXED, cycles=4, use_cache=False)
+    if args.tuned:
+        seg, cn, cps = (int(v) for v in args.tuned.split(","))
+        tuned = {"seg_len": seg, "coarse_nodes": cn, "cycles_per_step": cps}
+    else:
+        tuned = autotune.tune(sample, NAT.MIXED, cycles=4, use_cache=False)
     tune_s = time.perf_counter() - t0
     params = W.star_params(args.problems, seed=2207)
     cases = [W.star_case(i, *p) for i, p in enumerate(params)]
@@ -608,8 +617,8 @@ def bench_batched(args):
     # the single-problem solver, one problem after another (same problems,
     # same tolerance), in FP64 and in mixed precision: the first comparison
     # is batching and precision together, the second batching alone
-    one_by_one = {}
-    for pname, prec in (("fp64", NAT.FP64), ("mixed", NAT.MIXED)):
+    one_by_one = {"fp64": (float("nan"), [0]), "mixed": (float("nan"), [0])}
+    for pname, prec in () if args.no_one_by_one else (("fp64", NAT.FP64), ("mixed", NAT.MIXED)):
         el1, cyc1 = 0.0, []
         for c in cases:
             G, u, _ = make_problem(c, BatchConfig(seg_len=128, precision=prec, max_cycles=args.max_cycles))

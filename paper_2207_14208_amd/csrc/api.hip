@@ -12,6 +12,8 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "bcmg_internal.h"
 #include "launch.h"
 #include "mem.h"
@@ -211,6 +213,23 @@ struct PhaseTimer {
     }
 };
 thread_local PhaseTimer *t_phase = nullptr;
+
+// roctx range over a host-side phase (setup, its levels, solves, batch
+// steps, the cycles between two host checks); seen by rocprofv3
+// --marker-trace, free without a profiler attached
+struct TraceRange {
+    explicit TraceRange(const char *fmt, ...) __attribute__((format(printf, 2, 3))) {
+        char msg[96];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(msg, sizeof msg, fmt, ap);
+        va_end(ap);
+        roctxRangePushA(msg);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 #define PHASE(what, level) \
     do {                   \
         if (t_phase) t_phase->mark(what, level); \
@@ -471,6 +490,7 @@ bcmg_status build_restrict_rows(bcmg_problem *P, int l, int *h_total) {
 bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratch_offsets, int *total_dev,
                         int *h_total) {
     LevelH &V = P->lev[l];
+    const TraceRange tr("bcmg_setup level %d (N=%d)", l, V.N);
     const int d = P->d;
     hipStream_t s = P->stream;
     bcmg_status st;
@@ -782,6 +802,7 @@ bcmg_status bcmg_setup(int32_t dim, int32_t N, const double *phi_dev, const bcmg
         bcmg_default_options(&o);
     bcmg_status st = check_options(dim, N, &o);
     if (st) return st;
+    const TraceRange tr("bcmg_setup %dD N=%d", dim, N);
     bcmg_problem *P = new bcmg_problem();
     P->d = dim;
     P->N = N;
@@ -1847,6 +1868,7 @@ static void drain_timing(bcmg_batch *b) {
 
 bcmg_status bcmg_batch_step(bcmg_batch *b, int32_t cycles, int32_t *active_host) {
     if (!b || cycles < 1) return fail(BCMG_ERR_INVALID, "bad argument");
+    const TraceRange tr("bcmg_batch_step %d cycles", cycles);
     bcmg_status st = batch_join(b);
     if (st) return st;
     st = batch_launch_cycles(b, cycles);
@@ -1928,6 +1950,7 @@ static bcmg_status solo_attach(bcmg_problem *P, double *u, double rtol) {
 bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats *stats, double *hist) {
     if (!P || !u) return fail(BCMG_ERR_INVALID, "null argument");
     if (!(rtol >= 0.0)) return fail(BCMG_ERR_INVALID, "bad tolerance");
+    const TraceRange tr("bcmg_solve");
     bcmg_status st = solo_attach(P, u, rtol);
     if (st) return st;
     bcmg_batch *b = P->solo;
@@ -1957,6 +1980,7 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     int k = 1, tail = 1, checked_cycles = 0;
     double checked_sq = -1.0;
     while (b->h_state[0].active) {
+        const TraceRange trk("cycles %d..%d", b->h_state[0].cycles + 1, b->h_state[0].cycles + k);
         int left = k;
         while (left > tail && J > 1) {
             const int j = std::min(J, left - tail);

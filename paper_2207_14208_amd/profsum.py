@@ -5,6 +5,9 @@
     python -m paper_2207_14208_amd.profsum traffic <fetch_dir> <write_dir> --kernel NAME --grid G --copy-bytes B
         FETCH_SIZE / WRITE_SIZE per dispatch of one kernel, scaled by what the
         same counters read for the plain copy kernel of B bytes
+    python -m paper_2207_14208_amd.profsum markers <dir>
+        the library's roctx ranges (rocprofv3 --marker-trace): per range name,
+        calls, host time, and the kernel time that fell inside the ranges
 
 Runs on the host; reads only the files rocprofv3 wrote.
 """
@@ -111,6 +114,45 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, grid: int, copy_bytes: 
             "bytes_per_launch": (f_k * fs + w_k * ws) * 1024.0}
 
 
+def _range_key(name: str) -> str:
+    # ranges that carry counts (levels, cycle spans) are grouped by their
+    # leading words
+    if name.startswith("cycles "):
+        return "cycles a..b (one host check)"
+    if name.startswith("bcmg_batch_step"):
+        return "bcmg_batch_step"
+    return name
+
+
+def marker_table(d: str):
+    """(range, calls, host ms, kernel ms inside) for the roctx ranges."""
+    ranges = []
+    for path in _find(d, "*marker_api_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                ranges.append((r["Function"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    kernels = []
+    for path in _find(d, "*kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                kernels.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    kernels.sort()
+    starts = [k[0] for k in kernels]
+    import bisect
+    agg = collections.OrderedDict()
+    for name, t0, t1 in sorted(ranges, key=lambda x: x[1]):
+        k = _range_key(name)
+        a = agg.setdefault(k, [0, 0, 0])
+        a[0] += 1
+        a[1] += t1 - t0
+        i = bisect.bisect_left(starts, t0)
+        while i < len(kernels) and kernels[i][0] < t1:
+            if kernels[i][1] <= t1:
+                a[2] += kernels[i][1] - kernels[i][0]
+            i += 1
+    return [(k, v[0], v[1] / 1e6, v[2] / 1e6) for k, v in agg.items()]
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -123,7 +165,14 @@ def main():
     c.add_argument("--kernel", required=True)
     c.add_argument("--grid", type=int, default=0, help="grid size in threads (0: the kernel's largest)")
     c.add_argument("--copy-bytes", type=int, required=True)
+    m = sub.add_parser("markers")
+    m.add_argument("dir")
     a = ap.parse_args()
+    if a.cmd == "markers":
+        print("| range | calls | host ms | kernel ms inside |\n|---|---:|---:|---:|")
+        for k, n, host, kern in marker_table(a.dir):
+            print(f"| {k} | {n} | {host:.3f} | {kern:.3f} |")
+        return
     if a.cmd == "trace":
         rows, tot_ms = trace_table(a.dir, a.top)
         print(f"total kernel time {tot_ms:.3f} ms\n")

@@ -25,6 +25,7 @@ def test_host_code_clean_under_asan_and_ubsan(tmp_path):
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(HERE, "host_sanitize_driver.cpp"),
            *[os.path.join(CSRC, f) for f in ("api.hip", "mem.hip", "cycle.hip", "setup.hip")],
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
            "-o", str(exe)]
     subprocess.run(cmd, check=True, capture_output=True, timeout=900)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")

@@ -81,3 +81,26 @@ def test_copy_probe_is_the_first_large_copy(tmp_path):
     t = profsum.traffic(str(fd), str(wd), "k_rb_sweep<3, float>", 0, 1 << 20)
     assert t["copy_fetch_kib"] == 512.0 and t["copy_write_kib"] == 1024.0
     assert t["bytes_per_launch"] == pytest.approx(230.0 * 1024)
+
+
+def test_marker_ranges_group_and_count_kernel_time_inside(tmp_path):
+    # two host checks of a solve and a setup range; kernels count toward a
+    # range only when they start and end inside it
+    _write(tmp_path / "m_marker_api_trace.csv",
+           ["Domain", "Function", "Process_Id", "Thread_Id", "Correlation_Id", "Start_Timestamp", "End_Timestamp"], [
+               ["MARKER_CORE_RANGE_API", "bcmg_setup 3D N=8", 1, 1, 1, 0, 1_000_000],
+               ["MARKER_CORE_RANGE_API", "bcmg_solve", 1, 1, 2, 2_000_000, 9_000_000],
+               ["MARKER_CORE_RANGE_API", "cycles 1..1", 1, 1, 3, 2_100_000, 3_000_000],
+               ["MARKER_CORE_RANGE_API", "cycles 2..9", 1, 1, 4, 3_000_000, 8_900_000],
+           ])
+    _write(tmp_path / "m_kernel_trace.csv", ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"], [
+        ["k_classify_a", 64, 100_000, 300_000],
+        ["k_rb_sweep<3, double>", 64, 2_200_000, 2_700_000],
+        ["k_rb_sweep<3, double>", 64, 3_500_000, 4_500_000],
+        ["k_rb_sweep<3, double>", 64, 8_800_000, 9_500_000],  # ends after both ranges
+    ])
+    rows = {k: (n, host, kern) for k, n, host, kern in profsum.marker_table(str(tmp_path))}
+    assert rows["bcmg_setup 3D N=8"] == (1, 1.0, 0.2)
+    assert rows["bcmg_solve"] == (1, 7.0, 1.5)
+    n, host, kern = rows["cycles a..b (one host check)"]
+    assert n == 2 and abs(host - 6.8) < 1e-12 and abs(kern - 1.5) < 1e-12
