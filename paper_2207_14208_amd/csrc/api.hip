@@ -548,10 +548,10 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
         long long rows = 1;
         for (int k = 1; k < d; k++) rows *= V.n;
         int *ext = nullptr;
-        HIPCHK(tmp.get(&ext, sizeof(int) * 2 * rows));
-        launch_row_extent(d, V.n, V.cls, ext, ext + rows, s);
-        std::vector<int> h(2 * rows);
-        HIPCHK(hipMemcpyAsync(h.data(), ext, sizeof(int) * 2 * rows, hipMemcpyDeviceToHost, s));
+        HIPCHK(tmp.get(&ext, sizeof(int) * 4 * rows));
+        launch_row_extent(d, V.n, V.cls, ext, ext + rows, ext + 2 * rows, ext + 3 * rows, s);
+        std::vector<int> h(4 * rows);
+        HIPCHK(hipMemcpyAsync(h.data(), ext, sizeof(int) * 4 * rows, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         V.segs.clear();
         for (long long r = 0; r < rows; r++) {
@@ -559,9 +559,12 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
             if (lo < 0) continue;
             const int j = d >= 2 ? (int)(r % V.n) : 0;
             const int k = d >= 3 ? (int)(r / V.n) : 0;
+            const int ia = h[2 * rows + r], ib = h[3 * rows + r];
             for (int x = lo; x <= hi; x += P->opt.seg_len) {
                 const int len = std::min(P->opt.seg_len, hi - x + 1);
-                V.segs.push_back(seg_item(0, r * V.n + x, x, len, j, k));
+                Item it = seg_item(0, r * V.n + x, x, len, j, k);
+                if (ib >= 0 && ia <= x && x + len - 1 <= ib) it.z |= kSegAllInside;
+                V.segs.push_back(it);
             }
         }
     }

@@ -50,9 +50,11 @@ constexpr long long kListNodes = 1 << 15;
 // in HBM); gfx950 gives a workgroup up to 160 KiB
 constexpr size_t kLdsBudget = 150 * 1024;
 
-// Work item over a row segment: desc, first node, x0 | len << 16, j | k << 16.
+// Work item over a row segment: desc, first node, x0 | len << 16 (| kSegAllInside), j | k << 16.
 // Ghost / band chunk: desc, first entry, count, unused.
 using Item = int4;
+// flag of a segment item whose nodes are all INSIDE (the sweep then needs no classes)
+constexpr int kSegAllInside = 1 << 24;
 
 struct alignas(16) Desc {
     int d, n, N, level;

@@ -80,7 +80,9 @@ hipError_t launch_scan(const int *counts, int n, int *ptr, hipStream_t s);
 void launch_need_mark(int d, int Nf, const uint8_t *cls_f, const uint8_t *cls_c, uint8_t *mark_c, long long nnf,
                       hipStream_t s);
 void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *flag, hipStream_t s);
-void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s);
+// per row: INSIDE/GHOST extent [xmin, xmax], and the INSIDE run [ia, ib] (ib = -1 unless the row's
+// INSIDE nodes are consecutive)
+void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, int *ia, int *ib, hipStream_t s);
 void launch_coarse_setup(int d, int N, double h, const uint8_t *cls, const int *gidx, int ng, const int *gcode,
                          const double *gtau, int bc, const double *gnd, double reaction, double *work, double *ainv,
                          int *cmap, int *info, hipStream_t s);

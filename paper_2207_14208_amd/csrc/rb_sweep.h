@@ -19,7 +19,8 @@ __device__ __forceinline__ void seg_rb(const Desc &L, const Item &it, int lane, 
     const NodeArr<T> u = node_u<T>(L);
     const NodeArr<const T> f = node_rhs<const T>(L);
     const long long nn = L.nn;
-    const int c = ((gcp<uint8_t>)L.cls)[p];
+    int c = C_INSIDE;  // segments of INSIDE nodes only skip the class load
+    if (!s.all_inside) c = ((gcp<uint8_t>)L.cls)[p];
     const T fp = f[p];
     const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
     T ym = 0, yp = 0, zm = 0, zp = 0;
@@ -75,7 +76,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep_multi(const Desc *__restric
         const NodeArr<T> u = node_u<T>(L);
         const NodeArr<const T> f = node_rhs<const T>(L);
         const long long nn = L.nn;
-        cw[j] = ((gcp<uint8_t>)L.cls)[p];
+        cw[j] = C_INSIDE;
+        if (!sg.all_inside) cw[j] = ((gcp<uint8_t>)L.cls)[p];
         const T fp = f[p];
         const T xm = u[clampi(p - 1, nn)], xp = u[clampi(p + 1, nn)];
         T ym = 0, yp = 0, zm = 0, zp = 0;

@@ -49,13 +49,15 @@ __device__ __forceinline__ int seg_lane_node(int lane, int h, long long half) {
 struct Seg {
     long long p0;  // first node
     int len, x0, yj, zk;
+    bool all_inside;  // every node of the segment is INSIDE
 };
 
 __device__ __forceinline__ Seg seg_of(const Item &it) {
     Seg s;
     s.p0 = it.y;
-    s.len = it.z >> 16;
+    s.len = (it.z >> 16) & 0xff;
     s.x0 = it.z & 0xffff;
+    s.all_inside = (it.z & kSegAllInside) != 0;
     s.yj = it.w & 0xffff;
     s.zk = it.w >> 16;
     return s;

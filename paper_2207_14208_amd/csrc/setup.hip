@@ -969,27 +969,38 @@ void launch_need_flags(const int *bidx, int nb, const uint8_t *mark, uint8_t *fl
 }
 
 // x-extent of the INSIDE/GHOST nodes of each grid row (-1 if none).
-__global__ void k_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, long long rows) {
+// Per row: first and last INSIDE or GHOST node (-1 if none), and the first
+// and last INSIDE node when the row's INSIDE nodes are consecutive (ib = -1
+// if they are not, or there are none).
+__global__ void k_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, int *ia, int *ib,
+                             long long rows) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     const uint8_t *row = cls + r * n;
-    int lo = -1, hi = -1;
+    int lo = -1, hi = -1, ilo = -1, ihi = -1, icount = 0;
     for (int x = 0; x < n; x++) {
         const uint8_t c = row[x];
         if (c == C_INSIDE || c == C_GHOST) {
             if (lo < 0) lo = x;
             hi = x;
         }
+        if (c == C_INSIDE) {
+            if (ilo < 0) ilo = x;
+            ihi = x;
+            icount++;
+        }
     }
     xmin[r] = lo;
     xmax[r] = hi;
+    ia[r] = ilo;
+    ib[r] = icount > 0 && icount == ihi - ilo + 1 ? ihi : -1;
 }
 
-void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, hipStream_t s) {
+void launch_row_extent(int d, int n, const uint8_t *cls, int *xmin, int *xmax, int *ia, int *ib, hipStream_t s) {
     long long rows = 1;
     for (int k = 1; k < d; k++) rows *= n;
-    hipLaunchKernelGGL(k_row_extent, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, s, d, n, cls, xmin, xmax,
-                       rows);
+    hipLaunchKernelGGL(k_row_extent, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, s, d, n, cls, xmin, xmax, ia,
+                       ib, rows);
 }
 
 // ----------------------------------------------------- coarsest-level inverse
