@@ -260,7 +260,7 @@ def bench_probe(args):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic (phi = -1 on the whole box)",
            "config": {"workload": f"roofline probe: red-black sweep of the full {N + 1}^3 box, FP32 split layout "
                                   f"(FP32 natural and FP64 beside it)", "nodes_per_axis": N + 1},
-           "roofline": {"bound": "hbm", "kernel": "k_rb_sweep_multi<3, float, 2> (split layout, one colour)",
+           "roofline": {"bound": "hbm", "kernel": "k_rb_sweep_split4<3> (split layout, one colour)",
                         "achieved": best["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": best["frac"], "traffic": None, "avg_launch_us": best["avg_launch_us"],
                         "alg_bytes_per_launch": best["alg_bytes_per_launch"]},

@@ -595,13 +595,16 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     // level arrays (cycle precision); the finest FP64 level uses caller memory for u
     const size_t esz = P->fp32 ? 4 : 8;
     if (l == 0 && P->fp32 && P->opt.layout == BCMG_LAYOUT_SPLIT && V.nn > kSplitMinNodes) V.half = (V.nn + 1) / 2;
+    // split arrays end in kSplitPad spare entries (the vector loads of the
+    // split sweep may read a few entries past the last node)
+    const long long alloc_nn = V.nn + (V.half ? kSplitPad : 0);
     if (l > 0 || P->fp32) {
-        if ((st = dalloc(P, &V.u, V.nn * esz))) return st;
+        if ((st = dalloc(P, &V.u, alloc_nn * esz))) return st;
     }
     if (l > 0 || P->fp32) {
-        if ((st = dalloc(P, &V.rhs, V.nn * esz))) return st;
+        if ((st = dalloc(P, &V.rhs, alloc_nn * esz))) return st;
     }
-    if ((st = dalloc(P, &V.r, V.nn * esz))) return st;
+    if ((st = dalloc(P, &V.r, alloc_nn * esz))) return st;
     return BCMG_OK;
 }
 

@@ -43,6 +43,8 @@ constexpr int kMaxCheckInterval = 8;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than
 // this are stored split by node parity under BCMG_LAYOUT_SPLIT
 constexpr long long kSplitMinNodes = 1 << 17;
+// spare entries at the end of a split array
+constexpr long long kSplitPad = 16;
 // levels with at most this many nodes keep a colour-sorted list of their
 // INSIDE nodes (used when they are cycled in LDS)
 constexpr long long kListNodes = 1 << 15;

@@ -1467,20 +1467,14 @@ static inline int blocks_for_segs(int nseg) { return (nseg + kWavesPerBlock - 1)
             DISPATCH_DB(d, KERNEL, T, false, __VA_ARGS__);                     \
     } while (0)
 
-#define DISPATCH_DS(d, KERNEL, T, S, ...)                                      \
-    do {                                                                       \
-        if ((d) == 1) hipLaunchKernelGGL((KERNEL<1, T, S>), __VA_ARGS__);      \
-        if ((d) == 2) hipLaunchKernelGGL((KERNEL<2, T, S>), __VA_ARGS__);      \
-        if ((d) == 3) hipLaunchKernelGGL((KERNEL<3, T, S>), __VA_ARGS__);      \
-    } while (0)
-
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s, int pair_min) {
     if (nseg <= 0) return;
     dim3 b(kBlock);
-    if (fp32 && nseg >= pair_min) {  // two segments per wavefront
-        dim3 g(blocks_for_segs((nseg + 1) / 2));
-        DISPATCH_DS(d, k_rb_sweep_multi, float, 2, g, b, 0, s, descs, items, nseg, colour, st);
+    if (fp32 && nseg >= pair_min && d >= 2) {  // split levels: four segments per wavefront
+        dim3 g(blocks_for_segs((nseg + 3) / 4));
+        if (d == 2) hipLaunchKernelGGL((k_rb_sweep_split4<2>), g, b, 0, s, descs, items, nseg, colour, st);
+        if (d == 3) hipLaunchKernelGGL((k_rb_sweep_split4<3>), g, b, 0, s, descs, items, nseg, colour, st);
         return;
     }
     dim3 g(blocks_for_segs(nseg));
