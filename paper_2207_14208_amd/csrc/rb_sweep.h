@@ -116,6 +116,11 @@ __device__ __forceinline__ void split4_lane(const Desc &L, const Item &it, int t
     }
     if (!live) return;
     gp<float> Uw = (gp<float>)L.u;
+    if (nv == 4 && c[0] == C_INSIDE && c[1] == C_INSIDE && c[2] == C_INSIDE && c[3] == C_INSIDE) {
+        const f32x4u w4 = {v[0], v[1], v[2], v[3]};
+        *(gp<f32x4u>)(Uw + bc) = w4;
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++)
         if (k < nv && c[k] == C_INSIDE) Uw[bc + k] = v[k];
