@@ -406,7 +406,8 @@ def bench_flower(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_rb_sweep<3, {'double' if head == 'fp64' else 'float'}> (finest level, one colour)",
+            "kernel": ("k_rb_sweep<3, double> (finest level, one colour)" if head == "fp64" else
+                       "k_rb_sweep_split4<3> (finest level, split storage order, one colour)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

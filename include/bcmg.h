@@ -116,14 +116,12 @@ typedef struct {
 #define BCMG_SMOOTH_JACOBI 1
 
 /* Storage order of the finest level's FP32 arrays of a mixed-precision
- * problem (the caller's arrays are always x fastest).  NATURAL (default):
- * x fastest everywhere.  SPLIT: when the finest level has more than 131072
- * nodes, the nodes of even index are stored before those of odd index; with
- * N + 1 odd these are the two colours of the red-black sweep, so each colour
- * pass reads and writes contiguous halves.  The arithmetic is the same, so
- * both give the same bits.  SPLIT halves the sweep's traffic on large dense
- * grids, but on the flower domains the other finest-level kernels lose what
- * the sweep gains, so it is not the default. */
+ * problem (the caller's arrays are always x fastest).  SPLIT (default): when
+ * the finest level has more than 131072 nodes, the nodes of even index are
+ * stored before those of odd index; with N + 1 odd these are the two colours
+ * of the red-black sweep, so each colour pass reads and writes contiguous
+ * halves, with 16-byte loads and stores.  NATURAL: x fastest everywhere.  The
+ * arithmetic is the same, so both give the same bits. */
 #define BCMG_LAYOUT_NATURAL 0
 #define BCMG_LAYOUT_SPLIT 1
 
@@ -378,8 +376,9 @@ bcmg_status bcmg_estimate_bytes(int32_t dim, int32_t N, int32_t precision, int64
 #define BCMG_PARAM_LDS_BYTES 2    /* LDS bytes that workgroup may hold its levels in (default and maximum 153600;
                                      0 keeps them in HBM) */
 #define BCMG_PARAM_SWEEP_PAIR_SEGS 3 /* FP32 red-black launches over split-layout levels (BCMG_LAYOUT_SPLIT) with
-                                        at least this many row segments give each wavefront two segments (default
-                                        32768); the results are the same bits */
+                                        at least this many row segments give each wavefront four segments and
+                                        each lane four nodes of a colour (default 1: all of them; a larger value
+                                        keeps smaller levels on one segment per wavefront); the same bits */
 
 bcmg_status bcmg_batch_set_param(bcmg_batch *b, int32_t param, int64_t value);
 

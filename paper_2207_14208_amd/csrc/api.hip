@@ -171,7 +171,7 @@ struct bcmg_batch {
     int nfseg = 0, nfgch = 0;
     int Ac = 0;                    // aligned levels 0..Ac run in the per-problem coarse workgroup
     long long coarse_nodes = kCoarseNodes;
-    int pair_segs = kSweepPairSegs;  // FP32 sweeps over this many segments pair them per wavefront
+    int pair_segs = kSweepPairSegs;  // FP32 sweeps of split levels over this many segments take four per wavefront
     CoarseProg *d_progs = nullptr;
     int nprog = 0;
     LdsProg *d_lprogs = nullptr;   // the same programs with their levels staged in LDS
@@ -739,7 +739,7 @@ bcmg_status bcmg_default_options(bcmg_options *o) {
     o->seg_len = kSegLen;
     o->bc = BCMG_BC_DIRICHLET;
     o->reaction = 0.0;
-    o->layout = BCMG_LAYOUT_NATURAL;
+    o->layout = BCMG_LAYOUT_SPLIT;
     o->cycle = BCMG_CYCLE_V;
     o->smoother = BCMG_SMOOTH_RB;
     o->check_interval = 1;

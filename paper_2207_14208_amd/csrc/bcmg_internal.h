@@ -35,9 +35,9 @@ constexpr int kRefFallback = INT32_MIN + 1; // band node with zero weight sum
 constexpr int kCoarseMax = 125;           // unknowns of the coarsest level (5^3)
 // levels with at most this many nodes are cycled by one workgroup per problem
 constexpr long long kCoarseNodes = 5000;
-// FP32 red-black launches over at least this many row segments give each
-// wavefront two of them (BCMG_PARAM_SWEEP_PAIR_SEGS)
-constexpr int kSweepPairSegs = 32768;
+// FP32 red-black launches over split levels with at least this many row
+// segments take four of them per wavefront (BCMG_PARAM_SWEEP_PAIR_SEGS)
+constexpr int kSweepPairSegs = 1;
 // largest check_interval (cycles per convergence check of bcmg_solve)
 constexpr int kMaxCheckInterval = 8;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than

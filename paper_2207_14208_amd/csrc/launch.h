@@ -6,8 +6,8 @@
 namespace bcmg {
 
 // ---- cycle kernels (cycle.hip); fp32 selects the element type of u/rhs/r ----
-// FP32 launches with at least pair_min segments take two segments per wavefront (callers pass
-// kSweepPairSegs for split-layout levels, INT32_MAX elsewhere)
+// FP32 launches over 2D/3D split levels with at least pair_min segments take four segments per
+// wavefront and four nodes per lane (callers pass their threshold for split levels, INT32_MAX elsewhere)
 void launch_rb_sweep(int d, int fp32, const Desc *descs, const Item *items, int nseg, int colour,
                      const SlotState *st, hipStream_t s, int pair_min = INT32_MAX);
 // weighted Jacobi on the INSIDE rows: new values into r from the old field,

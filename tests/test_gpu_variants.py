@@ -205,9 +205,9 @@ def test_split_layout_same_bits_as_natural(name):
 
 
 def test_paired_segment_sweep_same_bits():
-    """FP32 sweeps with two row segments per wavefront (forced on every
-    launched level here; by default only launches over 32768 segments take
-    it) give the same bits as one segment per wavefront."""
+    """FP32 sweeps of a split level with four row segments per wavefront
+    and four nodes per lane (the default) give the same bits as one segment
+    per wavefront (forced by a threshold above the level's segment count)."""
     _need_gpu()
     from paper_2207_14208_amd import _native as N
     from paper_2207_14208_amd.solver import Batch
