@@ -290,3 +290,36 @@ def test_coarse_workgroup_in_hbm_over_a_large_level():
     assert np.abs(uo - u.cpu().numpy()).max() <= 1e-12 * np.abs(uo).max()
     B.close()
     G.close()
+
+
+@pytest.mark.parametrize("d,N", [(3, 64), (2, 512)])
+def test_split_sweep_with_ghosts_on_a_box_face(d, N):
+    """The domain y > -1 + h/2: the whole face y = -1 is a row of ghosts next
+    to INSIDE nodes, so segments of the split sweep lie on the box face and
+    their lanes' neighbour reads start below the array (clamped, and never
+    used).  Split and natural storage give the same bits, and the mixed
+    solve meets the FP64 residual tolerance by the oracle's residual."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N_
+    h = 2.0 / N
+    sol = W.Manufactured(u=(lambda x, y: np.sin(x) * np.cos(y)) if d == 2 else (lambda x, y, z: np.exp(x + y + z)),
+                         f=(lambda x, y: 2 * np.sin(x) * np.cos(y)) if d == 2 else (lambda x, y, z: -3 * np.exp(x + y + z)))
+    c = W.make_case("face", d, N, lambda *xs: (-1.0 + 0.5 * h) - xs[1], sol)
+    O = oracle.Problem(c.d, c.N, c.phi)
+    cls = O.classes(0)
+    face_ghosts = int(np.count_nonzero(cls.reshape((N + 1,) * d)[(slice(None),) * (d - 2) + (0,)] == oracle.GHOST))
+    assert face_ghosts > 0
+    out = []
+    for layout in (N_.LAYOUT_SPLIT, N_.LAYOUT_NATURAL):
+        G = gpu_problem(c, precision=N_.MIXED, layout=layout)
+        u = G.initial_guess(torch.from_numpy(c.gB).cuda())
+        st, hist = G.solve(u, 1e-10)
+        assert st.status == 0, st
+        out.append((st.cycles, hist, u.cpu().numpy()))
+        G.close()
+    (c1, h1, u1), (c2, h2, u2) = out
+    assert c1 == c2 and np.array_equal(h1, h2) and np.array_equal(u1, u2)
+    O.set_rhs(c.f, W.points_eval(c.g, O.ghosts(0)["q"], c.d))
+    u0 = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
+    r0 = O.norm(0, O.residual(0, u0))
+    assert O.norm(0, O.residual(0, u1)) <= 1e-10 * r0 * 1.001
