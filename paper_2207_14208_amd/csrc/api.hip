@@ -1591,7 +1591,8 @@ static void launch_vcycle(bcmg_batch *b) {
         const Lists &L = b->lv[a];
         if (L.nseg == 0 && L.ngch == 0) continue;
         for (int i = 0; i < b->nu1; i++) smooth(b, a, nullptr, 0, i == 0);
-        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu);
+        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu, 1,
+                        L.split ? 1 : 0);
         // a coarse level cycled by launches gets its first red half-sweep here
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
                         !b->jacobi && b->nu1 > 0 && a - 1 > b->Ac);
@@ -1628,7 +1629,8 @@ static void wcycle_level(bcmg_batch *b, int a, bool restricted) {
     const bool work = L.nseg > 0 || L.ngch > 0;
     if (work) {
         for (int i = 0; i < b->nu1; i++) smooth(b, a, nullptr, 0, restricted && i == 0);
-        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu);
+        launch_residual(d, f, f, 0, b->d_desc, L.segs, L.nseg, L.gch, L.ngch, b->d_state, nullptr, s, b->neu, 1,
+                        L.split ? 1 : 0);
         launch_restrict(d, f, b->d_desc, L.csegs, L.ncseg, L.cgch, L.ncgch, b->d_state, s,
                         !b->jacobi && b->nu1 > 0 && a - 1 > b->Ac);
     }

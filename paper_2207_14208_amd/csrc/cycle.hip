@@ -786,6 +786,153 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     }
 }
 
+// Residual of the INSIDE rows of a level stored split by node parity (FP32),
+// four row segments per wavefront, sixteen lanes per segment and eight
+// consecutive nodes per lane: four of each parity, a and b, whose values,
+// x neighbours and f are consecutive in their halves (a: entries ia ..
+// ia + 3, b: ib .. ib + 3), x neighbours included: node a_k sits between b
+// entries k - 1 and k, node b_k between a entries k and k + 1.  16-byte loads
+// and stores; the arithmetic is seg_residual's, node by node (the same
+// result).  The rows of the ghost chunks follow as in k_residual.
+template <int D>
+__device__ __forceinline__ void split_residual_lane(const Desc &L, const Item &it, int t, bool live) {
+    const Seg s = seg_of(it);
+    const int q0 = 8 * t;
+    const int nv = min(max(s.len - q0, 0), 8);
+    const long long pa = s.p0 + (nv > 0 ? q0 : 0), pb = pa + 1;
+    const long long half = L.half_u;
+    auto at = [&](long long p, long long h) { return (p >> 1) + ((p & 1) ? h : 0LL); };
+    const long long lim = L.nn + kSplitPad - 5;
+    auto base = [&](long long b) { return b < 0 ? 0LL : (b > lim ? lim : b); };
+    gcp<float> U = (gcp<float>)L.u;
+    gcp<float> F = (gcp<float>)L.rhs;
+    const long long ia = at(pa, half), ib = at(pb, half);
+    const f32x4u a4 = *(gcp<f32x4u>)(U + base(ia));
+    const float a5 = U[base(ia) + 4];
+    const float b0 = U[base(ib - 1)];
+    const f32x4u b4 = *(gcp<f32x4u>)(U + base(ib));
+    const f32x4u fa = *(gcp<f32x4u>)(F + base(ia));
+    const f32x4u fb = *(gcp<f32x4u>)(F + base(ib));
+    f32x4u yam = {0, 0, 0, 0}, yap = {0, 0, 0, 0}, ybm = {0, 0, 0, 0}, ybp = {0, 0, 0, 0};
+    f32x4u zam = {0, 0, 0, 0}, zap = {0, 0, 0, 0}, zbm = {0, 0, 0, 0}, zbp = {0, 0, 0, 0};
+    if (D >= 2) {
+        yam = *(gcp<f32x4u>)(U + base(at(pa - L.sy, half)));
+        yap = *(gcp<f32x4u>)(U + base(at(pa + L.sy, half)));
+        ybm = *(gcp<f32x4u>)(U + base(at(pb - L.sy, half)));
+        ybp = *(gcp<f32x4u>)(U + base(at(pb + L.sy, half)));
+    }
+    if (D >= 3) {
+        zam = *(gcp<f32x4u>)(U + base(at(pa - L.sz, half)));
+        zap = *(gcp<f32x4u>)(U + base(at(pa + L.sz, half)));
+        zbm = *(gcp<f32x4u>)(U + base(at(pb - L.sz, half)));
+        zbp = *(gcp<f32x4u>)(U + base(at(pb + L.sz, half)));
+    }
+    int c[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) c[j] = C_INSIDE;
+    if (!s.all_inside) {
+        gcp<uint8_t> cls = (gcp<uint8_t>)L.cls;
+#pragma unroll
+        for (int j = 0; j < 8; j++) c[j] = cls[pa + (j < nv ? j : 0)];
+    }
+    const float A[5] = {a4.x, a4.y, a4.z, a4.w, a5};
+    const float B[5] = {b0, b4.x, b4.y, b4.z, b4.w};  // b entries ib - 1 .. ib + 3
+    const float FA[4] = {fa.x, fa.y, fa.z, fa.w}, FB[4] = {fb.x, fb.y, fb.z, fb.w};
+    const float YAM[4] = {yam.x, yam.y, yam.z, yam.w}, YAP[4] = {yap.x, yap.y, yap.z, yap.w};
+    const float YBM[4] = {ybm.x, ybm.y, ybm.z, ybm.w}, YBP[4] = {ybp.x, ybp.y, ybp.z, ybp.w};
+    const float ZAM[4] = {zam.x, zam.y, zam.z, zam.w}, ZAP[4] = {zap.x, zap.y, zap.z, zap.w};
+    const float ZBM[4] = {zbm.x, zbm.y, zbm.z, zbm.w}, ZBP[4] = {zbp.x, zbp.y, zbp.z, zbp.w};
+    float ra[4], rb[4];
+    auto row = [&](double up, double fp, double xm, double xp, double ym, double yp, double zm, double zp) {
+        double sum = xp + xm;
+        if (D >= 2) sum += yp + ym;
+        if (D >= 3) sum += zp + zm;
+        double lap = (2.0 * D * up - sum) / L.h2;
+        if (L.reaction != 0.0) lap += L.reaction * up;  // c u - Laplace u
+        return fp - lap;
+    };
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        ra[k] = (float)row((double)A[k], (double)FA[k], (double)B[k], (double)B[k + 1], (double)YAM[k],
+                           (double)YAP[k], (double)ZAM[k], (double)ZAP[k]);
+        rb[k] = (float)row((double)B[k + 1], (double)FB[k], (double)A[k], (double)A[k + 1], (double)YBM[k],
+                           (double)YBP[k], (double)ZBM[k], (double)ZBP[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        pin(ra[k]);
+        pin(rb[k]);
+    }
+    if (!live || nv <= 0) return;
+    gp<float> R = (gp<float>)L.r;
+    const long long ra0 = at(pa, L.half_r), rb0 = at(pb, L.half_r);
+    // node a_k is segment node q0 + 2k, b_k is q0 + 2k + 1
+    bool fa_all = nv == 8, fb_all = nv == 8;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        fa_all = fa_all && c[2 * k] == C_INSIDE;
+        fb_all = fb_all && c[2 * k + 1] == C_INSIDE;
+    }
+    if (fa_all) {
+        *(gp<f32x4u>)(R + ra0) = f32x4u{ra[0], ra[1], ra[2], ra[3]};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (2 * k < nv && c[2 * k] == C_INSIDE) R[ra0 + k] = ra[k];
+    }
+    if (fb_all) {
+        *(gp<f32x4u>)(R + rb0) = f32x4u{rb[0], rb[1], rb[2], rb[3]};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (2 * k + 1 < nv && c[2 * k + 1] == C_INSIDE) R[rb0 + k] = rb[k];
+    }
+}
+
+template <int D, bool NEU>
+__global__ __launch_bounds__(kBlock) void k_residual_split(const Desc *__restrict__ descs,
+                                                           const Item *__restrict__ items, int nseg,
+                                                           const Item *__restrict__ gch, int nseg_blocks,
+                                                           const SlotState *__restrict__ st) {
+    const int lb = xcd_block_second_first(nseg_blocks);
+    if (lb < nseg_blocks) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int first = __builtin_amdgcn_readfirstlane((lb * kWavesPerBlock + wave) * 4);
+        if (first >= nseg) return;
+        const int g = lane >> 4, t = lane & 15;
+        Item its[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) its[k] = items[min(first + k, nseg - 1)];
+        const int nk = min(nseg - first, 4);
+        bool uniform = true;
+#pragma unroll
+        for (int k = 1; k < 4; k++) uniform = uniform && (k >= nk || its[k].x == its[0].x);
+        if (uniform) {
+            const Desc L = descs[its[0].x];
+            const bool live = st[L.slot].active != 0;
+            Item mine = its[0];
+#pragma unroll
+            for (int k = 1; k < 4; k++)
+                if (g == k) mine = its[k];
+            if (g < nk) split_residual_lane<D>(L, mine, t, live);
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (k >= nk) break;
+            const Desc L = descs[its[k].x];
+            const bool live = st[L.slot].active != 0;
+            if (g == k) split_residual_lane<D>(L, its[k], t, live);
+        }
+        return;
+    }
+    const int cb = lb - nseg_blocks;
+    const Item it = gch[cb];
+    const Desc &L = descs[it.x];
+    const bool live = st[L.slot].active != 0;
+    if ((int)threadIdx.x < it.z) ghost_residual<D, float, float, NEU>(L, it.y + threadIdx.x, live, true);
+}
+
 // Weighted Jacobi on the INSIDE rows (Sec. 2.1: the smoother omega D + (1 -
 // omega) I, with omega = 2d / (2d + 1) in d dimensions, 2/3 in 1D).  Pass 0
 // computes u + omega ((h^2 f + sum of the 2d neighbours) / (2d + c h^2) - u)
@@ -1528,7 +1675,16 @@ static void residual_t(int d, const Desc *descs, const Item *segs, int nseg, con
 
 template <bool NEU>
 static void residual_n(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
-                       const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int store) {
+                       const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int store,
+                       int split) {
+    if (split && tu32 && tr32 && !norm && store && d >= 2) {  // split FP32 level: vector loads and stores
+        const int sb = blocks_for_segs((nseg + 3) / 4);
+        if (sb + ngch <= 0) return;
+        dim3 g(sb + ngch), b(kBlock);
+        if (d == 2) hipLaunchKernelGGL((k_residual_split<2, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st);
+        if (d == 3) hipLaunchKernelGGL((k_residual_split<3, NEU>), g, b, 0, s, descs, segs, nseg, gch, sb, st);
+        return;
+    }
     if (!tu32 && !tr32) {
         if (norm)
             residual_t<double, double, true, NEU>(d, descs, segs, nseg, gch, ngch, st, partials, s, store);
@@ -1546,11 +1702,11 @@ static void residual_n(int d, int tu32, int tr32, int norm, const Desc *descs, c
 
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
                      const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu,
-                     int store) {
+                     int store, int split) {
     if (neu)
-        residual_n<true>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store);
+        residual_n<true>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store, split);
     else
-        residual_n<false>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store);
+        residual_n<false>(d, tu32, tr32, norm, descs, segs, nseg, gch, ngch, st, partials, s, store, split);
 }
 
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,

@@ -21,10 +21,12 @@ void launch_jacobi(int d, int fp32, const Desc *descs, const Item *items, int ns
 void launch_ghost_relax(int d, int fp32, const Desc *descs, const Item *gch, int ngch, const SlotState *st,
                         hipStream_t s, const Item *bch = nullptr, int nbch = 0, int neu = 0);
 // tu32/tr32: element types of (u, rhs) and r; norm: write partial sums of r^2;
-// store 0: skip the stores of r (only the partial sums are wanted)
+// store 0: skip the stores of r (only the partial sums are wanted);
+// split: every descriptor's level is stored split by node parity (an FP32,
+// 2D or 3D level: vector loads and stores)
 void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, const Item *segs, int nseg,
                      const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu = 0,
-                     int store = 1);
+                     int store = 1, int split = 0);
 // mode 1: the check after ncyc cycles (ncyc - 1 of them unchecked)
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s,
