@@ -99,7 +99,7 @@ def parse():
                          "request loop; rho_sweep: convergence factors of the paper's 2D tests, batched; neumann: "
                          "the 257^3 ellipsoid with Neumann rows and the reaction term against Dirichlet Poisson")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64", help="flower257: precision")
-    ap.add_argument("--check-interval", type=int, default=8,
+    ap.add_argument("--check-interval", type=int, default=16,
                     help="flower513, flower257: at most this many cycles per convergence check of the solve "
                          "(bcmg_options.check_interval; 1 checks after every cycle)")
     ap.add_argument("--problems", type=int, default=512, help="batched: number of problems")

@@ -94,7 +94,7 @@ typedef struct {
     int32_t layout;        /* BCMG_LAYOUT_*: storage order of the library's own finest-level arrays */
     int32_t cycle;         /* BCMG_CYCLE_V (default) or BCMG_CYCLE_W */
     int32_t smoother;      /* BCMG_SMOOTH_RB (red-black Gauss-Seidel, default) or BCMG_SMOOTH_JACOBI */
-    int32_t check_interval; /* bcmg_solve: at most this many cycles per convergence check (1..8, default 1:
+    int32_t check_interval; /* bcmg_solve: at most this many cycles per convergence check (1..16, default 1:
                                a check after every cycle); see bcmg_solve */
 } bcmg_options;
 

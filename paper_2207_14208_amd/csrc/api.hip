@@ -1979,7 +1979,7 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
     if ((st = batch_join(b))) return st;
     // The host waits on the device once per k cycles, with k the number of
     // cycles the observed convergence rate still needs (at least 1, at most
-    // 16).  Cycles launched after convergence find the slot inactive and
+    // 16 or twice check_interval).  Cycles launched after convergence find the slot inactive and
     // change nothing.  Those k cycles run in blocks of up to check_interval
     // cycles with a device-side check after each block, as long as at least
     // two predicted cycles remain after the block; the rest are checked one
@@ -2008,7 +2008,7 @@ bcmg_status bcmg_solve(bcmg_problem *P, double *u, double rtol, bcmg_solve_stats
             const double rate = std::log(S.lastsq / checked_sq) / dc;  // log of rho^2 per cycle, < 0
             const double need = std::log(S.tolsq / S.lastsq) / rate;   // cycles still needed
             const double nc = std::min(1e6, std::floor(need));
-            if (need > 1.0) k = (int)std::min(16.0, nc);
+            if (need > 1.0) k = (int)std::min((double)std::max(16, 2 * J), nc);
             k = std::max(1, std::min(k, S.max_cycles - S.cycles));
             // the cycles predicted to be the last two are checked one by one
             tail = (int)std::max(0.0, 2.0 - (nc - k));

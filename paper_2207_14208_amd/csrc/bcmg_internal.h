@@ -39,7 +39,7 @@ constexpr long long kCoarseNodes = 5000;
 // segments take four of them per wavefront (BCMG_PARAM_SWEEP_PAIR_SEGS)
 constexpr int kSweepPairSegs = 1;
 // largest check_interval (cycles per convergence check of bcmg_solve)
-constexpr int kMaxCheckInterval = 8;
+constexpr int kMaxCheckInterval = 16;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than
 // this are stored split by node parity under BCMG_LAYOUT_SPLIT
 constexpr long long kSplitMinNodes = 1 << 17;

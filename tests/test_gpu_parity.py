@@ -516,7 +516,7 @@ def test_solve_parity_cycle_and_smoother_options(name, variant):
 
 
 @pytest.mark.parametrize("name", ["circle65", "flower3d_65", "star_257"])
-@pytest.mark.parametrize("interval", [3, 8])
+@pytest.mark.parametrize("interval", [3, 8, 16])
 def test_solve_with_deferred_checks(name, interval):
     """check_interval > 1: blocks of cycles with one convergence check each
     while the observed rate predicts at least two more cycles.  The cycle
