@@ -21,13 +21,16 @@ def test_host_only_calls():
     assert L.bcmg_version() >= 100
     o = N.default_options()
     assert (o.nu1, o.nu2, o.coarsest_N, o.ext_iters, o.precision) == (2, 1, 4, 4, N.FP64)
+    assert (o.layout, o.cycle, o.smoother, o.check_interval) == (N.LAYOUT_SPLIT, N.CYCLE_V, N.SMOOTH_RB, 1)
     b = C.c_int64()
     N.check(L.bcmg_estimate_bytes(3, 256, N.FP64, C.byref(b)))
     assert b.value > 257 ** 3 * 33
     # argument validation happens on the host before any device call
     h = C.c_void_p()
     for dim, n, kw in [(4, 64, {}), (2, 63, {}), (2, 4, {}), (3, 2048, {}), (2, 64, {"ext_iters": 0}),
-                       (2, 64, {"coarsest_N": 2}), (2, 64, {"max_cycles": 0}), (2, 64, {"precision": 7})]:
+                       (2, 64, {"coarsest_N": 2}), (2, 64, {"max_cycles": 0}), (2, 64, {"precision": 7}),
+                       (2, 64, {"layout": 2}), (2, 64, {"cycle": 2}), (2, 64, {"smoother": 2}),
+                       (2, 64, {"check_interval": 0}), (2, 64, {"check_interval": 17})]:
         o = N.default_options(**kw)
         st = L.bcmg_setup(dim, n, C.c_void_p(16), C.byref(o), None, C.byref(h))
         assert st == N.ERR_INVALID, (dim, n, kw)
