@@ -115,13 +115,14 @@ typedef struct {
 #define BCMG_SMOOTH_RB 0
 #define BCMG_SMOOTH_JACOBI 1
 
-/* Storage order of the finest level's FP32 arrays of a mixed-precision
- * problem (the caller's arrays are always x fastest).  SPLIT (default): when
- * the finest level has more than 131072 nodes, the nodes of even index are
- * stored before those of odd index; with N + 1 odd these are the two colours
- * of the red-black sweep, so each colour pass reads and writes contiguous
- * halves, with 16-byte loads and stores.  NATURAL: x fastest everywhere.  The
- * arithmetic is the same, so both give the same bits. */
+/* Storage order of the FP32 level arrays of a mixed-precision problem (the
+ * caller's arrays are always x fastest).  SPLIT (default): on the finest
+ * level when it has more than 131072 nodes, and on a coarser level with more
+ * than 4194304 nodes, the nodes of even index are stored before those of odd
+ * index; with N + 1 odd these are the two colours of the red-black sweep, so
+ * each colour pass reads and writes contiguous halves, with 16-byte loads and
+ * stores.  NATURAL: x fastest everywhere.  The arithmetic is the same, so
+ * both give the same bits. */
 #define BCMG_LAYOUT_NATURAL 0
 #define BCMG_LAYOUT_SPLIT 1
 

@@ -594,7 +594,8 @@ bcmg_status setup_level(bcmg_problem *P, int l, int *scratch_counts, int *scratc
     }
     // level arrays (cycle precision); the finest FP64 level uses caller memory for u
     const size_t esz = P->fp32 ? 4 : 8;
-    if (l == 0 && P->fp32 && P->opt.layout == BCMG_LAYOUT_SPLIT && V.nn > kSplitMinNodes) V.half = (V.nn + 1) / 2;
+    const long long split_min = l == 0 ? kSplitMinNodes : kSplitMinCoarseNodes;
+    if (P->fp32 && P->opt.layout == BCMG_LAYOUT_SPLIT && V.nn > split_min) V.half = (V.nn + 1) / 2;
     // split arrays end in kSplitPad spare entries (the vector loads of the
     // split sweep may read a few entries past the last node)
     const long long alloc_nn = V.nn + (V.half ? kSplitPad : 0);
@@ -1379,7 +1380,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         // the workgroup cycles natural-order arrays only
         bool split = false;
         for (int s = 0; s < b->cap; s++)
-            if (b->prob[s] && b->prob[s]->L - 1 == a2 && b->prob[s]->lev[0].half) split = true;
+            if (b->prob[s] && b->prob[s]->L - 1 >= a2 && b->prob[s]->lev[b->prob[s]->L - 1 - a2].half) split = true;
         if (split) break;
         Ac = a2;
     }

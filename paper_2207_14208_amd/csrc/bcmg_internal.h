@@ -43,6 +43,11 @@ constexpr int kMaxCheckInterval = 16;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than
 // this are stored split by node parity under BCMG_LAYOUT_SPLIT
 constexpr long long kSplitMinNodes = 1 << 17;
+// the same for a coarser level: its restriction and prolongation reach the
+// coarse values through the split index, which costs about what the vector
+// sweep saves until the level is large (measured: a 257^3 level gains, the
+// 129^3 and 65^3 levels, whose sweeps take a few microseconds, lose)
+constexpr long long kSplitMinCoarseNodes = 1 << 22;
 // spare entries at the end of a split array
 constexpr long long kSplitPad = 16;
 // levels with at most this many nodes keep a colour-sorted list of their

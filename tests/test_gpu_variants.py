@@ -166,17 +166,19 @@ def test_mixed_precision_at_full_size():
     assert em <= 0.02 and abs(em - ed) <= 1e-8, (em, ed)
 
 
-@pytest.mark.parametrize("name", ["flower3d65", "star1025"])
+@pytest.mark.parametrize("name", ["flower3d65", "star1025", "flower3d513"])
 def test_split_layout_same_bits_as_natural(name):
-    """With BCMG_LAYOUT_SPLIT the finest FP32 arrays of a large
-    mixed-precision problem are stored split by node parity: the same
-    arithmetic in another storage order, so the solve gives the same cycle
-    count, history and u bits as with BCMG_LAYOUT_NATURAL, alone and in a
-    batch with a problem too small to be split."""
+    """With BCMG_LAYOUT_SPLIT the FP32 arrays of the large levels of a
+    mixed-precision problem are stored split by node parity (the finest
+    level of all three cases; at 513^3 also the 257^3 level below it): the
+    same arithmetic in another storage order, so the solve gives the same
+    cycle count, history and u bits as with BCMG_LAYOUT_NATURAL, alone and
+    in a batch with a problem too small to be split."""
     _need_gpu()
     from paper_2207_14208_amd import _native as N
     from paper_2207_14208_amd.solver import Batch
-    c = {"flower3d65": lambda: W.flower3d(64), "star1025": lambda: W.star_case(0, 1025, 0.45, 0.08, 5)}[name]()
+    c = {"flower3d65": lambda: W.flower3d(64), "star1025": lambda: W.star_case(0, 1025, 0.45, 0.08, 5),
+         "flower3d513": lambda: W.flower3d(512)}[name]()
     small = W.star_case(1, 65, 0.35, 0.05, 3) if c.d == 2 else W.ellipsoid(32)
     out = []
     for layout in (N.LAYOUT_SPLIT, N.LAYOUT_NATURAL):
