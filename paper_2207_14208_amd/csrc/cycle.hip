@@ -217,6 +217,80 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
     return r2;
 }
 
+// Residual of the INSIDE rows of a segment of an FP64 natural-order field:
+// lane t takes the adjacent nodes q0 = 2t and q0 + 1 and reads them with
+// 16-byte loads (u at x - 1 .. x + 2, the four y and z neighbour pairs, f);
+// the arithmetic is seg_residual's, node by node (the same r).  The caller
+// checks that every load of the segment stays in the array (pair_loads_fit).
+using f64x2u = double __attribute__((ext_vector_type(2), aligned(8)));
+
+template <int D>
+__device__ __forceinline__ bool pair_loads_fit(const Desc &L, const Seg &s) {
+    const long long reach = 1 + (D >= 3 ? L.sz : (D >= 2 ? L.sy : 0));
+    return s.p0 - reach >= 0 && s.p0 + s.len + reach < L.nn;
+}
+
+template <int D, typename Tr>
+__device__ __forceinline__ double seg_residual_pair(const Desc &L, const Seg &s, int lane, bool live, bool store) {
+    const int q0 = 2 * lane;
+    const int nv = min(max(s.len - q0, 0), 2);
+    const long long p = s.p0 + (nv > 0 ? q0 : 0);
+    gcp<double> U = (gcp<double>)L.u;
+    gcp<double> F = (gcp<double>)L.rhs;
+    const f64x2u xl = *(gcp<f64x2u>)(U + p - 1);  // x - 1, x
+    const f64x2u xr = *(gcp<f64x2u>)(U + p + 1);  // x + 1, x + 2
+    const f64x2u f2 = *(gcp<f64x2u>)(F + p);
+    f64x2u ym = {0.0, 0.0}, yp = {0.0, 0.0}, zm = {0.0, 0.0}, zp = {0.0, 0.0};
+    if (D >= 2) {
+        ym = *(gcp<f64x2u>)(U + p - L.sy);
+        yp = *(gcp<f64x2u>)(U + p + L.sy);
+    }
+    if (D >= 3) {
+        zm = *(gcp<f64x2u>)(U + p - L.sz);
+        zp = *(gcp<f64x2u>)(U + p + L.sz);
+    }
+    int cc[2] = {C_INSIDE, C_INSIDE};
+    if (!s.all_inside) {
+        gcp<uint8_t> cls = (gcp<uint8_t>)L.cls;
+        cc[0] = cls[p];
+        cc[1] = cls[p + (nv > 1 ? 1 : 0)];
+    }
+    const double X[4] = {xl.x, xl.y, xr.x, xr.y};
+    const double FP[2] = {f2.x, f2.y}, YM[2] = {ym.x, ym.y}, YP[2] = {yp.x, yp.y};
+    const double ZM[2] = {zm.x, zm.y}, ZP[2] = {zp.x, zp.y};
+    double rv[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const double up = X[h + 1];
+        double sum = X[h + 2] + X[h];
+        if (D >= 2) sum += YP[h] + YM[h];
+        if (D >= 3) sum += ZP[h] + ZM[h];
+        double lap = (2.0 * D * up - sum) / L.h2;
+        if (L.reaction != 0.0) lap += L.reaction * up;  // c u - Laplace u
+        rv[h] = FP[h] - lap;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(rv[h]);
+        pin(cc[h]);
+    }
+    double r2 = 0.0;
+    if (!live) return r2;
+    const NodeArr<Tr> r = node_r<Tr>(L);
+    if (store && sizeof(Tr) == 8 && !r.half && nv == 2 && cc[0] == C_INSIDE && cc[1] == C_INSIDE) {
+        *(gp<f64x2u>)((gp<double>)L.r + p) = f64x2u{rv[0], rv[1]};
+        return rv[0] * rv[0] + rv[1] * rv[1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        if (h < nv && cc[h] == C_INSIDE) {
+            if (store) r[p + h] = (Tr)rv[h];
+            r2 += rv[h] * rv[h];
+        }
+    }
+    return r2;
+}
+
 // Restriction (fine level F, coarse level C; eq. coarseFW, Sec. 3.2 FW,
 // Sec. 3.3).  Coarse INSIDE node: FW over the 3^d fine box around X = 2J if
 // all of it is INSIDE, else the FW weights of its INSIDE nodes renormalised
@@ -760,7 +834,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(const Desc *__restrict__ de
     const int lb = xcd_block_second_first(nseg_blocks);
     if (lb < nseg_blocks) {
         SEG_ITEM_AT(lb)
-        double r2 = seg_residual<D, Tu, Tr>(L, it, lane, live, store != 0);
+        double r2;
+        if constexpr (sizeof(Tu) == 8 && D >= 2) {  // FP64 fields are in the natural order
+            const Seg s = seg_of(it);
+            if (pair_loads_fit<D>(L, s))
+                r2 = seg_residual_pair<D, Tr>(L, s, lane, live, store != 0);
+            else
+                r2 = seg_residual<D, Tu, Tr>(L, it, lane, live, store != 0);
+        } else {
+            r2 = seg_residual<D, Tu, Tr>(L, it, lane, live, store != 0);
+        }
         if (NORM) {
             r2 = wave_sum(r2);
             if (lane == 0) partials[sidx] = r2;
