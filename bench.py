@@ -83,7 +83,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--N", type=int, default=0, help="intervals per axis (default: 512 for flower513, 256 for flower257)")
+    ap.add_argument("--N", type=int, default=0,
+                    help="intervals per axis (default: 512 for flower513, 256 for flower257 and neumann)")
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle V-cycles in the CPU sample (default: 1 at "
@@ -469,7 +470,7 @@ def bench_neumann(args):
     from paper_2207_14208_amd import _native as NAT
     from paper_2207_14208_amd import workloads as W
     from paper_2207_14208_amd.solver import Problem
-    N = args.N
+    N = args.N or 256
     out = {"metric": METRIC,
            "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,
