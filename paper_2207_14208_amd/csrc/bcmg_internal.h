@@ -1,9 +1,10 @@
 // Internal declarations shared by the HIP translation units of libbcmg.
 // Device data layout:
 //   * every level keeps dense node arrays (x fastest): class (uint8), u, rhs, r;
-//     with BCMG_LAYOUT_SPLIT the finest FP32 arrays of a large mixed-precision
-//     problem store the two parities of the node index one after the other
-//     (NodeArr in seg.h);
+//     with BCMG_LAYOUT_SPLIT the FP32 arrays of the large levels of a
+//     mixed-precision problem (kSplitMinNodes, kSplitMinCoarseNodes) store
+//     the two parities of the node index one after the other (NodeArr in
+//     seg.h);
 //   * the work of a launch is a list of items: row segments of <= 128 nodes
 //     (one wavefront each) or chunks of <= 256 ghost / band entries (one
 //     workgroup each); each item names a level descriptor, so one launch can
