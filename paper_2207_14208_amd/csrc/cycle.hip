@@ -576,8 +576,10 @@ __device__ __forceinline__ void prolong_node(const Desc &F, const Desc &C, long 
 // values are loaded once for the pair; each node then sums its corners as
 // prolong_at does (the same terms in the same order).  bvalid: node I0 + 1 is
 // wanted (else x = B + 1 is read only if node I0 needs it: with I0 even on
-// the box face, B + 1 lies beyond the row).
-template <int D, typename PE>
+// the box face, B + 1 lies beyond the row).  PAIRS (an FP64 natural-order
+// coarse array ec, gcp<double>): each coarse row's two values come from one
+// 16-byte load; the caller has checked that x = B + 1 stays in the array.
+template <int D, bool PAIRS = false, typename PE>
 __device__ __forceinline__ void prolong_pair(PE ec, long long csy, long long csz, int I0, int I1, int I2,
                                              bool bvalid, double &ea, double &eb) {
     const int h0 = I0 & 1, h1 = D >= 2 ? (I1 & 1) : 0, h2 = D >= 3 ? (I2 & 1) : 0;
@@ -585,15 +587,27 @@ __device__ __forceinline__ void prolong_pair(PE ec, long long csy, long long csz
     constexpr int M1 = D >= 2 ? 2 : 1, M2 = D >= 3 ? 2 : 1;
     double ev[M2][M1][2];  // coarse values at x = B0, B0 + 1
     const long long b = B0 + B1 * csy + B2 * csz;
+    if constexpr (PAIRS) {
 #pragma unroll
-    for (int m2 = 0; m2 < M2; m2++)
+        for (int m2 = 0; m2 < M2; m2++)
 #pragma unroll
-        for (int m1 = 0; m1 < M1; m1++)
-#pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const bool in = m1 <= h1 && m2 <= h2 && (c == 0 || h0 == 1 || bvalid);
-                ev[m2][m1][c] = (double)ec[in ? b + c + m1 * csy + m2 * csz : b];
+            for (int m1 = 0; m1 < M1; m1++) {
+                const bool in = m1 <= h1 && m2 <= h2;
+                const f64x2u pr = *(gcp<f64x2u>)(ec + (in ? b + m1 * csy + m2 * csz : b));
+                ev[m2][m1][0] = pr.x;
+                ev[m2][m1][1] = pr.y;
             }
+    } else {
+#pragma unroll
+        for (int m2 = 0; m2 < M2; m2++)
+#pragma unroll
+            for (int m1 = 0; m1 < M1; m1++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const bool in = m1 <= h1 && m2 <= h2 && (c == 0 || h0 == 1 || bvalid);
+                    ev[m2][m1][c] = (double)ec[in ? b + c + m1 * csy + m2 * csz : b];
+                }
+    }
     // node a = I0 (corners x = B0 .. B0 + h0); node b = I0 + 1: with I0 even
     // it is odd over B0, B0 + 1, with I0 odd it is even at B0 + 1 alone
     double a = 0.0, e2 = 0.0;
@@ -624,9 +638,52 @@ __device__ __forceinline__ void prolong_pair(PE ec, long long csy, long long csz
     eb = e2;
 }
 
+// FP64 fields (natural order): the pair's fine values, and each coarse
+// row's two values, by 16-byte loads, where every such load of the segment
+// stays in its array.
+template <int D>
+__device__ __forceinline__ void seg_prolong_pairs(const Desc &F, const Desc &C, const Seg &s, int lane, bool live) {
+    const int q0 = 2 * lane;
+    const int qa = q0 < s.len ? q0 : 0;
+    double e[2];
+    prolong_pair<D, true>((gcp<double>)C.u, C.sy, C.sz, s.x0 + qa, s.yj, s.zk, q0 + 1 < s.len, e[0], e[1]);
+    const long long p = s.p0 + qa;
+    gp<double> U = (gp<double>)F.u;
+    const f64x2u u2 = *(gcp<f64x2u>)(U + p);
+    int fc[2] = {C_INSIDE, C_INSIDE};
+    if (!s.all_inside) {
+        fc[0] = ((gcp<uint8_t>)F.cls)[p];
+        fc[1] = ((gcp<uint8_t>)F.cls)[p + (q0 + 1 < s.len ? 1 : 0)];
+    }
+    double v[2] = {u2.x + e[0], u2.y + e[1]};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        pin(v[h]);
+        pin(fc[h]);
+    }
+    if (!live || q0 >= s.len) return;
+    const bool w0 = fc[0] == C_INSIDE || fc[0] == C_GHOST;
+    const bool w1 = q0 + 1 < s.len && (fc[1] == C_INSIDE || fc[1] == C_GHOST);
+    if (w0 && w1) {
+        *(gp<f64x2u>)(U + p) = f64x2u{v[0], v[1]};
+    } else {
+        if (w0) U[p] = v[0];
+        if (w1) U[p + 1] = v[1];
+    }
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void seg_prolong(const Desc &F, const Desc &C, const Item &it, int lane, bool live) {
     const Seg s = seg_of(it);
+    if constexpr (sizeof(T) == 8) {
+        // the last coarse value a pair load may touch, and the fine pair
+        // after the segment's last node
+        const long long cmax = ((s.x0 + s.len) >> 1) + 1 + ((s.yj + 1) >> 1) * C.sy + ((s.zk + 1) >> 1) * C.sz;
+        if (cmax < C.nn && s.p0 + s.len < F.nn) {
+            seg_prolong_pairs<D>(F, C, s, lane, live);
+            return;
+        }
+    }
     // lane takes the adjacent nodes q0 = 2 lane and q0 + 1 (for a split
     // array, one of each parity: both loads stay contiguous per half)
     const int q0 = 2 * lane;
