@@ -301,7 +301,10 @@ __device__ __forceinline__ double seg_residual_pair(const Desc &L, const Seg &s,
 // weights of its INSIDE nodes renormalised (or their plain mean).
 // PLANES: load and accumulate one plane of m2 at a time (the same terms in
 // the same order), a third of the registers for three memory round trips.
-template <int D, bool PLANES = false, typename PR, typename PC>
+// PAIRS (r an FP64 natural-order NodeArr): each fine row's three residuals
+// come from one 16-byte and one 8-byte load; the caller has checked that
+// x - 1 and x + 1 of every row stay in the array.
+template <int D, bool PLANES = false, bool PAIRS = false, typename PR, typename PC>
 __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long long fsy, long long fsz, int X0,
                                                      int X1, int X2, int mode) {
     constexpr int R1 = D >= 2 ? 1 : 0, R2 = D >= 3 ? 1 : 0;
@@ -315,21 +318,44 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
         uint8_t fc[NL][2 * R1 + 1][3];
         double rv[NL][2 * R1 + 1][3];
         bool inb[NL][2 * R1 + 1][3];
+        if constexpr (PAIRS) {
 #pragma unroll
-        for (int i2 = 0; i2 < NL; i2++)
+            for (int i2 = 0; i2 < NL; i2++)
 #pragma unroll
-            for (int m1 = -R1; m1 <= R1; m1++)
-#pragma unroll
-                for (int m0 = -1; m0 <= 1; m0++) {
+                for (int m1 = -R1; m1 <= R1; m1++) {
                     const int m2 = g + i2 - R2;
-                    const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
-                    const bool in = J0 >= 0 && J0 <= FN && (D < 2 || (J1 >= 0 && J1 <= FN)) &&
-                                    (D < 3 || (J2 >= 0 && J2 <= FN));
-                    const long long q = in ? pf + m0 + m1 * fsy + m2 * fsz : pf;
-                    inb[i2][m1 + R1][m0 + 1] = in;
-                    fc[i2][m1 + R1][m0 + 1] = fcls[q];
-                    rv[i2][m1 + R1][m0 + 1] = (double)r[q];
+                    const int J1 = X1 + m1, J2 = X2 + m2;
+                    const bool rin = (D < 2 || (J1 >= 0 && J1 <= FN)) && (D < 3 || (J2 >= 0 && J2 <= FN));
+                    const long long qc = rin ? pf + m1 * fsy + m2 * fsz : pf;
+                    const f64x2u lo = *(gcp<f64x2u>)(r.a + qc - 1);  // x - 1, x
+                    const double hi = r.a[qc + 1];
+                    const double v3[3] = {lo.x, lo.y, hi};
+#pragma unroll
+                    for (int m0 = -1; m0 <= 1; m0++) {
+                        const int J0 = X0 + m0;
+                        const bool in = rin && J0 >= 0 && J0 <= FN;
+                        inb[i2][m1 + R1][m0 + 1] = in;
+                        fc[i2][m1 + R1][m0 + 1] = fcls[in ? qc + m0 : pf];
+                        rv[i2][m1 + R1][m0 + 1] = v3[m0 + 1];  // read only where in
+                    }
                 }
+        } else {
+#pragma unroll
+            for (int i2 = 0; i2 < NL; i2++)
+#pragma unroll
+                for (int m1 = -R1; m1 <= R1; m1++)
+#pragma unroll
+                    for (int m0 = -1; m0 <= 1; m0++) {
+                        const int m2 = g + i2 - R2;
+                        const int J0 = X0 + m0, J1 = X1 + m1, J2 = X2 + m2;
+                        const bool in = J0 >= 0 && J0 <= FN && (D < 2 || (J1 >= 0 && J1 <= FN)) &&
+                                        (D < 3 || (J2 >= 0 && J2 <= FN));
+                        const long long q = in ? pf + m0 + m1 * fsy + m2 * fsz : pf;
+                        inb[i2][m1 + R1][m0 + 1] = in;
+                        fc[i2][m1 + R1][m0 + 1] = fcls[q];
+                        rv[i2][m1 + R1][m0 + 1] = (double)r[q];
+                    }
+        }
 #pragma unroll
         for (int i2 = 0; i2 < NL; i2++)
 #pragma unroll
@@ -372,11 +398,18 @@ __device__ __forceinline__ double restrict_inside_at(PR r, PC fcls, int FN, long
 // pre-smoothing: from the zero initial guess every neighbour of an INSIDE
 // node is zero, so the update of a red node (i+j+k even) is h^2 f / (2d),
 // computed as the sweep computes it (a zero neighbour sum added).
+// pairs: FP64 fields, whose rows the segment's pair loads keep inside the
+// fine array (restrict_pairs_fit).
 template <int D, typename T>
 __device__ __forceinline__ void restrict_node(const Desc &C, const Desc &F, long long pc, int X0, int X1, int X2,
-                                              bool red, T &fv, T &uv, int &cc) {
-    const double out = restrict_inside_at<D, true>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1,
-                                                   X2, C.restrict_mode);
+                                              bool red, T &fv, T &uv, int &cc, bool pairs = false) {
+    double out;
+    if (sizeof(T) == 8 && pairs)
+        out = restrict_inside_at<D, true, sizeof(T) == 8>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz,
+                                                          X0, X1, X2, C.restrict_mode);
+    else
+        out = restrict_inside_at<D, true>(node_r<const T>(F), (gcp<uint8_t>)F.cls, F.N, F.sy, F.sz, X0, X1, X2,
+                                          C.restrict_mode);
     cc = ((gcp<uint8_t>)C.cls)[pc];
     fv = (T)out;
     uv = (T)0;
@@ -465,6 +498,15 @@ __device__ __forceinline__ void restrict_ghost(const Desc &C, const Desc &F, int
 
 // The restriction of coarse node q of a segment (one node per lane: its 3^d
 // box of fine residuals and classes is 54 loads, all in flight at once).
+// The fine rows of a coarse segment's restriction boxes stay inside the
+// fine array with one node to spare at either end (their pair loads).
+template <int D>
+__device__ __forceinline__ bool restrict_pairs_fit(const Desc &F, const Seg &s) {
+    const long long rows = (D >= 2 ? F.sy : 0) + (D >= 3 ? F.sz : 0);
+    const long long pf0 = 2LL * s.x0 + 2LL * s.yj * F.sy + 2LL * s.zk * F.sz;
+    return pf0 - 1 - rows >= 0 && pf0 + 2LL * (s.len - 1) + 1 + rows < F.nn;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void seg_restrict_one(const Desc &C, const Desc &F, const Item &it, int q, bool live,
                                                  bool red) {
@@ -472,7 +514,8 @@ __device__ __forceinline__ void seg_restrict_one(const Desc &C, const Desc &F, c
     const int qq = q < s.len ? q : 0;
     T fv, uv;
     int cc;
-    restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, red, fv, uv, cc);
+    const bool pairs = sizeof(T) == 8 && restrict_pairs_fit<D>(F, s);
+    restrict_node<D, T>(C, F, s.p0 + qq, 2 * (s.x0 + qq), 2 * s.yj, 2 * s.zk, red, fv, uv, cc, pairs);
     pin(fv);
     pin(uv);
     pin(cc);
