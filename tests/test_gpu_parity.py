@@ -47,6 +47,11 @@ CASES = {
     "spheres_65": lambda: spheres_case(64),
     "line1d_129": lambda: W.make_case("line1d", 1, 128, W.phi_halfspace(0.3137), W.Manufactured(
         u=lambda x: np.exp(x), f=lambda x: -np.exp(x))),
+    # y > -1 + h/2: the whole face y = -1 is ghosts, so row segments start at
+    # the array's first rows and the FP64 pair loads take their bounds-checked
+    # fallback there
+    "face3d_65": lambda: W.make_case("face3d", 3, 64, lambda x, y, z: (-1.0 + 0.5 * 2.0 / 64) - y, W.exp_sum(3)),
+    "face2d_129": lambda: W.make_case("face2d", 2, 128, lambda x, y: (-1.0 + 0.5 * 2.0 / 128) - y, W.sincos_xy()),
 }
 
 
