@@ -217,19 +217,23 @@ __device__ __forceinline__ double seg_residual(const Desc &L, const Item &it, in
     return r2;
 }
 
-// Residual of the INSIDE rows of a segment of an FP64 natural-order field:
-// lane t takes the adjacent nodes q0 = 2t and q0 + 1 and reads them with
-// 16-byte loads (u at x - 1 .. x + 2, the four y and z neighbour pairs, f);
-// the arithmetic is seg_residual's, node by node (the same r).  The caller
-// checks that every load of the segment stays in the array (pair_loads_fit).
+// Two adjacent FP64 values by one 16-byte load or store (8-byte aligned).
 using f64x2u = double __attribute__((ext_vector_type(2), aligned(8)));
 
+// Every pair load of seg_residual_pair over segment s (one node before the
+// segment to one after it, in its row and the y and z neighbour rows) stays
+// in the level's arrays.
 template <int D>
 __device__ __forceinline__ bool pair_loads_fit(const Desc &L, const Seg &s) {
     const long long reach = 1 + (D >= 3 ? L.sz : (D >= 2 ? L.sy : 0));
     return s.p0 - reach >= 0 && s.p0 + s.len + reach < L.nn;
 }
 
+// Residual of the INSIDE rows of a segment of an FP64 natural-order field:
+// lane t takes the adjacent nodes q0 = 2t and q0 + 1 and reads them with
+// 16-byte loads (u at x - 1 .. x + 2, the four y and z neighbour pairs, f);
+// the arithmetic is seg_residual's, node by node (the same r).  The caller
+// has checked pair_loads_fit.
 template <int D, typename Tr>
 __device__ __forceinline__ double seg_residual_pair(const Desc &L, const Seg &s, int lane, bool live, bool store) {
     const int q0 = 2 * lane;
