@@ -360,6 +360,9 @@ def bench(args) -> dict:
         "throughput_req_per_s": len(meas) / span,
         "throughput_unknowns_per_s": sum(r.unknowns for r in ok) / span,
         "converged": len(ok), "failed": len(meas) - len(ok), "rejected": len(st.rejected),
+        # the failed requests by id (their draws follow from the seed and the id)
+        "failed_requests": [{"rid": r.rid, "side": r.params["side"], "spheres": r.params["m"], "status": r.status,
+                             "cycles": r.cycles, "attempts": r.attempts} for r in meas if r.status != 0],
         "retried_with_const_dtau": sum(1 for r in meas if r.attempts > 1),
         "peak_slots": st.peak_slots, "peak_bytes": st.peak_bytes,
         "peak_torch_allocated_bytes": int(be.torch.cuda.max_memory_allocated()),
