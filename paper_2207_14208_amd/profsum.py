@@ -1,7 +1,9 @@
 """Summaries of rocprofv3 output (CSV or rocpd SQLite) for the solver's kernels.
 
-    python -m paper_2207_14208_amd.profsum trace <dir> [--top K]
-        per (kernel, grid) call count, average and share of the kernel time
+    python -m paper_2207_14208_amd.profsum trace <dir> [--top K] [--last NAME GRID COUNT]
+        per (kernel, grid) call count, average and share of the kernel time;
+        --last adds the average of the last COUNT dispatches of one kernel at
+        one grid (a timed burst at the end of the run)
     python -m paper_2207_14208_amd.profsum traffic <fetch_dir> <write_dir> --kernel NAME --grid G --copy-bytes B
         FETCH_SIZE / WRITE_SIZE per dispatch of one kernel, scaled by what the
         same counters read for the plain copy kernel of B bytes
@@ -62,6 +64,24 @@ def kernel_rows(d: str):
         con = sqlite3.connect(db)
         for name, gx, dur in con.execute("select name, grid_x, duration from kernels"):
             yield _short(name), int(gx), int(dur)
+
+
+def last_dispatches_us(d: str, kernel: str, grid: int, count: int) -> tuple[float, int]:
+    """Average duration (us) of the last `count` dispatches, by start time,
+    of one kernel at one grid size in a CSV kernel trace, and how many were
+    averaged."""
+    found = []
+    for path in _find(d, "*kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if _short(r["Kernel_Name"]) != kernel or int(_col(r, "Grid_Size_X", "Grid_Size", default=0)) != grid:
+                    continue
+                t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                found.append((t0, t1 - t0))
+    if not found:
+        raise SystemExit(f"no dispatches of {kernel} at grid {grid} in {d}")
+    tail = [dur for _, dur in sorted(found)[-count:]]
+    return sum(tail) / len(tail) / 1e3, len(tail)
 
 
 def trace_table(d: str, top: int = 30) -> tuple[list, float]:
@@ -159,6 +179,7 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("dir")
     t.add_argument("--top", type=int, default=30)
+    t.add_argument("--last", nargs=3, metavar=("NAME", "GRID", "COUNT"))
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -179,6 +200,9 @@ def main():
         print("| kernel | grid | calls | avg us | share |\n|---|---:|---:|---:|---:|")
         for k, g, n, avg, share in rows:
             print(f"| {k} | {g} | {n} | {avg:.2f} | {share:.1f}% |")
+        if a.last:
+            avg, n = last_dispatches_us(a.dir, a.last[0], int(a.last[1]), int(a.last[2]))
+            print(f"\nlast {n} dispatches of {a.last[0]} at grid {a.last[1]}: {avg:.2f} us on average")
     else:
         print(json.dumps(traffic(a.fetch_dir, a.write_dir, a.kernel, a.grid, a.copy_bytes), indent=1))
 

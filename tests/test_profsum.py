@@ -104,3 +104,20 @@ def test_marker_ranges_group_and_count_kernel_time_inside(tmp_path):
     assert rows["bcmg_solve"] == (1, 7.0, 1.5)
     n, host, kern = rows["cycles a..b (one host check)"]
     assert n == 2 and abs(host - 6.8) < 1e-12 and abs(kern - 1.5) < 1e-12
+
+
+def test_last_dispatches_average_the_final_burst(tmp_path):
+    # dispatches out of order in the file: the last two by start time are
+    # the 5 us and 7 us ones; another grid and another kernel are ignored
+    hdr = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"]
+    _write(tmp_path / "t_kernel_trace.csv", hdr, [
+        ["void k_a<3>(int)", 1024, 300, 7300],
+        ["void k_a<3>(int)", 1024, 0, 20000],
+        ["void k_a<3>(int)", 1024, 200, 5200],
+        ["void k_a<3>(int)", 512, 900, 9900],
+        ["void k_b(int)", 1024, 1000, 90000],
+    ])
+    avg, n = profsum.last_dispatches_us(str(tmp_path), "k_a<3>", 1024, 2)
+    assert n == 2 and avg == pytest.approx(6.0)
+    avg, n = profsum.last_dispatches_us(str(tmp_path), "k_a<3>", 1024, 10)
+    assert n == 3 and avg == pytest.approx((20.0 + 5.0 + 7.0) / 3)
