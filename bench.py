@@ -78,13 +78,23 @@ def stored_traffic(N: int, precision: str):
     return rec["bytes_per_launch"]
 
 
+# intervals per axis of the workloads that take --N, when it is not given
+DEFAULT_N = {"flower513": 512, "flower257": 256, "probe513": 512, "cycle_options": 256, "neumann": 256}
+
+
+def intervals(args) -> int:
+    """--N, or the workload's default intervals per axis."""
+    return args.N or DEFAULT_N[args.workload]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=0,
-                    help="intervals per axis (default: 512 for flower513, 256 for flower257 and neumann)")
+                    help="intervals per axis (default: 512 for flower513 and probe513, 256 for flower257, "
+                         "cycle_options and neumann)")
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle V-cycles in the CPU sample (default: 1 at "
@@ -179,7 +189,7 @@ def bench_cycle_options(args):
     from paper_2207_14208_amd.solver import Problem
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
-    N = args.N or 256
+    N = intervals(args)
     case = W.flower3d(N)
     phi = torch.from_numpy(case.phi).cuda()
     f = torch.from_numpy(case.f).cuda()
@@ -234,7 +244,7 @@ def bench_probe(args):
     from paper_2207_14208_amd.solver import Problem
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
-    N = args.N or 512
+    N = intervals(args)
     phi = -torch.ones((N + 1) ** 3, dtype=torch.float64, device="cuda")
     reps = 100
     res = {}
@@ -283,7 +293,7 @@ def bench_flower(args):
     torch.cuda.set_device(0)
     dev = "cuda"
     big = args.workload == "flower513"
-    N = args.N or (512 if big else 256)
+    N = intervals(args)
     names = ["fp64", "mixed"] if big else [args.precision]
     head = names[-1]
     prec_of = {"fp64": NAT.FP64, "mixed": NAT.MIXED}
@@ -470,7 +480,7 @@ def bench_neumann(args):
     from paper_2207_14208_amd import _native as NAT
     from paper_2207_14208_amd import workloads as W
     from paper_2207_14208_amd.solver import Problem
-    N = args.N or 256
+    N = intervals(args)
     out = {"metric": METRIC,
            "unit": "unknowns/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "data": "synthetic (analytic level set and manufactured solution)", "steps": args.steps,

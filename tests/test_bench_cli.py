@@ -30,3 +30,15 @@ def test_rho_last_skips_unchecked_cycles():
     assert abs(bench.rho_last(h) - 0.5) < 1e-15
     assert abs(bench.rho_last(np.array([1.0, 0.5, 0.2])) - 0.4) < 1e-15
     assert bench.rho_last(np.array([1.0, 0.5])) is None
+
+
+def test_workloads_that_take_N_have_a_default():
+    # every workload that reads --N has its own default (a missing one once
+    # made --workload neumann divide by zero), and --N overrides it
+    import argparse
+    sys.path.insert(0, ROOT)
+    import bench
+    for w, n in (("flower513", 512), ("flower257", 256), ("probe513", 512), ("cycle_options", 256),
+                 ("neumann", 256)):
+        assert bench.intervals(argparse.Namespace(N=0, workload=w)) == n
+        assert bench.intervals(argparse.Namespace(N=64, workload=w)) == 64
