@@ -165,6 +165,12 @@ struct bcmg_batch {
     int ncoarse = 0;
     double *d_partials = nullptr;
     size_t partials_cap = 0;
+    // norm of the finest residual by norm_blocks workgroups per slot (block
+    // sums and per-slot arrival counters, zero between launches)
+    int norm_blocks = 1;
+    double *d_norm_blk = nullptr;
+    int *d_norm_cnt = nullptr;
+    size_t norm_cap = 0;
     int A = 0;
     std::vector<Lists> lv;
     Item *fsegs = nullptr, *fgch = nullptr;
@@ -1201,6 +1207,8 @@ bcmg_status bcmg_batch_destroy(bcmg_batch *b) {
     bfree(b, b->d_lprogs);
     bfree(b, b->d_limage);
     bfree(b, b->d_partials);
+    bfree(b, b->d_norm_blk);
+    bfree(b, b->d_norm_cnt);
     if (b->join) hipEventDestroy(b->join);
     if (b->stream) hipStreamDestroy(b->stream);
     delete b;
@@ -1493,6 +1501,25 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
         b->partials_cap = std::max(np, 2 * b->partials_cap);
         HIPCHK(balloc(b, (void **)&b->d_partials, sizeof(double) * b->partials_cap));
     }
+    {
+        // one workgroup per slot sums up to kNormBlockEntries partials; a
+        // slot with more gets more workgroups (all slots the same number)
+        int most = 0;
+        for (const NormRange &R : ranges) most = std::max(most, (R.seg_end - R.seg_beg) + (R.gch_end - R.gch_beg));
+        b->norm_blocks = std::min(kNormBlocksMax, std::max(1, most / kNormBlockEntries));
+        const size_t need = (size_t)b->cap * (size_t)b->norm_blocks;
+        if (b->norm_blocks > 1 && need > b->norm_cap) {
+            bfree(b, b->d_norm_blk);
+            bfree(b, b->d_norm_cnt);
+            b->d_norm_blk = nullptr;
+            b->d_norm_cnt = nullptr;
+            b->norm_cap = 0;
+            HIPCHK(balloc(b, (void **)&b->d_norm_blk, sizeof(double) * need));
+            HIPCHK(balloc(b, (void **)&b->d_norm_cnt, sizeof(int) * (size_t)b->cap));
+            HIPCHK(hipMemsetAsync(b->d_norm_cnt, 0, sizeof(int) * (size_t)b->cap, b->stream));
+            b->norm_cap = need;
+        }
+    }
     hipStream_t cs = b->stream;
     if (!descs.empty())
         HIPCHK(hipMemcpyAsync(b->d_desc, descs.data(), sizeof(Desc) * descs.size(), hipMemcpyHostToDevice, cs));
@@ -1663,7 +1690,7 @@ static void launch_outer_residual(bcmg_batch *b, int mode, int ncyc = 1) {
     launch_residual(b->d, 0, b->fp32, 1, b->d_outer, b->fsegs, b->nfseg, b->fgch, b->nfgch, b->d_state, b->d_partials,
                     b->stream, b->neu, b->fp32 ? 1 : 0);
     launch_norm_finish(b->d_ranges, b->cap, b->d_partials, b->nfseg, b->d_state, b->d_rtol2, b->d_hist,
-                       b->hist_stride, mode, nullptr, b->stream, ncyc);
+                       b->hist_stride, mode, nullptr, b->stream, ncyc, b->norm_blocks, b->d_norm_blk, b->d_norm_cnt);
 }
 
 // one multigrid cycle of the batch's shape on the correction equations

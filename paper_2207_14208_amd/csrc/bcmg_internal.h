@@ -39,6 +39,10 @@ constexpr long long kCoarseNodes = 5000;
 // FP32 red-black launches over split levels with at least this many row
 // segments take four of them per wavefront (BCMG_PARAM_SWEEP_PAIR_SEGS)
 constexpr int kSweepPairSegs = 1;
+// the finest residual's norm: partials per workgroup, and at most this many
+// workgroups per slot
+constexpr int kNormBlockEntries = 4096;
+constexpr int kNormBlocksMax = 32;
 // largest check_interval (cycles per convergence check of bcmg_solve)
 constexpr int kMaxCheckInterval = 16;
 // the finest FP32 arrays of a mixed-precision problem with more nodes than

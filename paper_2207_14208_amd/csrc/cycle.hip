@@ -1184,32 +1184,27 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const Desc *__restrict__ desc
 // not followed by a check; their history entries are NaN); mode 2: only store
 // the norm.
 constexpr int kNormThreads = 1024;
-__global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
-                                                              const double *__restrict__ partials, int nseg_total,
-                                                              SlotState *__restrict__ st,
-                                                              const double *__restrict__ rtol2,
-                                                              double *__restrict__ hist, int hist_stride, int mode,
-                                                              int ncyc, double *__restrict__ out) {
-    const int s = blockIdx.x;
-    if (s >= nslots) return;
-    if (mode == 1 && st[s].active != 1) return;
-    if (mode == 0 && st[s].active != 2) return;
-    const NormRange R = ranges[s];
-    const int nA = R.seg_end - R.seg_beg, nB = R.gch_end - R.gch_beg, n = nA + nB;
+
+// the workgroup's fixed-order sum of entries [lo, hi) of a slot's partials
+// (segment partials first, then its ghost-chunk partials); every thread
+// takes part, thread 0 gets the sum
+__device__ __forceinline__ double norm_range_sum(const NormRange &R, const double *__restrict__ partials,
+                                                 int nseg_total, int lo, int hi) {
+    const int nA = R.seg_end - R.seg_beg;
     // a thread's entries are loaded eight at a time and added in order; the
     // tree pairs t with t + w, through LDS while w spans wavefronts and by
     // shuffles within the first wavefront after that (the same pairs)
     double acc = 0.0;
-    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kNormThreads) {
+    for (int i0 = lo + (int)threadIdx.x; i0 < hi; i0 += 8 * kNormThreads) {
         double v[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            const int i = min(i0 + k * kNormThreads, n - 1);
+            const int i = min(i0 + k * kNormThreads, hi - 1);
             v[k] = i < nA ? partials[R.seg_beg + i] : partials[nseg_total + R.gch_beg + (i - nA)];
         }
 #pragma unroll
         for (int k = 0; k < 8; k++)
-            if (i0 + k * kNormThreads < n) acc += v[k];
+            if (i0 + k * kNormThreads < hi) acc += v[k];
     }
     __shared__ double red[kNormThreads];
     red[threadIdx.x] = acc;
@@ -1218,13 +1213,18 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x >= 64) return;
-    double t = red[threadIdx.x];
-    for (int w = 32; w > 0; w >>= 1) t += __shfl_down(t, w);
-    if (threadIdx.x != 0) return;
-    const double tot = t;
+    double t = 0.0;
+    if (threadIdx.x < 64) {
+        t = red[threadIdx.x];
+        for (int w = 32; w > 0; w >>= 1) t += __shfl_down(t, w);
+    }
+    return t;
+}
+
+// the slot's bookkeeping once its squared norm tot is known (one thread)
+__device__ void norm_update(SlotState &S, int s, double tot, const double *__restrict__ rtol2,
+                            double *__restrict__ hist, int hist_stride, int mode, int ncyc, double *__restrict__ out) {
     if (out) out[s] = tot;
-    SlotState &S = st[s];
     if (mode == 0) {
         // a non-finite initial residual (a NaN or Inf in f, g(Q) or u0) ends
         // the solve before any cycle, as a divergence
@@ -1262,6 +1262,51 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *_
     } else {
         S.lastsq = tot;
     }
+}
+
+__global__ __launch_bounds__(kNormThreads) void k_norm_finish(const NormRange *__restrict__ ranges, int nslots,
+                                                              const double *__restrict__ partials, int nseg_total,
+                                                              SlotState *__restrict__ st,
+                                                              const double *__restrict__ rtol2,
+                                                              double *__restrict__ hist, int hist_stride, int mode,
+                                                              int ncyc, double *__restrict__ out) {
+    const int s = blockIdx.x;
+    if (s >= nslots) return;
+    if (mode == 1 && st[s].active != 1) return;
+    if (mode == 0 && st[s].active != 2) return;
+    const NormRange R = ranges[s];
+    const int n = (R.seg_end - R.seg_beg) + (R.gch_end - R.gch_beg);
+    const double tot = norm_range_sum(R, partials, nseg_total, 0, n);
+    if (threadIdx.x != 0) return;
+    norm_update(st[s], s, tot, rtol2, hist, hist_stride, mode, ncyc, out);
+}
+
+// The same for slots with many partials, by nblk workgroups per slot: block
+// b sums its fixed share of the entries, in the order above, into
+// blk[s nblk + b]; the last block of the slot to finish (counted in cnt[s],
+// which it resets) adds the nblk sums in index order and does the
+// bookkeeping.  The result depends on nblk only, not on the blocks' timing.
+__global__ __launch_bounds__(kNormThreads) void k_norm_finish_split(
+    const NormRange *__restrict__ ranges, int nslots, int nblk, const double *__restrict__ partials, int nseg_total,
+    double *__restrict__ blk, int *__restrict__ cnt, SlotState *__restrict__ st, const double *__restrict__ rtol2,
+    double *__restrict__ hist, int hist_stride, int mode, int ncyc, double *__restrict__ out) {
+    const int s = blockIdx.x / nblk, b = blockIdx.x % nblk;
+    if (s >= nslots) return;
+    if (mode == 1 && st[s].active != 1) return;
+    if (mode == 0 && st[s].active != 2) return;
+    const NormRange R = ranges[s];
+    const int n = (R.seg_end - R.seg_beg) + (R.gch_end - R.gch_beg);
+    const int lo = (int)((long long)n * b / nblk), hi = (int)((long long)n * (b + 1) / nblk);
+    const double part = norm_range_sum(R, partials, nseg_total, lo, hi);
+    if (threadIdx.x != 0) return;
+    blk[(long long)s * nblk + b] = part;
+    __threadfence();
+    if (atomicAdd(&cnt[s], 1) != nblk - 1) return;
+    __threadfence();
+    double tot = 0.0;
+    for (int k = 0; k < nblk; k++) tot += blk[(long long)s * nblk + k];
+    cnt[s] = 0;
+    norm_update(st[s], s, tot, rtol2, hist, hist_stride, mode, ncyc, out);
 }
 
 // Extension of u into the band chunks (ghost values read from u).
@@ -1898,8 +1943,13 @@ void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, con
 
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s,
-                        int ncyc) {
+                        int ncyc, int nblk, double *blk, int *cnt) {
     if (nslots <= 0) return;
+    if (nblk > 1 && blk && cnt) {
+        hipLaunchKernelGGL(k_norm_finish_split, dim3(nslots * nblk), dim3(kNormThreads), 0, s, ranges, nslots, nblk,
+                           partials, nseg_total, blk, cnt, st, rtol2, hist, hist_stride, mode, ncyc, out);
+        return;
+    }
     hipLaunchKernelGGL(k_norm_finish, dim3(nslots), dim3(kNormThreads), 0, s, ranges, nslots, partials, nseg_total,
                        st, rtol2, hist, hist_stride, mode, ncyc, out);
 }

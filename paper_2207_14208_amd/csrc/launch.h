@@ -28,9 +28,11 @@ void launch_residual(int d, int tu32, int tr32, int norm, const Desc *descs, con
                      const Item *gch, int ngch, const SlotState *st, double *partials, hipStream_t s, int neu = 0,
                      int store = 1, int split = 0);
 // mode 1: the check after ncyc cycles (ncyc - 1 of them unchecked)
+// nblk > 1 (with blk: nslots * nblk doubles, cnt: nslots ints, zero): nblk
+// workgroups per slot
 void launch_norm_finish(const NormRange *ranges, int nslots, const double *partials, int nseg_total, SlotState *st,
                         const double *rtol2, double *hist, int hist_stride, int mode, double *out, hipStream_t s,
-                        int ncyc = 1);
+                        int ncyc = 1, int nblk = 1, double *blk = nullptr, int *cnt = nullptr);
 // extension of u into the band chunks bch (ghost values read from u)
 // via_need: the chunks run over the needed band entries (bneed) instead of all of them
 void launch_ext_gather(int fp32, const Desc *descs, const Item *bch, int nbch, int via_need, const SlotState *st,
