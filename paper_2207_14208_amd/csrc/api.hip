@@ -163,6 +163,7 @@ struct bcmg_batch {
     size_t items_cap = 0;
     int *d_coarse = nullptr;
     int ncoarse = 0;
+    std::vector<int> desc_base;  // per slot: index of its finest level's descriptor in d_desc (-1: empty)
     double *d_partials = nullptr;
     size_t partials_cap = 0;
     // norm of the finest residual by norm_blocks workgroups per slot (block
@@ -1528,6 +1529,7 @@ static bcmg_status batch_rebuild(bcmg_batch *b) {
     if (!coarse.empty())
         HIPCHK(hipMemcpyAsync(b->d_coarse, coarse.data(), sizeof(int) * coarse.size(), hipMemcpyHostToDevice, cs));
     HIPCHK(hipMemcpyAsync(b->d_outer, outer.data(), sizeof(Desc) * b->cap, hipMemcpyHostToDevice, cs));
+    b->desc_base = base;
     HIPCHK(hipMemcpyAsync(b->d_eptr, eptr.data(), sizeof(float *) * b->cap, hipMemcpyHostToDevice, cs));
     HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), sizeof(NormRange) * b->cap, hipMemcpyHostToDevice, cs));
     if (!progs.empty())
@@ -1966,6 +1968,24 @@ bcmg_status bcmg_batch_stats(bcmg_batch *b, int32_t slot, bcmg_solve_stats *stat
 }
 
 // ------------------------------------------------------------ single solve
+// Slot s solves into another caller array u: only the descriptors that name
+// the caller's u change (the outer one, and an FP64 problem's finest level);
+// the kernels read descriptors from device memory, so the work lists and
+// captured graphs stay valid.  Queued work is ordered before the copies.
+static bcmg_status batch_set_u(bcmg_batch *b, int s, double *u) {
+    bcmg_problem *P = b->prob[s];
+    b->u[s] = u;
+    if (b->dirty) return BCMG_OK;  // the next rebuild takes b->u
+    const Desc o = make_desc(P, 0, u, P->rhs64, P->fp32 ? P->lev[0].rhs : (void *)P->r64, s);
+    HIPCHK(hipMemcpyAsync(b->d_outer + s, &o, sizeof o, hipMemcpyHostToDevice, b->stream));
+    if (!P->fp32) {
+        const Desc d0 = make_desc(P, 0, u, P->lev[0].rhs, P->lev[0].r, s);
+        HIPCHK(hipMemcpyAsync(b->d_desc + b->desc_base[s], &d0, sizeof d0, hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return BCMG_OK;
+}
+
 static bcmg_status solo_attach(bcmg_problem *P, double *u, double rtol) {
     bcmg_status st;
     if (!P->solo) {
@@ -1973,7 +1993,8 @@ static bcmg_status solo_attach(bcmg_problem *P, double *u, double rtol) {
     }
     bcmg_batch *b = P->solo;
     if ((st = batch_join(b))) return st;
-    if (b->prob[0] == P && b->u[0] == u) {
+    if (b->prob[0] == P) {
+        if (b->u[0] != u && (st = batch_set_u(b, 0, u))) return st;
         b->rtol[0] = rtol;
         if (P->fp32) HIPCHK(hipMemsetAsync(P->lev[0].u, 0, P->lev[0].nn * 4, b->stream));
         return batch_init_slot(b, 0, rtol);
