@@ -282,7 +282,9 @@ bcmg_status bcmg_residual_norm_noalloc(bcmg_problem *prob, const double *u_dev, 
  * In BCMG_MIXED mode each cycle is an FP64 residual, an FP32 V-cycle on the
  * correction with an FP64 coarse solve, and an FP64 update (iterative
  * refinement).  hist_host (max_cycles+1 doubles, may be NULL) receives
- * ||r^m|| for m = 0..cycles.  Returns the solve status.
+ * ||r^m|| for m = 0..cycles.  Returns the solve status.  The problem keeps
+ * its work lists and captured cycles between calls, also when u_dev is
+ * another array than the last call's.
  *
  * Convergence checks.  A check is the residual norm over the finest level
  * (in BCMG_MIXED mode also the update and the FP32 right-hand side of the

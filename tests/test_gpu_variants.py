@@ -325,3 +325,35 @@ def test_split_sweep_with_ghosts_on_a_box_face(d, N):
     u0 = np.where(cls == oracle.BOXDIR, c.gB, 0.0)
     r0 = O.norm(0, O.residual(0, u0))
     assert O.norm(0, O.residual(0, u1)) <= 1e-10 * r0 * 1.001
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_solve_into_another_array_same_as_fresh_problem(mixed):
+    """A second solve of the same problem into another caller array (the
+    descriptors that name u are rewritten in place, the work lists and graphs
+    kept) gives the bits of a fresh problem solving into that array, and
+    leaves the first array as its own solve left it."""
+    _need_gpu()
+    from paper_2207_14208_amd import _native as N
+    c = W.flower3d(64)
+    prec = N.MIXED if mixed else N.FP64
+    G = gpu_problem(c, precision=prec, check_interval=4)
+    gB = torch.from_numpy(c.gB).cuda()
+    u1 = G.initial_guess(gB)
+    st1, h1 = G.solve(u1, 1e-10)
+    first = u1.clone()
+    u2 = G.initial_guess(gB)
+    st2, h2 = G.solve(u2, 1e-10)
+    assert torch.equal(u1, first)
+    F = gpu_problem(c, precision=prec, check_interval=4)
+    u3 = F.initial_guess(gB)
+    st3, h3 = F.solve(u3, 1e-10)
+    assert st2.status == 0 and st2.cycles == st3.cycles
+    assert np.array_equal(h2, h3, equal_nan=True)
+    assert torch.equal(u2, u3)
+    # and back into the first array: the same result again
+    u1.copy_(G.initial_guess(gB))
+    st4, _ = G.solve(u1, 1e-10)
+    assert st4.cycles == st3.cycles and torch.equal(u1, u3)
+    G.close()
+    F.close()
